@@ -1,0 +1,431 @@
+"""FP64 CPU oracle for pROST's per-frame alternating minimisation.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or
+executes this module; only the tests, the smoke check and the CPU-baseline
+leg of the benchmark do.  It shares no code with the HIP library.
+
+Paper: Seidel, Hage, Kleinsteuber, "pROST: A Smoothed lp-norm Robust Online
+Subspace Tracking Method for Realtime Background Subtraction in Video"
+(arXiv:1302.2073).  Every function below cites the passage it follows.
+
+Conventions
+-----------
+* A frame x is a vector of m = C*P entries stored plane by plane
+  (all P pixels of channel 0, then channel 1, ...), each plane row-major
+  over an H x W image, as in Sec. 3.4 "Color images" (x = [x_R; x_G; x_B]).
+  Pixel index p = row*W + col; entry index e = c*P + p.
+* U is m x k with orthonormal columns (Sec. 2.1, eq. stiefeldef), y in R^k.
+* All arithmetic is float64, sums are numpy's (pairwise) sums.  There is no
+  blocking, fusion or reordering beyond the definitions.
+
+Readings of points the paper leaves open are marked READING and listed in
+the design notes of the repository.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+COST_LP = "lp"    # eq. (smoothlpnorm): (r^2 + mu)^(p/2)
+COST_LOG = "log"  # log(1 + r^2/mu), the p -> 0 limit of the lp form (shifted, rescaled)
+
+
+# ---------------------------------------------------------------------------
+# Cost functor, Sec. 3.1, eqs. (smoothlpnorm), (weightedLPnorm)
+# ---------------------------------------------------------------------------
+
+def phi(r, p, mu, form=COST_LP):
+    """Per-entry smoothed cost.  lp form: eq. (smoothlpnorm) summand
+    (r^2+mu)^(p/2).  log form: log(1 + r^2/mu)."""
+    r = np.asarray(r, dtype=np.float64)
+    if form == COST_LP:
+        return (r * r + mu) ** (p / 2.0)
+    if form == COST_LOG:
+        return np.log1p(r * r / mu)
+    raise ValueError(form)
+
+
+def dphi(r, p, mu, form=COST_LP):
+    """d phi / d r.  lp form: p r (r^2+mu)^(p/2-1), the factor appearing in the
+    derivative of Sec. 3.3 (Step 2).  log form: 2r/(mu+r^2)."""
+    r = np.asarray(r, dtype=np.float64)
+    if form == COST_LP:
+        return p * r * (r * r + mu) ** (p / 2.0 - 1.0)
+    if form == COST_LOG:
+        return 2.0 * r / (mu + r * r)
+    raise ValueError(form)
+
+
+def curv(r, p, mu, form=COST_LP):
+    """c(r) = phi'(r)/r, the weight of the quadratic majoriser of phi at r
+    (phi is a concave function of r^2 for p <= 2, Sec. 3.1)."""
+    r = np.asarray(r, dtype=np.float64)
+    if form == COST_LP:
+        return p * (r * r + mu) ** (p / 2.0 - 1.0)
+    if form == COST_LOG:
+        return 2.0 / (mu + r * r)
+    raise ValueError(form)
+
+
+def dphi_dmu(r, p, mu, form=COST_LP):
+    """d phi / d mu, needed by the differentiable cost."""
+    r = np.asarray(r, dtype=np.float64)
+    if form == COST_LP:
+        return (p / 2.0) * (r * r + mu) ** (p / 2.0 - 1.0)
+    if form == COST_LOG:
+        return -(r * r) / (mu * (mu + r * r))
+    raise ValueError(form)
+
+
+def delta_from_mu(mu, p, form=COST_LP):
+    """Threshold delta at which the second derivative of the cost in r
+    vanishes, eqs. (opt_mu), (opt_mu2): mu = delta^2 (1-p) for the lp form,
+    so delta = sqrt(mu/(1-p)).  For the log form the inflection is at
+    sqrt(mu) (the same condition applied to log(1+r^2/mu))."""
+    if form == COST_LP:
+        return math.sqrt(mu / (1.0 - p))
+    return math.sqrt(mu)
+
+
+def mu_from_delta(delta, p):
+    """eq. (opt_mu2): mu = delta^2 (1 - p)."""
+    return delta * delta * (1.0 - p)
+
+
+# ---------------------------------------------------------------------------
+# Parameters and state
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Params:
+    """Parameter set of Sec. 5.1 (k, omega, t_init, t_min, delta, p, mu and the
+    number of CG steps).  Defaults are the benchmark values printed there,
+    except mu/delta which callers set per workload."""
+    width: int
+    height: int
+    channels: int = 1
+    k: int = 15
+    cg_iters: int = 5            # "a maximum of five CG steps" (Sec. 5.1)
+    cost: str = COST_LP
+    p: float = 0.25
+    mu: float = 1e-3
+    delta: Optional[float] = None  # None -> delta_from_mu (eq. opt_mu2)
+    omega: float = 5e-5
+    t_init: float = 5e-3
+    t_min: float = 1e-4
+    i_init: int = 100
+    labels_after_update: bool = True   # READING: step 3 uses U^(i+1)
+    weights_from_filtered: bool = False  # READING: raw labels feed the weights
+
+    @property
+    def P(self):
+        return self.width * self.height
+
+    @property
+    def m(self):
+        return self.channels * self.P
+
+    @property
+    def thr(self):
+        return self.delta if self.delta is not None else delta_from_mu(self.mu, self.p, self.cost)
+
+
+@dataclasses.dataclass
+class State:
+    U: np.ndarray        # m x k
+    y: np.ndarray        # k
+    labels: np.ndarray   # P, uint8 raw labels of the previous frame
+    mask: np.ndarray     # P, uint8 median-filtered mask of the previous frame
+    n: int = 0           # number of frames processed
+
+    def copy(self):
+        return State(self.U.copy(), self.y.copy(), self.labels.copy(), self.mask.copy(), self.n)
+
+
+def initial_state(U0, P):
+    """Start of the online scheme, Sec. 3.4 (Initialization): U0 given
+    (a reduced QR of a random matrix, drawn by the caller); y = 0; no pixel
+    labelled foreground yet."""
+    U0 = np.array(U0, dtype=np.float64)
+    k = U0.shape[1]
+    return State(U0, np.zeros(k), np.zeros(P, np.uint8), np.zeros(P, np.uint8), 0)
+
+
+# ---------------------------------------------------------------------------
+# Weighted cost and its pieces, eqs. (weightedLPnorm), (spcacost)
+# ---------------------------------------------------------------------------
+
+def pixel_weights(labels, omega, channels):
+    """eq. (pixelweighting): weight 1 where the previous frame's label is
+    background, omega where it is foreground.  READING: one weight per pixel,
+    shared by all colour entries of that pixel."""
+    wp = np.where(np.asarray(labels) == 0, 1.0, float(omega))
+    return np.tile(wp, channels)
+
+
+def cost(U, x, y, w, p, mu, form=COST_LP):
+    """h_{mu,w}(x - U y), eq. (spcacost)."""
+    r = x - U @ y
+    return float(np.sum(w * phi(r, p, mu, form)))
+
+
+def grad_y(U, x, y, w, p, mu, form=COST_LP):
+    """Gradient of eq. (spcacost) in y: -U^T (w * phi'(r)), r = x - U y."""
+    r = x - U @ y
+    return -(U.T @ (w * dphi(r, p, mu, form)))
+
+
+def curvature(U, x, y, w, p, mu, form=COST_LP):
+    """H = U^T diag(w * c(r)) U: curvature of the quadratic majoriser of
+    eq. (spcacost) at y (c = phi'/r)."""
+    r = x - U @ y
+    cw = w * curv(r, p, mu, form)
+    return U.T @ (U * cw[:, None])
+
+
+# ---------------------------------------------------------------------------
+# Step 1: y-solve, eq. (onlinestep1), CG of Sec. 3.3
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class CGRecord:
+    f: list            # cost at y_0 .. y_J (f[-1] at the returned y)
+    alpha: list
+    beta: list
+    restarts: int
+    iters: int
+
+
+def cg_solve(U, x, w, y0, J, p, mu, form=COST_LP):
+    """Minimise h_{mu,w}(x - U y) over y from the warm start y0 with at most J
+    nonlinear conjugate-gradient steps (Sec. 3.3 Step 1; J = 5, Sec. 5.1).
+
+    READING (the paper names CG but not its variant or line search):
+    Polak-Ribiere-plus direction, restart along -g when the direction is not
+    a descent direction, and the step alpha = -g.d / (d.H d) that minimises
+    the quadratic majoriser f + a g.d + a^2/2 d.H d of the cost along d
+    (H from `curvature`), so the cost never increases.  A fixed number of
+    steps; stop early only at an exactly zero gradient or zero curvature."""
+    y = np.array(y0, dtype=np.float64)
+    rec = CGRecord([], [], [], 0, 0)
+    g_prev = d_prev = None
+    for j in range(J):
+        r = x - U @ y
+        rec.f.append(float(np.sum(w * phi(r, p, mu, form))))
+        g = -(U.T @ (w * dphi(r, p, mu, form)))
+        if not np.any(g):
+            break
+        if j == 0:
+            d = -g
+            beta = 0.0
+        else:
+            beta = max(0.0, float(g @ (g - g_prev)) / float(g_prev @ g_prev))
+            d = -g + beta * d_prev
+            if float(g @ d) >= 0.0:
+                d = -g
+                rec.restarts += 1
+        H = U.T @ (U * (w * curv(r, p, mu, form))[:, None])
+        dHd = float(d @ H @ d)
+        if not dHd > 0.0:
+            break
+        alpha = -float(g @ d) / dHd
+        y = y + alpha * d
+        rec.alpha.append(alpha)
+        rec.beta.append(beta)
+        rec.iters += 1
+        g_prev, d_prev = g, d
+    rec.f.append(cost(U, x, y, w, p, mu, form))
+    return y, rec
+
+
+# ---------------------------------------------------------------------------
+# Step 2: one geodesic step on the Grassmannian, Sec. 3.2, 3.3
+# ---------------------------------------------------------------------------
+
+def project_tangent(U, H):
+    """eq. (gproject): pi(H) = (I - U U^T) H."""
+    return H - U @ (U.T @ H)
+
+
+def step_size(n, t_init, t_min, i_init):
+    """Step-size rule of Sec. 3.4: t = max(exp(-tau i) t_init, t_min) with
+    tau = -log(t_min/t_init) / i_init.  READING: i is the 0-based frame
+    index."""
+    tau = -math.log(t_min / t_init) / i_init
+    return max(math.exp(-tau * n) * t_init, t_min)
+
+
+def eta_vector(U, x, y, w, p, mu, form=COST_LP):
+    """eta_i = -p w_i r_i (r_i^2+mu)^(p/2-1) = -w_i phi'(r_i), r = x - U y
+    (Sec. 3.3 Step 2); the Euclidean gradient in U is eta y^T."""
+    r = x - U @ y
+    return -w * dphi(r, p, mu, form)
+
+
+def rank_one_svd(U, eta, y):
+    """Closed-form SVD of the projected gradient G_U = pi(eta) y^T, eq. (svd):
+    s = pi(eta)/||pi(eta)||, sigma = ||pi(eta)|| ||y||, v = y/||y||.
+    The projection is applied twice so that s is orthogonal to span(U) to
+    working precision.  Returns (s, sigma, v, zeta, nu) with zeta =
+    ||pi(eta)|| and nu = ||y||; s or v is None when zeta or nu is 0."""
+    z = project_tangent(U, eta)
+    z = project_tangent(U, z)
+    zeta = float(np.linalg.norm(z))
+    nu = float(np.linalg.norm(y))
+    s = z / zeta if zeta > 0 else None
+    v = y / nu if nu > 0 else None
+    return s, zeta * nu, v, zeta, nu
+
+
+def geodesic_rank_one(U, s, v, theta):
+    """eq. (geodesic) for the descent direction B = -G_U = sigma (-s) v^T.
+    The thin SVD of B completes v to an orthonormal V in O(k) (all other
+    singular values are zero), which leaves
+        U(t) = U + (cos(theta) - 1) (U v) v^T - sin(theta) s v^T,
+    theta = sigma t.  READING: the "compact SVD" of the paper is taken as
+    this thin SVD; a literal rank-one compact SVD would collapse U(t)."""
+    Uv = U @ v
+    return U + (math.cos(theta) - 1.0) * np.outer(Uv, v) - math.sin(theta) * np.outer(s, v)
+
+
+# ---------------------------------------------------------------------------
+# Step 3: segmentation and weights, Sec. 3.3 Step 3, Sec. 3.4
+# ---------------------------------------------------------------------------
+
+def pixel_labels(U, x, y, thr, channels):
+    """Label a pixel foreground when the largest residual over its colour
+    channels reaches the threshold, Sec. 3.4 (Color images);
+    eq. (pixelweighting) for one channel.  READING: ties (== thr) are
+    foreground, as in the colour rule."""
+    r = np.abs(x - U @ y)
+    P = r.size // channels
+    rmax = r.reshape(channels, P).max(axis=0)
+    return (rmax >= thr).astype(np.uint8)
+
+
+def median3x3(labels, height, width):
+    """3x3 median filter of the binary mask (Sec. 3.4, Pre- and
+    post-processing).  On binary values the median of the nine neighbours is
+    1 exactly when at least five of them are 1.  READING: image borders
+    replicate the edge pixel."""
+    L = np.asarray(labels, dtype=np.int64).reshape(height, width)
+    pad = np.pad(L, 1, mode="edge")
+    acc = np.zeros_like(L)
+    for di in range(3):
+        for dj in range(3):
+            acc += pad[di:di + height, dj:dj + width]
+    return (acc >= 5).astype(np.uint8).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# One frame of the online alternating minimisation, Sec. 3.3
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class FrameInfo:
+    cg: CGRecord
+    t: float
+    sigma: float
+    theta: float
+    zeta: float
+    nu: float
+    updated: bool
+
+
+def track_frame(state: State, x, prm: Params):
+    """Process frame x (length m): Step 1 refines y from the previous y,
+    Step 2 takes one geodesic step on U, Step 3 labels the pixels (Sec. 3.3),
+    followed by the 3x3 median (Sec. 3.4).  Returns (new_state, info)."""
+    x = np.asarray(x, dtype=np.float64)
+    U = state.U
+    src = state.mask if prm.weights_from_filtered else state.labels
+    w = pixel_weights(src, prm.omega, prm.channels)
+    # Step 1
+    y, rec = cg_solve(U, x, w, state.y, prm.cg_iters, prm.p, prm.mu, prm.cost)
+    # Step 2
+    eta = eta_vector(U, x, y, w, prm.p, prm.mu, prm.cost)
+    s, sigma, v, zeta, nu = rank_one_svd(U, eta, y)
+    t = step_size(state.n, prm.t_init, prm.t_min, prm.i_init)
+    theta = sigma * t
+    updated = s is not None and v is not None   # READING: no step when G_U = 0
+    U_new = geodesic_rank_one(U, s, v, theta) if updated else U.copy()
+    # Step 3
+    U_lab = U_new if prm.labels_after_update else U
+    labels = pixel_labels(U_lab, x, y, prm.thr, prm.channels)
+    mask = median3x3(labels, prm.height, prm.width)
+    new = State(U_new, y, labels, mask, state.n + 1)
+    return new, FrameInfo(rec, t, sigma, theta, zeta, nu, updated)
+
+
+def band_pixels(U, x, y, thr, channels, guard):
+    """Pixels whose largest channel residual lies within `guard` of the
+    threshold: the only pixels whose label may legitimately differ between
+    two correct implementations that round differently."""
+    r = np.abs(x - U @ y)
+    P = r.size // channels
+    rmax = r.reshape(channels, P).max(axis=0)
+    return np.abs(rmax - thr) <= guard
+
+
+# ---------------------------------------------------------------------------
+# Precision form: nearest orthonormal basis (re-orthonormalisation)
+# ---------------------------------------------------------------------------
+
+def lowdin(U):
+    """Nearest matrix with orthonormal columns (polar factor) U G^{-1/2},
+    G = U^T U, and the factor G^{1/2} that keeps U y unchanged to first order
+    (y <- G^{1/2} y).  Keeps [U] on the Grassmannian (Sec. 3.2: only the
+    span matters) with the smallest change of basis."""
+    G = U.T @ U
+    lam, Q = np.linalg.eigh(G)
+    Gm = (Q / np.sqrt(lam)) @ Q.T
+    Gp = (Q * np.sqrt(lam)) @ Q.T
+    return U @ Gm, Gp
+
+
+# ---------------------------------------------------------------------------
+# Differentiable cost h_mu,w(x - U y) for a batch of frames
+# ---------------------------------------------------------------------------
+
+def lpcost_forward(U, Y, X, w, p, mu, form=COST_LP):
+    """f_b = sum_e w_e phi(X[e,b] - u_e^T Y[:,b]), eqs. (weightedLPnorm),
+    (spcacost), for each column b.  U: m x k, Y: k x B, X: m x B, w: m."""
+    R = X - U @ Y
+    return (w[:, None] * phi(R, p, mu, form)).sum(axis=0)
+
+
+def lpcost_backward(U, Y, X, w, p, mu, gout, form=COST_LP):
+    """Adjoint of lpcost_forward for an upstream gradient gout (length B).
+    dX = gout * w phi'(R); dY = -U^T (w phi'(R)) gout; dU = -(w phi'(R) gout) Y^T
+    (for one frame with gout = 1, -dU is the eta y^T of Sec. 3.3);
+    dmu = sum_b gout_b sum_e w_e dphi/dmu."""
+    R = X - U @ Y
+    D = w[:, None] * dphi(R, p, mu, form)
+    Dg = D * gout[None, :]
+    dX = Dg
+    dY = -(U.T @ Dg)
+    dU = -(Dg @ Y.T)
+    dmu = float(np.sum((w[:, None] * dphi_dmu(R, p, mu, form)) * gout[None, :]))
+    return dX, dU, dY, dmu
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics
+# ---------------------------------------------------------------------------
+
+def orthonormality_error(U):
+    """||U^T U - I||_F (Sec. 2.1, eq. stiefeldef)."""
+    k = U.shape[1]
+    return float(np.linalg.norm(U.T @ U - np.eye(k)))
+
+
+def principal_angles(A, B):
+    """Principal angles between span(A) (orthonormal, m x a) and span(B)
+    (orthonormal, m x b, b >= a), from the singular values of the part of A
+    outside span(B) (arcsin form, accurate for small angles)."""
+    R = A - B @ (B.T @ A)
+    sv = np.linalg.svd(R, compute_uv=False)
+    return np.arcsin(np.clip(sv, 0.0, 1.0))

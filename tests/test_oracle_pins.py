@@ -1,0 +1,412 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each checks a closed form, an
+invariant, a special case that reduces to a textbook/library routine, or a
+brute-force property, chosen so that a dropped term, a wrong sign, index or
+exponent in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.ndimage
+
+from oracle import prost_oracle as O
+from synth import video as V
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(*s):
+    return np.random.default_rng(list(s))
+
+
+# --------------------------------------------------------------------------
+# cost functor, Sec. 3.1
+# --------------------------------------------------------------------------
+
+def test_cost_special_cases_p2_p1():
+    """p = 2 makes eq. (smoothlpnorm) the shifted square r^2 + mu; p = 1 the
+    Charbonnier function sqrt(r^2 + mu).  Catches a wrong exponent."""
+    r = np.linspace(-3, 3, 101)
+    mu = 0.37
+    np.testing.assert_allclose(O.phi(r, 2.0, mu), r * r + mu, rtol=1e-15)
+    np.testing.assert_allclose(O.phi(r, 1.0, mu), np.sqrt(r * r + mu), rtol=1e-15)
+    np.testing.assert_allclose(O.dphi(r, 2.0, mu), 2 * r, rtol=1e-14, atol=1e-15)
+
+
+def test_log_form_is_small_p_limit():
+    """(2/(p mu^{p/2})) ((r^2+mu)^{p/2} - mu^{p/2}) -> log(1 + r^2/mu) as p -> 0."""
+    r = np.linspace(-2, 2, 41)
+    mu = 1e-3
+    p = 1e-7
+    lim = (2.0 / (p * mu ** (p / 2))) * (O.phi(r, p, mu) - mu ** (p / 2))
+    np.testing.assert_allclose(O.phi(r, 0.0, mu, O.COST_LOG), lim, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("form,p", [(O.COST_LP, 0.25), (O.COST_LP, 0.5), (O.COST_LP, 1.0),
+                                    (O.COST_LP, 2.0), (O.COST_LOG, 0.0)])
+def test_cost_derivatives_finite_differences(form, p):
+    """phi' and dphi/dmu against central differences of phi."""
+    r = np.linspace(-1.5, 1.5, 61) + 1e-3
+    mu = 1e-2
+    h = 1e-6
+    fd = (O.phi(r + h, p, mu, form) - O.phi(r - h, p, mu, form)) / (2 * h)
+    np.testing.assert_allclose(O.dphi(r, p, mu, form), fd, rtol=1e-7, atol=1e-9)
+    hm = 1e-8
+    fdm = (O.phi(r, p, mu + hm, form) - O.phi(r, p, mu - hm, form)) / (2 * hm)
+    np.testing.assert_allclose(O.dphi_dmu(r, p, mu, form), fdm, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("form,p", [(O.COST_LP, 0.25), (O.COST_LP, 0.75), (O.COST_LP, 2.0),
+                                    (O.COST_LOG, 0.0)])
+def test_quadratic_majoriser_brute_force(form, p):
+    """phi(s) <= phi(r) + phi'(r)(s-r) + c(r)/2 (s-r)^2 for all s, with
+    equality at s = r and s = -r (phi is concave in r^2 for p <= 2).  The
+    equality at -r fixes c = phi'/r exactly."""
+    mu = 1e-3
+    s = np.linspace(-2, 2, 2001)
+    for r in (-0.7, -0.03, 0.001, 0.02, 0.31, 1.4):
+        q = O.phi(r, p, mu, form) + O.dphi(r, p, mu, form) * (s - r) + 0.5 * O.curv(r, p, mu, form) * (s - r) ** 2
+        assert np.all(O.phi(s, p, mu, form) <= q + 1e-12 * np.maximum(1, np.abs(q)))
+        q_neg = O.phi(r, p, mu, form) + O.dphi(r, p, mu, form) * (-2 * r) + 0.5 * O.curv(r, p, mu, form) * 4 * r * r
+        assert abs(q_neg - O.phi(-r, p, mu, form)) <= 1e-12 * max(1.0, abs(q_neg))
+
+
+@pytest.mark.parametrize("form,p", [(O.COST_LP, 0.25), (O.COST_LP, 0.5), (O.COST_LOG, 0.0)])
+def test_delta_mu_coupling(form, p):
+    """eq. (opt_mu): the second derivative in r vanishes at delta, and changes
+    sign there (positive inside, negative outside)."""
+    mu = 1e-3
+    d = O.delta_from_mu(mu, p, form)
+    h = 1e-7
+
+    def d2(r):
+        return (O.dphi(r + h, p, mu, form) - O.dphi(r - h, p, mu, form)) / (2 * h)
+
+    scale = abs(d2(0.0))
+    assert abs(d2(d)) < 1e-5 * scale
+    assert d2(0.9 * d) > 0 > d2(1.1 * d)
+
+
+def test_paper_parameters_golden():
+    """Benchmark parameter set printed in Sec. 5.1, with mu from eq. (opt_mu2)."""
+    g = json.load(open(os.path.join(GOLD, "paper_parameters.json")))
+    assert O.mu_from_delta(g["delta"], g["p"]) == pytest.approx(g["mu_expected"], rel=1e-15)
+    assert O.delta_from_mu(g["mu_expected"], g["p"]) == pytest.approx(g["delta"], rel=1e-14)
+    prm = O.Params(160, 120, 3)
+    assert (prm.k, prm.omega, prm.t_init, prm.t_min, prm.p, prm.cg_iters) == \
+        (g["k"], g["omega"], g["t_init"], g["t_min"], g["p"], g["max_cg_steps"])
+
+
+# --------------------------------------------------------------------------
+# Step 1: y-solve
+# --------------------------------------------------------------------------
+
+def _problem(m=300, k=4, seed=0, frac_w=0.3):
+    rng = _rng(seed)
+    U = V.random_orthonormal(m, k, rng)
+    x = U @ rng.standard_normal(k) * 0.3 + 0.02 * rng.standard_normal(m)
+    out = rng.random(m) < 0.08
+    x[out] += rng.uniform(0.2, 1.0, out.sum())
+    w = np.where(rng.random(m) < frac_w, 5e-2, 1.0)
+    return U, x, w
+
+
+@pytest.mark.parametrize("form,p", [(O.COST_LP, 0.25), (O.COST_LOG, 0.0)])
+def test_gradient_and_majoriser_along_direction(form, p):
+    """g against central differences of the cost in y; and the MM bound
+    f(y + a d) <= f(y) + a g.d + a^2/2 d.H d on a grid of a (brute force)."""
+    U, x, w = _problem(seed=3)
+    mu = 1e-3
+    rng = _rng(4)
+    y = rng.standard_normal(U.shape[1]) * 0.2
+    g = O.grad_y(U, x, y, w, p, mu, form)
+    h = 1e-6
+    for j in range(U.shape[1]):
+        e = np.zeros_like(y); e[j] = h
+        fd = (O.cost(U, x, y + e, w, p, mu, form) - O.cost(U, x, y - e, w, p, mu, form)) / (2 * h)
+        assert fd == pytest.approx(g[j], rel=1e-6, abs=1e-8)
+    H = O.curvature(U, x, y, w, p, mu, form)
+    f0 = O.cost(U, x, y, w, p, mu, form)
+    for _ in range(5):
+        d = rng.standard_normal(U.shape[1])
+        for a in np.linspace(-3, 3, 121):
+            q = f0 + a * g @ d + 0.5 * a * a * d @ H @ d
+            assert O.cost(U, x, y + a * d, w, p, mu, form) <= q + 1e-10 * abs(q)
+
+
+def test_cg_monotone_on_video():
+    """The cost never increases over the CG steps of any frame."""
+    wl = V.small_gray()
+    sv = V.SyntheticVideo(wl.video)
+    prm = O.Params(80, 60, 1, k=5, mu=wl.mu)
+    st = O.initial_state(V.initial_subspace(prm.m, 5, 1), prm.P)
+    for n in range(60):
+        st, info = O.track_frame(st, sv.frame(n), prm)
+        f = np.array(info.cg.f)
+        assert np.all(np.diff(f) <= 1e-12 * f[0]), (n, f)
+
+
+def test_cg_mu_infinity_is_least_squares():
+    """mu -> infinity makes the cost quadratic: w = 1 gives y = U^T x; general
+    w gives the weighted least-squares solution (U^T W U)^{-1} U^T W x
+    (Sec. 2.1 fit)."""
+    U, x, w = _problem(m=200, k=3, seed=5)
+    y, _ = O.cg_solve(U, x, np.ones_like(x), np.zeros(3), 5, 0.25, 1e8)
+    np.testing.assert_allclose(y, U.T @ x, rtol=1e-6)
+    y, _ = O.cg_solve(U, x, w, np.zeros(3), 5, 0.25, 1e8)
+    Wls = np.linalg.solve(U.T @ (U * w[:, None]), U.T @ (w * x))
+    np.testing.assert_allclose(y, Wls, rtol=1e-6)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cg_p2_reaches_weighted_least_squares_in_k_steps(seed):
+    """p = 2: phi is quadratic, so the CG is linear CG and ends at the exact
+    weighted least-squares solution after at most k steps.  Catches a wrong
+    PR+ coefficient or step length."""
+    k = 5
+    U, x, w = _problem(m=250, k=k, seed=10 + seed, frac_w=0.5)
+    rng = _rng(seed)
+    y0 = rng.standard_normal(k)
+    y, rec = O.cg_solve(U, x, w, y0, k, 2.0, 0.1)
+    Wls = np.linalg.solve(U.T @ (U * w[:, None]), U.T @ (w * x))
+    np.testing.assert_allclose(y, Wls, rtol=1e-10, atol=1e-12)
+    # w = 1: H is a multiple of I, one step is exact
+    y1, _ = O.cg_solve(U, x, np.ones_like(x), y0, 1, 2.0, 0.1)
+    np.testing.assert_allclose(y1, U.T @ x, rtol=1e-12, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Step 2: geodesic step
+# --------------------------------------------------------------------------
+
+def test_projection_idempotent_and_tangent():
+    """eq. (gproject): pi(pi(H)) = pi(H) and U^T pi(H) = 0."""
+    rng = _rng(21)
+    U = V.random_orthonormal(120, 4, rng)
+    Hm = rng.standard_normal((120, 3))
+    P1 = O.project_tangent(U, Hm)
+    np.testing.assert_allclose(O.project_tangent(U, P1), P1, atol=1e-14)
+    assert np.abs(U.T @ P1).max() < 1e-14
+
+
+def test_rank_one_svd_matches_lapack():
+    """eq. (svd) against LAPACK's SVD of G_U = pi(eta) y^T: one nonzero
+    singular value sigma = ||pi(eta)|| ||y||, singular vectors s, v up to sign."""
+    U, x, w = _problem(m=150, k=4, seed=7)
+    y = _rng(8).standard_normal(4)
+    eta = O.eta_vector(U, x, y, w, 0.25, 1e-3)
+    s, sigma, v, zeta, nu = O.rank_one_svd(U, eta, y)
+    G = np.outer(O.project_tangent(U, eta), y)
+    Uu, S, Vt = np.linalg.svd(G, full_matrices=False)
+    assert S[0] == pytest.approx(sigma, rel=1e-13)
+    assert np.all(S[1:] < 1e-12 * S[0])
+    assert min(np.linalg.norm(Uu[:, 0] - s), np.linalg.norm(Uu[:, 0] + s)) < 1e-12
+    assert min(np.linalg.norm(Vt[0] - v), np.linalg.norm(Vt[0] + v)) < 1e-12
+
+
+def _geodesic_setup(seed=9, m=40, k=3):
+    U, x, w = _problem(m=m, k=k, seed=seed)
+    y = _rng(seed + 1).standard_normal(k)
+    eta = O.eta_vector(U, x, y, w, 0.25, 1e-3)
+    return U, x, w, y, eta
+
+
+@pytest.mark.parametrize("t", [1e-4, 3e-3, 0.02])
+def test_geodesic_matches_edelman_thin_svd_and_expm(t):
+    """The rank-one closed form equals (i) eq. (geodesic) evaluated with the
+    LAPACK thin SVD of B = -G_U and (ii) the matrix exponential of the skew
+    block generator [[0, -R^T], [R, 0]] with B = Q R, on tiny inputs."""
+    U, x, w, y, eta = _geodesic_setup()
+    s, sigma, v, _, _ = O.rank_one_svd(U, eta, y)
+    Uc = O.geodesic_rank_one(U, s, v, sigma * t)
+    B = -np.outer(O.project_tangent(U, O.project_tangent(U, eta)), y)
+    Th, S, Vt = np.linalg.svd(B, full_matrices=False)
+    V_ = Vt.T
+    Ue = (U @ V_ @ np.diag(np.cos(S * t)) + Th @ np.diag(np.sin(S * t))) @ Vt
+    np.testing.assert_allclose(Uc, Ue, atol=1e-13)
+    Q, R = np.linalg.qr(B)
+    k = U.shape[1]
+    X = np.block([[np.zeros((k, k)), -R.T], [R, np.zeros((k, k))]])
+    E = scipy.linalg.expm(t * X)
+    Ux = np.hstack([U, Q]) @ E[:, :k]
+    np.testing.assert_allclose(Uc, Ux, atol=1e-13)
+
+
+def test_geodesic_is_descent_with_rate_minus_sigma_squared():
+    """d/dt h(x - U(t) y) at t = 0 equals <eta y^T, B> = -sigma^2: a
+    sign error or a missing factor in the step shows here."""
+    U, x, w, y, eta = _geodesic_setup(m=60, k=4)
+    s, sigma, v, _, _ = O.rank_one_svd(U, eta, y)
+    h = 1e-7
+
+    def f(t):
+        return O.cost(O.geodesic_rank_one(U, s, v, sigma * t), x, y, w, 0.25, 1e-3)
+
+    slope = (f(h) - f(-h)) / (2 * h)
+    assert slope == pytest.approx(-sigma ** 2, rel=1e-5)
+
+
+def test_step_size_schedule():
+    """Sec. 3.4: t = t_init at frame 0 and t_min from frame i_init on."""
+    assert O.step_size(0, 5e-3, 1e-4, 100) == pytest.approx(5e-3, rel=1e-15)
+    assert O.step_size(100, 5e-3, 1e-4, 100) == pytest.approx(1e-4, rel=1e-12)
+    assert O.step_size(500, 5e-3, 1e-4, 100) == 1e-4
+    assert O.step_size(50, 5e-3, 1e-4, 100) == pytest.approx(math.sqrt(5e-3 * 1e-4), rel=1e-12)
+
+
+def test_orthonormality_along_trajectory():
+    """The geodesic keeps U on the Stiefel manifold: ||U^T U - I|| < 1e-12
+    after every frame (eq. stiefeldef)."""
+    wl = V.small_gray()
+    sv = V.SyntheticVideo(wl.video)
+    prm = O.Params(80, 60, 1, k=5, mu=wl.mu)
+    st = O.initial_state(V.initial_subspace(prm.m, 5, 1), prm.P)
+    for n in range(200):
+        st, _ = O.track_frame(st, sv.frame(n), prm)
+        assert O.orthonormality_error(st.U) < 1e-12
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_planted_subspace_recovery(k):
+    """Noise- and foreground-free rank-2 video: span(U) converges to the
+    planted span(Q) (principal angles < 1e-6) from a random start."""
+    spec = V.VideoSpec(12, 10, 1, rank=2, seed=11, noise=0.0, fg_kind="none")
+    sv = V.SyntheticVideo(spec)
+    prm = O.Params(12, 10, 1, k=k, mu=1e-3, t_init=2e-3, t_min=2e-3, omega=1.0)
+    st = O.initial_state(V.initial_subspace(prm.m, k, 7), prm.P)
+    for n in range(3000):
+        st, _ = O.track_frame(st, sv.frame(n), prm)
+    assert O.principal_angles(sv.Q, st.U).max() < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Step 3: labels and median
+# --------------------------------------------------------------------------
+
+def test_labels_recover_planted_mask_with_exact_background():
+    """With U spanning the planted background and y its exact coefficients,
+    noise well below delta and foreground textures far from the background,
+    the labels are the planted mask; one channel alone is enough to mark a
+    pixel (max over channels, Sec. 3.4)."""
+    spec = V.VideoSpec(40, 30, 3, rank=3, seed=12, noise=0.001, fg_kind="rects",
+                       fg_count=2, fg_density=0.1)
+    sv = V.SyntheticVideo(spec)
+    x, mask = sv.frame(5, with_mask=True)
+    c = sv.coeffs(5)
+    bg = sv.Q @ c
+    far = np.abs(x - bg).reshape(3, -1).max(axis=0)
+    ok = (~mask) | (far > 0.05)     # foreground pixels that differ clearly
+    lab = O.pixel_labels(sv.Q, x, c, 0.02, 3)
+    assert np.array_equal(lab[ok].astype(bool), mask[ok])
+    # a single-channel outlier marks its pixel
+    x2 = bg.copy()
+    x2[2 * spec.P + 17] += 0.5
+    lab2 = O.pixel_labels(sv.Q, x2, c, 0.02, 3)
+    assert lab2.sum() == 1 and lab2[17] == 1
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (5, 1), (9, 13), (60, 80)])
+def test_median_matches_scipy(shape):
+    rng = _rng(13, *shape)
+    L = (rng.random(shape) < 0.4).astype(np.uint8)
+    ref = scipy.ndimage.median_filter(L, size=3, mode="nearest")
+    got = O.median3x3(L.reshape(-1), *shape).reshape(shape)
+    assert np.array_equal(got, ref)
+
+
+def test_tracker_segments_small_video():
+    """After 200 frames of the 80x60 workload the filtered mask agrees with
+    the planted foreground on > 99% of pixels."""
+    wl = V.small_gray()
+    sv = V.SyntheticVideo(wl.video)
+    prm = O.Params(80, 60, 1, k=5, mu=wl.mu)
+    st = O.initial_state(V.initial_subspace(prm.m, 5, 1), prm.P)
+    for n in range(200):
+        st, _ = O.track_frame(st, sv.frame(n), prm)
+    _, mask = sv.frame(199, with_mask=True)
+    assert (st.mask.astype(bool) == mask).mean() > 0.99
+
+
+# --------------------------------------------------------------------------
+# precision form: re-orthonormalisation
+# --------------------------------------------------------------------------
+
+def test_lowdin_is_polar_factor():
+    rng = _rng(14)
+    U = V.random_orthonormal(90, 5, rng) + 1e-3 * rng.standard_normal((90, 5))
+    Ul, Gp = O.lowdin(U)
+    Up, Pp = scipy.linalg.polar(U)
+    np.testing.assert_allclose(Ul, Up, atol=1e-13)
+    np.testing.assert_allclose(Gp, Pp, atol=1e-13)
+    assert O.orthonormality_error(Ul) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# differentiable cost
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("form,p", [(O.COST_LP, 0.25), (O.COST_LOG, 0.0)])
+def test_lpcost_backward_finite_differences(form, p):
+    """All four adjoints against FP64 central differences (m=48, k=3, B=2,
+    every entry)."""
+    rng = _rng(15)
+    m, k, B = 48, 3, 2
+    U = rng.standard_normal((m, k)) * 0.3
+    Y = rng.standard_normal((k, B)) * 0.3
+    X = rng.standard_normal((m, B)) * 0.3
+    w = np.where(rng.random(m) < 0.3, 0.1, 1.0)
+    mu = 1e-2
+    gout = rng.standard_normal(B)
+    dX, dU, dY, dmu = O.lpcost_backward(U, Y, X, w, p, mu, gout, form)
+
+    def L(U_, Y_, X_, mu_):
+        return float(gout @ O.lpcost_forward(U_, Y_, X_, w, p, mu_, form))
+
+    h = 1e-6
+    for A, dA, name in ((U, dU, "U"), (Y, dY, "Y"), (X, dX, "X")):
+        fd = np.zeros_like(A)
+        for idx in np.ndindex(A.shape):
+            Ap, Am = A.copy(), A.copy()
+            Ap[idx] += h; Am[idx] -= h
+            args_p = dict(U_=U, Y_=Y, X_=X, mu_=mu); args_m = dict(args_p)
+            key = {"U": "U_", "Y": "Y_", "X": "X_"}[name]
+            args_p[key] = Ap; args_m[key] = Am
+            fd[idx] = (L(**args_p) - L(**args_m)) / (2 * h)
+        np.testing.assert_allclose(dA, fd, rtol=1e-6, atol=1e-7)
+    hm = 1e-8
+    fdm = (L(U, Y, X, mu + hm) - L(U, Y, X, mu - hm)) / (2 * hm)
+    assert dmu == pytest.approx(fdm, rel=1e-5)
+
+
+@pytest.mark.parametrize("form,p", [(O.COST_LP, 0.25), (O.COST_LOG, 0.0)])
+def test_lpcost_backward_torch_autograd(form, p):
+    """Against torch's FP64 autograd of the forward written in torch ops."""
+    torch = pytest.importorskip("torch")
+    rng = _rng(16)
+    m, k, B = 200, 4, 3
+    U = rng.standard_normal((m, k)) * 0.3
+    Y = rng.standard_normal((k, B)) * 0.3
+    X = rng.standard_normal((m, B)) * 0.3
+    w = np.where(rng.random(m) < 0.3, 0.1, 1.0)
+    mu = 1e-3
+    gout = rng.standard_normal(B)
+    tU, tY, tX = (torch.tensor(a, requires_grad=True) for a in (U, Y, X))
+    tmu = torch.tensor(mu, dtype=torch.float64, requires_grad=True)
+    R = tX - tU @ tY
+    if form == O.COST_LP:
+        ph = (R * R + tmu) ** (p / 2)
+    else:
+        ph = torch.log1p(R * R / tmu)
+    f = (torch.tensor(w)[:, None] * ph).sum(0)
+    (f * torch.tensor(gout)).sum().backward()
+    dX, dU, dY, dmu = O.lpcost_backward(U, Y, X, w, p, mu, gout, form)
+    np.testing.assert_allclose(dU, tU.grad.numpy(), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(dY, tY.grad.numpy(), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(dX, tX.grad.numpy(), rtol=1e-10, atol=1e-12)
+    assert dmu == pytest.approx(float(tmu.grad), rel=1e-10)
+    np.testing.assert_allclose(O.lpcost_forward(U, Y, X, w, p, mu, form), f.detach().numpy(), rtol=1e-12)
