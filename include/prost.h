@@ -1,0 +1,182 @@
+/*
+ * prost.h -- C ABI of the MI355X (gfx950) pROST per-frame hot path.
+ *
+ * pROST (Seidel, Hage, Kleinsteuber, arXiv:1302.2073) tracks a background
+ * subspace U (m x k, orthonormal columns) of a video online.  Every frame x
+ * (m = channels * width * height entries) is processed in three steps
+ * (Sec. 3.3 "An online alternating minimization algorithm"):
+ *   Step 1  y = argmin_y h_{mu,w}(x - U y)            eq. (onlinestep1),
+ *           a few conjugate-gradient steps on the weighted smoothed cost
+ *           h_{mu,w}(r) = sum_i w_i (r_i^2 + mu)^(p/2)  eq. (weightedLPnorm);
+ *   Step 2  one descent step of U along the Grassmann geodesic eq. (geodesic)
+ *           using the closed-form rank-one SVD of the projected gradient
+ *           eq. (svd) and the step-size rule of Sec. 3.4;
+ *   Step 3  segmentation: pixel i is foreground when max over colour channels
+ *           of |x_i - u_i^T y| >= delta (Sec. 3.4 "Color images"); the labels
+ *           set the weights w (1 or omega) of the next frame
+ *           eq. (pixelweighting); a 3x3 median filter gives the output mask
+ *           (Sec. 3.4 "Pre- and post-processing").
+ *
+ * Layout.  Frames are planar: all P = width*height pixels of channel 0, then
+ * channel 1, ... ; each plane row-major (pixel p = row*width + col, entry
+ * e = c*P + p), as x = [x_R; x_G; x_B] of Sec. 3.4.  Masks are P bytes (0/1).
+ * State exchanged through pros_get_state / pros_set_state is float64 on the
+ * host: U column-major m x k (column j at U + j*m), y of length k.
+ *
+ * Ownership.  A handle owns all device memory it uses (U, y, labels, mask,
+ * partial sums, staging).  Callers own every buffer they pass in.  Device
+ * pointers passed in must stay valid and unmodified until the work queued on
+ * the handle's stream has completed.
+ *
+ * Asynchrony and errors.  Work is queued on the HIP stream given at init
+ * (NULL = the default stream).  pros_track_frame returns without waiting;
+ * errors detected on the device (a non-finite frame, a kernel that timed out
+ * waiting for its peers) are reported by the next call that synchronises
+ * (pros_get_mask, pros_get_state, pros_get_stats, pros_sync).  No function
+ * throws; every function returns a pros_status.  After PROS_EHIP or
+ * PROS_ETIMEOUT the handle must be destroyed.  A handle is not thread-safe.
+ */
+#ifndef PROST_H
+#define PROST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pros_status {
+  PROS_OK = 0,
+  PROS_EINVAL = -1,        /* invalid argument or parameter set */
+  PROS_ENOMEM = -2,        /* device or host allocation failed */
+  PROS_EHIP = -3,          /* a HIP runtime call failed (handle unusable) */
+  PROS_ESTATE = -4,        /* call not valid in the current handle state */
+  PROS_EBADFRAME = -5,     /* frame had a NaN/Inf entry; state left unchanged */
+  PROS_ETIMEOUT = -6,      /* a persistent kernel gave up waiting (handle unusable) */
+  PROS_EUNSUPPORTED = -7   /* size/option outside what this build supports */
+} pros_status;
+
+typedef enum pros_dtype { PROS_F32 = 0, PROS_BF16 = 1 } pros_dtype;
+
+/* Per-entry cost phi(r):
+ *   PROS_COST_LP : (r^2 + mu)^(p/2), eq. (smoothlpnorm), 0 < p <= 2;
+ *   PROS_COST_LOG: log(1 + r^2/mu), the p -> 0 limit of the lp form. */
+typedef enum pros_cost { PROS_COST_LP = 0, PROS_COST_LOG = 1 } pros_cost;
+
+enum { PROS_MAX_K = 16, PROS_MAX_CG = 16 };
+
+typedef struct pros_params {
+  int32_t width, height, channels; /* channels 1..4 */
+  int32_t k;                       /* subspace dimension, 1..PROS_MAX_K */
+  int32_t cg_iters;                /* CG steps per frame (Sec. 5.1: 5), 1..PROS_MAX_CG */
+  int32_t cost;                    /* pros_cost */
+  double p;                        /* lp exponent (Sec. 5.1: 0.25) */
+  double mu;                       /* smoothing mu > 0 */
+  double delta;                    /* threshold; <= 0 selects eq. (opt_mu2):
+                                      sqrt(mu/(1-p)) (lp) or sqrt(mu) (log) */
+  double omega;                    /* foreground weight in [0,1] (Sec. 5.1: 5e-5) */
+  double t_init, t_min;            /* step-size rule of Sec. 3.4 */
+  int32_t i_init;                  /* frames to decay from t_init to t_min */
+  int32_t storage;                 /* pros_dtype of U and of device frames */
+  int32_t reorth_every;            /* re-orthonormalise U every N frames; 0 = never */
+  int32_t labels_after_update;     /* 1: labels use the updated U (default) */
+  int32_t weights_from_filtered;   /* 1: weights from the median-filtered mask */
+  int32_t reserved;                /* must be 0 */
+} pros_params;
+
+typedef struct pros_stats {
+  int64_t frame;                 /* 0-based index of the frame described */
+  int32_t cg_steps;              /* CG steps taken (< cg_iters only at an exact stop) */
+  int32_t restarts;              /* steps whose PR+ direction was reset to -g */
+  int32_t updated;               /* 1 if U moved (zeta > 0 and nu > 0) */
+  int32_t bad_frame;             /* 1 if the frame was rejected (non-finite) */
+  double f[PROS_MAX_CG + 1];     /* cost at y_0 .. y_{cg_steps} */
+  double alpha[PROS_MAX_CG];     /* CG step lengths */
+  double beta[PROS_MAX_CG];      /* PR+ coefficients */
+  double t;                      /* step size of the frame (Sec. 3.4) */
+  double sigma;                  /* ||pi(eta)|| ||y||, eq. (svd) */
+  double theta;                  /* geodesic angle sigma * t */
+  double zeta;                   /* ||pi(eta)|| */
+  double nu;                     /* ||y|| */
+} pros_stats;
+
+typedef struct pros_handle pros_handle;
+
+/* Fill *out with the Sec. 5.1 benchmark parameters for a width x height x
+ * channels video (k=15, 5 CG steps, p=0.25, omega=5e-5, t_init=5e-3,
+ * t_min=1e-4, i_init=100, mu=1e-3, FP32 storage).  Returns PROS_EINVAL on a
+ * NULL pointer. */
+pros_status pros_params_default(pros_params* out, int32_t width, int32_t height, int32_t channels);
+
+/* Validate a parameter set without touching the GPU.  PROS_EINVAL names no
+ * field; pros_last_error() gives the reason. */
+pros_status pros_validate(const pros_params* prm);
+
+/* Create a tracker.  Allocates the device state on the current HIP device and
+ * queues its initialisation on `hip_stream` (a hipStream_t, NULL = default):
+ * U = 0 (must be set with pros_set_state before the first frame), y = 0,
+ * labels = mask = 0, frame counter 0.  On error *out is NULL. */
+pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out);
+
+/* Release all device memory of the handle (waits for its stream).  NULL is
+ * accepted. */
+void pros_destroy(pros_handle* h);
+
+/* Load tracker state from host float64 arrays: U (m x k column-major,
+ * required), y (k, NULL = zeros), labels (P bytes, NULL = zeros; also used as
+ * the previous filtered mask), frame counter n >= 0.  U is rounded to the
+ * storage type.  Synchronous. */
+pros_status pros_set_state(pros_handle* h, const double* U, const double* y,
+                           const uint8_t* labels, int64_t n);
+
+/* Copy the tracker state to host buffers (any may be NULL): U as float64
+ * m x k column-major, y (k), raw labels (P bytes), frame counter.
+ * Synchronises the stream and reports pending device errors. */
+pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_t* labels, int64_t* n);
+
+/* Process one frame (Steps 1-3 of Sec. 3.3 and the median).  `frame` holds m
+ * entries of type `dtype` (PROS_F32 or PROS_BF16, must equal the storage
+ * type when on_device = 1).  on_device = 0: host memory, copied to a device
+ * staging buffer before returning (rejected with PROS_EBADFRAME if an entry
+ * is not finite); on_device = 1: device memory read in place by the queued
+ * kernels.  Asynchronous. */
+pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device);
+
+/* Copy the latest mask: filtered = 1 gives the 3x3-median mask F, 0 the raw
+ * labels.  out holds P bytes on the host (on_device = 0, synchronises) or on
+ * the device (on_device = 1, queued on the stream). */
+pros_status pros_get_mask(pros_handle* h, uint8_t* out, int32_t filtered, int32_t on_device);
+
+/* Statistics of the last processed frame.  Synchronises. */
+pros_status pros_get_stats(pros_handle* h, pros_stats* out);
+
+/* Wait for the handle's queued work and report pending device errors. */
+pros_status pros_sync(pros_handle* h);
+
+/* Re-orthonormalise U now (nearest orthonormal basis U (U^T U)^{-1/2},
+ * accumulated and solved in float64 on the GPU; y <- (U^T U)^{1/2} y so that
+ * U y is unchanged to first order).  Asynchronous.  Also run automatically
+ * every reorth_every frames. */
+pros_status pros_reorthonormalize(pros_handle* h);
+
+/* Launch configuration chosen for the handle (for diagnostics). */
+typedef struct pros_launch_info {
+  int32_t workgroups;        /* persistent workgroups of the frame kernel */
+  int32_t threads;           /* threads per workgroup */
+  int32_t rows_per_thread;   /* register-resident rows of U per thread */
+  int32_t pixels_per_wg;     /* pixels of one workgroup tile */
+  int32_t barriers_per_frame;/* gang-wide reductions per frame */
+  int32_t reserved;
+} pros_launch_info;
+pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out);
+
+/* Text for a status code (static storage). */
+const char* pros_strerror(pros_status s);
+/* Detail of the last error on the calling thread (static thread storage). */
+const char* pros_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROST_H */

@@ -1,0 +1,126 @@
+"""ctypes binding of libprost.so (argument marshalling only).
+
+Every entry point of include/prost.h is exposed under the same name.  The
+library must exist (built by paper_1302_2073_amd.build); there is no
+fallback path: importing the functions without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprost.so")
+
+PROS_OK = 0
+PROS_EINVAL = -1
+PROS_ENOMEM = -2
+PROS_EHIP = -3
+PROS_ESTATE = -4
+PROS_EBADFRAME = -5
+PROS_ETIMEOUT = -6
+PROS_EUNSUPPORTED = -7
+
+PROS_F32 = 0
+PROS_BF16 = 1
+PROS_COST_LP = 0
+PROS_COST_LOG = 1
+PROS_MAX_K = 16
+PROS_MAX_CG = 16
+
+
+class pros_params(C.Structure):
+    _fields_ = [
+        ("width", C.c_int32), ("height", C.c_int32), ("channels", C.c_int32),
+        ("k", C.c_int32), ("cg_iters", C.c_int32), ("cost", C.c_int32),
+        ("p", C.c_double), ("mu", C.c_double), ("delta", C.c_double), ("omega", C.c_double),
+        ("t_init", C.c_double), ("t_min", C.c_double), ("i_init", C.c_int32),
+        ("storage", C.c_int32), ("reorth_every", C.c_int32),
+        ("labels_after_update", C.c_int32), ("weights_from_filtered", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class pros_stats(C.Structure):
+    _fields_ = [
+        ("frame", C.c_int64), ("cg_steps", C.c_int32), ("restarts", C.c_int32),
+        ("updated", C.c_int32), ("bad_frame", C.c_int32),
+        ("f", C.c_double * (PROS_MAX_CG + 1)), ("alpha", C.c_double * PROS_MAX_CG),
+        ("beta", C.c_double * PROS_MAX_CG),
+        ("t", C.c_double), ("sigma", C.c_double), ("theta", C.c_double),
+        ("zeta", C.c_double), ("nu", C.c_double),
+    ]
+
+
+class pros_launch_info(C.Structure):
+    _fields_ = [("workgroups", C.c_int32), ("threads", C.c_int32), ("rows_per_thread", C.c_int32),
+                ("pixels_per_wg", C.c_int32), ("barriers_per_frame", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ProstError(RuntimeError):
+    def __init__(self, status, detail=""):
+        self.status = status
+        super().__init__(f"{strerror(status)} ({status}): {detail}")
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "pros_params_default": (C.c_int, [C.POINTER(pros_params), C.c_int32, C.c_int32, C.c_int32]),
+    "pros_validate": (C.c_int, [C.POINTER(pros_params)]),
+    "pros_init": (C.c_int, [C.POINTER(pros_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pros_destroy": (None, [C.c_void_p]),
+    "pros_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "pros_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
+    "pros_track_frame": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    "pros_get_mask": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    "pros_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pros_stats)]),
+    "pros_sync": (C.c_int, [C.c_void_p]),
+    "pros_reorthonormalize": (C.c_int, [C.c_void_p]),
+    "pros_get_launch_info": (C.c_int, [C.c_void_p, C.POINTER(pros_launch_info)]),
+    "pros_strerror": (C.c_char_p, [C.c_int]),
+    "pros_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libprost.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1302_2073_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def strerror(status):
+    try:
+        return lib().pros_strerror(int(status)).decode()
+    except ImportError:
+        return f"status {status}"
+
+
+def last_error():
+    return lib().pros_last_error().decode()
+
+
+def check(status, allow=()):
+    if status != PROS_OK and status not in allow:
+        raise ProstError(status, last_error())
+    return status
+
+
+def __getattr__(name):
+    if name in _SIGS:
+        return getattr(lib(), name)
+    raise AttributeError(name)

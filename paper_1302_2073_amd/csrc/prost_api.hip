@@ -1,0 +1,513 @@
+// C ABI of the pROST per-frame hot path: handle management, state exchange,
+// launch of the persistent frame kernel.  No torch types cross this boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/prost.h"
+#include "prost_frame.hpp"
+#include "prost_kernels.hpp"
+#include "prost_host.hpp"
+
+using prost::FrameArgs;
+
+namespace {
+thread_local char g_last_error[512] = "";
+}  // namespace
+
+pros_status prost_host::set_error(pros_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define fail prost_host::set_error
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      return fail(PROS_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                                \
+    }                                                                                 \
+  } while (0)
+
+
+
+namespace prost_host {
+
+double effective_delta(const pros_params& p) {
+  if (p.delta > 0.0) return p.delta;
+  if (p.cost == PROS_COST_LOG) return std::sqrt(p.mu);
+  return std::sqrt(p.mu / (1.0 - p.p));
+}
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_to_f32(uint16_t b) {
+  uint32_t u = ((uint32_t)b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+}  // namespace prost_host
+
+using namespace prost_host;
+
+extern "C" {
+
+const char* pros_strerror(pros_status s) {
+  switch (s) {
+    case PROS_OK: return "ok";
+    case PROS_EINVAL: return "invalid argument";
+    case PROS_ENOMEM: return "out of memory";
+    case PROS_EHIP: return "HIP runtime error";
+    case PROS_ESTATE: return "invalid handle state";
+    case PROS_EBADFRAME: return "frame contains NaN or Inf";
+    case PROS_ETIMEOUT: return "persistent kernel timed out";
+    case PROS_EUNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* pros_last_error(void) { return g_last_error; }
+
+pros_status pros_params_default(pros_params* out, int32_t width, int32_t height, int32_t channels) {
+  if (!out) return fail(PROS_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->width = width;
+  out->height = height;
+  out->channels = channels;
+  out->k = 15;
+  out->cg_iters = 5;
+  out->cost = PROS_COST_LP;
+  out->p = 0.25;
+  out->mu = 1e-3;
+  out->delta = 0.0;
+  out->omega = 5e-5;
+  out->t_init = 5e-3;
+  out->t_min = 1e-4;
+  out->i_init = 100;
+  out->storage = PROS_F32;
+  out->reorth_every = 0;
+  out->labels_after_update = 1;
+  out->weights_from_filtered = 0;
+  return PROS_OK;
+}
+
+pros_status pros_validate(const pros_params* p) {
+  if (!p) return fail(PROS_EINVAL, "params is NULL");
+  if (p->width <= 0 || p->height <= 0) return fail(PROS_EINVAL, "width/height must be positive");
+  if (p->channels < 1 || p->channels > 4) return fail(PROS_EINVAL, "channels must be 1..4");
+  const long long P = (long long)p->width * p->height;
+  if (P * p->channels > (1LL << 30)) return fail(PROS_EINVAL, "frame too large");
+  if (p->k < 1 || p->k > PROS_MAX_K) return fail(PROS_EINVAL, "k must be 1..%d", PROS_MAX_K);
+  if (p->k > P * p->channels) return fail(PROS_EINVAL, "k exceeds the frame size");
+  if (p->cg_iters < 1 || p->cg_iters > PROS_MAX_CG) return fail(PROS_EINVAL, "cg_iters must be 1..%d", PROS_MAX_CG);
+  if (p->cost != PROS_COST_LP && p->cost != PROS_COST_LOG) return fail(PROS_EINVAL, "unknown cost");
+  if (p->cost == PROS_COST_LP && !(p->p > 0.0 && p->p <= 2.0)) return fail(PROS_EINVAL, "p must be in (0, 2]");
+  if (!(p->mu > 0.0) || !std::isfinite(p->mu)) return fail(PROS_EINVAL, "mu must be > 0");
+  if (p->cost == PROS_COST_LP && p->delta <= 0.0 && !(p->p < 1.0))
+    return fail(PROS_EINVAL, "delta from mu needs p < 1");
+  if (!std::isfinite(p->delta)) return fail(PROS_EINVAL, "delta must be finite");
+  if (!(p->omega >= 0.0 && p->omega <= 1.0)) return fail(PROS_EINVAL, "omega must be in [0, 1]");
+  if (!(p->t_init > 0.0) || !(p->t_min > 0.0) || !std::isfinite(p->t_init) || !std::isfinite(p->t_min))
+    return fail(PROS_EINVAL, "t_init and t_min must be > 0");
+  if (p->i_init < 1) return fail(PROS_EINVAL, "i_init must be >= 1");
+  if (p->storage != PROS_F32 && p->storage != PROS_BF16) return fail(PROS_EINVAL, "unknown storage type");
+  if (p->reorth_every < 0) return fail(PROS_EINVAL, "reorth_every must be >= 0");
+  if (p->labels_after_update != 0 && p->labels_after_update != 1) return fail(PROS_EINVAL, "labels_after_update must be 0/1");
+  if (p->weights_from_filtered != 0 && p->weights_from_filtered != 1) return fail(PROS_EINVAL, "weights_from_filtered must be 0/1");
+  if (p->reserved != 0) return fail(PROS_EINVAL, "reserved must be 0");
+  return PROS_OK;
+}
+
+static void free_handle(pros_handle* h) {
+  if (!h) return;
+  void* ptrs[] = {h->U, h->xstage, h->lab, h->mask, h->y, h->nframe, h->stats, h->part, h->sync, h->reorth_ws};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete h;
+}
+
+// Pick the register rows per thread NR: the smallest NR whose gang fits in
+// two workgroups per CU, else the smallest that fits the device at all.
+static pros_status choose_launch(pros_handle* h, int force_nr) {
+  const int nrs[] = {1, 2, 4, 8, 16};
+  const void* best = nullptr;
+  int bestNR = 0, bestG = 0, bestT = 0;
+  for (int NR : nrs) {
+    if (force_nr > 0 && NR != force_nr) continue;
+    const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR)
+                                                  : prost::frame_kernel_f32(h->k, NR);
+    if (!f) continue;
+    const int tpw = (prost::kBlock * NR) / h->C;
+    if (tpw < 1) continue;
+    const long long G = (h->P + tpw - 1) / tpw;
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0));
+    const long long cap = (long long)occ * h->num_cu;
+    if (G > cap) continue;
+    best = f; bestNR = NR; bestG = (int)G; bestT = tpw;
+    if (force_nr > 0 || G <= 2LL * h->num_cu) break;
+  }
+  if (!best)
+    return fail(PROS_EUNSUPPORTED, "frame of %d pixels x %d channels at k=%d does not fit the device's resident workgroups",
+                h->P, h->C, h->k);
+  h->kfn = best;
+  h->NR = bestNR;
+  h->G = bestG;
+  h->tpw = bestT;
+  return PROS_OK;
+}
+
+pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out) {
+  if (!out) return fail(PROS_EINVAL, "out is NULL");
+  *out = nullptr;
+  pros_status st = pros_validate(prm);
+  if (st != PROS_OK) return st;
+  pros_handle* h = new pros_handle();
+  h->prm = *prm;
+  h->P = prm->width * prm->height;
+  h->C = prm->channels;
+  h->m = h->P * h->C;
+  h->k = prm->k;
+  h->ldU = ((long long)h->m + 63) / 64 * 64;
+  h->stream = (hipStream_t)hip_stream;
+  auto bail = [&](pros_status s) { free_handle(h); return s; };
+#define INIT_TRY(expr)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      pros_status s_ = (e_ == hipErrorOutOfMemory) ? PROS_ENOMEM : PROS_EHIP;             \
+      fail(s_, "%s failed: %s", #expr, hipGetErrorString(e_));                            \
+      return bail(s_);                                                                    \
+    }                                                                                     \
+  } while (0)
+  INIT_TRY(hipGetDevice(&h->device));
+  INIT_TRY(hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+  int wclk_khz = 0;
+  INIT_TRY(hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, h->device));
+  if (wclk_khz <= 0) wclk_khz = 100000;
+  h->timeout_ticks = (long long)wclk_khz * 1000LL * 2;  // 2 s per barrier wait
+  st = choose_launch(h, 0);
+  if (st != PROS_OK) return bail(st);
+  const size_t es = (prm->storage == PROS_BF16) ? 2 : 4;
+  INIT_TRY(hipMalloc(&h->U, es * (size_t)h->ldU * h->k));
+  INIT_TRY(hipMalloc(&h->xstage, es * (size_t)h->m));
+  INIT_TRY(hipMalloc((void**)&h->lab, (size_t)h->P));
+  INIT_TRY(hipMalloc((void**)&h->mask, (size_t)h->P));
+  INIT_TRY(hipMalloc((void**)&h->y, sizeof(double) * PROS_MAX_K));
+  INIT_TRY(hipMalloc((void**)&h->nframe, sizeof(long long)));
+  INIT_TRY(hipMalloc((void**)&h->stats, sizeof(pros_stats)));
+  INIT_TRY(hipMalloc((void**)&h->part, sizeof(double) * 2 * (size_t)h->G * prost::kSlot));
+  INIT_TRY(hipMalloc((void**)&h->sync, 64));
+  INIT_TRY(hipMemsetAsync(h->U, 0, es * (size_t)h->ldU * h->k, h->stream));
+  INIT_TRY(hipMemsetAsync(h->lab, 0, (size_t)h->P, h->stream));
+  INIT_TRY(hipMemsetAsync(h->mask, 0, (size_t)h->P, h->stream));
+  INIT_TRY(hipMemsetAsync(h->y, 0, sizeof(double) * PROS_MAX_K, h->stream));
+  INIT_TRY(hipMemsetAsync(h->nframe, 0, sizeof(long long), h->stream));
+  INIT_TRY(hipMemsetAsync(h->stats, 0, sizeof(pros_stats), h->stream));
+  INIT_TRY(hipMemsetAsync(h->sync, 0, 64, h->stream));
+  INIT_TRY(hipStreamSynchronize(h->stream));
+#undef INIT_TRY
+  *out = h;
+  return PROS_OK;
+}
+
+void pros_destroy(pros_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  free_handle(h);
+}
+
+static pros_status check_usable(pros_handle* h) {
+  if (!h) return fail(PROS_EINVAL, "handle is NULL");
+  if (h->broken) return fail(h->broken_status, "handle unusable after an earlier error");
+  return PROS_OK;
+}
+
+// Synchronise and fold device-side error bits into a status.
+static pros_status sync_and_check(pros_handle* h) {
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    h->broken = true;
+    h->broken_status = PROS_EHIP;
+    return fail(PROS_EHIP, "stream synchronisation failed: %s", hipGetErrorString(e));
+  }
+  unsigned bits[3] = {0, 0, 0};
+  e = hipMemcpy(bits, h->sync, sizeof(bits), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    h->broken = true;
+    h->broken_status = PROS_EHIP;
+    return fail(PROS_EHIP, "reading the error word failed: %s", hipGetErrorString(e));
+  }
+  if (bits[2] & prost::kErrTimeout) {
+    h->broken = true;
+    h->broken_status = PROS_ETIMEOUT;
+    return fail(PROS_ETIMEOUT, "a frame kernel timed out waiting for its workgroups");
+  }
+  if (bits[2] & prost::kErrBadFrame) {
+    unsigned zero = 0;
+    e = hipMemcpy(h->sync + 2, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      h->broken = true;
+      h->broken_status = PROS_EHIP;
+      return fail(PROS_EHIP, "clearing the error word failed: %s", hipGetErrorString(e));
+    }
+    return fail(PROS_EBADFRAME, "a frame with a non-finite entry was rejected");
+  }
+  return PROS_OK;
+}
+
+pros_status pros_sync(pros_handle* h) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  return sync_and_check(h);
+}
+
+pros_status pros_set_state(pros_handle* h, const double* U, const double* y, const uint8_t* labels, int64_t n) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (!U) return fail(PROS_EINVAL, "U is NULL");
+  if (n < 0) return fail(PROS_EINVAL, "n must be >= 0");
+  for (long long i = 0; i < (long long)h->m * h->k; ++i)
+    if (!std::isfinite(U[i])) return fail(PROS_EINVAL, "U has a non-finite entry");
+  if (y)
+    for (int j = 0; j < h->k; ++j)
+      if (!std::isfinite(y[j])) return fail(PROS_EINVAL, "y has a non-finite entry");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const bool bf = h->prm.storage == PROS_BF16;
+  const size_t es = bf ? 2 : 4;
+  std::vector<unsigned char> buf(es * (size_t)h->ldU * h->k, 0);
+  for (int j = 0; j < h->k; ++j) {
+    for (int e = 0; e < h->m; ++e) {
+      const float v = (float)U[(size_t)j * h->m + e];
+      const size_t o = (size_t)j * h->ldU + e;
+      if (bf) {
+        const uint16_t b = bf16_rne(v);
+        std::memcpy(&buf[o * 2], &b, 2);
+      } else {
+        std::memcpy(&buf[o * 4], &v, 4);
+      }
+    }
+  }
+  HIP_TRY(hipMemcpy(h->U, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  double yv[PROS_MAX_K] = {0};
+  if (y)
+    for (int j = 0; j < h->k; ++j) yv[j] = y[j];
+  HIP_TRY(hipMemcpy(h->y, yv, sizeof(yv), hipMemcpyHostToDevice));
+  if (labels) {
+    std::vector<uint8_t> l(labels, labels + h->P);
+    for (auto& v : l) v = v ? 1 : 0;
+    HIP_TRY(hipMemcpy(h->lab, l.data(), (size_t)h->P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->mask, l.data(), (size_t)h->P, hipMemcpyHostToDevice));
+  } else {
+    HIP_TRY(hipMemset(h->lab, 0, (size_t)h->P));
+    HIP_TRY(hipMemset(h->mask, 0, (size_t)h->P));
+  }
+  long long nn = n;
+  HIP_TRY(hipMemcpy(h->nframe, &nn, sizeof(nn), hipMemcpyHostToDevice));
+  HIP_TRY(hipDeviceSynchronize());
+  h->submitted = n;
+  h->state_set = true;
+  return PROS_OK;
+}
+
+pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_t* labels, int64_t* n) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  st = sync_and_check(h);
+  if (st != PROS_OK && st != PROS_EBADFRAME) return st;
+  pros_status pending = st;
+  const bool bf = h->prm.storage == PROS_BF16;
+  if (U) {
+    const size_t es = bf ? 2 : 4;
+    std::vector<unsigned char> buf(es * (size_t)h->ldU * h->k);
+    HIP_TRY(hipMemcpy(buf.data(), h->U, buf.size(), hipMemcpyDeviceToHost));
+    for (int j = 0; j < h->k; ++j)
+      for (int e = 0; e < h->m; ++e) {
+        const size_t o = (size_t)j * h->ldU + e;
+        double v;
+        if (bf) {
+          uint16_t b;
+          std::memcpy(&b, &buf[o * 2], 2);
+          v = bf16_to_f32(b);
+        } else {
+          float f;
+          std::memcpy(&f, &buf[o * 4], 4);
+          v = f;
+        }
+        U[(size_t)j * h->m + e] = v;
+      }
+  }
+  if (y) {
+    double yv[PROS_MAX_K];
+    HIP_TRY(hipMemcpy(yv, h->y, sizeof(yv), hipMemcpyDeviceToHost));
+    for (int j = 0; j < h->k; ++j) y[j] = yv[j];
+  }
+  if (labels) HIP_TRY(hipMemcpy(labels, h->lab, (size_t)h->P, hipMemcpyDeviceToHost));
+  if (n) {
+    long long nn;
+    HIP_TRY(hipMemcpy(&nn, h->nframe, sizeof(nn), hipMemcpyDeviceToHost));
+    *n = nn;
+  }
+  return pending;
+}
+
+static FrameArgs make_args(pros_handle* h, const void* x) {
+  FrameArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const pros_params& p = h->prm;
+  a.U = h->U;
+  a.x = x;
+  a.lab = h->lab;
+  a.mask = h->mask;
+  a.y = h->y;
+  a.nframe = h->nframe;
+  a.stats = h->stats;
+  a.part = h->part;
+  a.sync = h->sync;
+  a.ldU = h->ldU;
+  a.m = h->m;
+  a.P = h->P;
+  a.C = h->C;
+  a.W = p.width;
+  a.H = p.height;
+  a.k = h->k;
+  a.G = h->G;
+  a.tpw = h->tpw;
+  a.cp.form = (p.cost == PROS_COST_LOG) ? 1 : 0;
+  a.cp.p = (float)p.p;
+  a.cp.half_p = (float)(0.5 * p.p);
+  a.cp.mu = (float)p.mu;
+  a.cp.inv_mu = (float)(1.0 / p.mu);
+  a.delta = (float)effective_delta(p);
+  a.omega = (float)p.omega;
+  a.t_init = p.t_init;
+  a.t_min = p.t_min;
+  a.tau = -std::log(p.t_min / p.t_init) / (double)p.i_init;
+  a.J = p.cg_iters;
+  a.labels_after_update = p.labels_after_update;
+  a.weights_from_filtered = p.weights_from_filtered;
+  a.timeout = h->timeout_ticks;
+  return a;
+}
+
+
+pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (!frame) return fail(PROS_EINVAL, "frame is NULL");
+  if (dtype != PROS_F32 && dtype != PROS_BF16) return fail(PROS_EINVAL, "unknown frame dtype");
+  if (!h->state_set) return fail(PROS_ESTATE, "set U with pros_set_state before the first frame");
+  const void* x = frame;
+  if (on_device) {
+    if (dtype != h->prm.storage) return fail(PROS_EINVAL, "device frames must have the storage dtype");
+  } else {
+    const bool bf = h->prm.storage == PROS_BF16;
+    const size_t es = bf ? 2 : 4;
+    std::vector<unsigned char> tmp;
+    const void* src = frame;
+    if (dtype == PROS_F32) {
+      const float* f = (const float*)frame;
+      for (int e = 0; e < h->m; ++e)
+        if (!std::isfinite(f[e])) return fail(PROS_EBADFRAME, "frame entry %d is not finite", e);
+      if (bf) {
+        tmp.resize(es * h->m);
+        for (int e = 0; e < h->m; ++e) {
+          const uint16_t b = bf16_rne(f[e]);
+          std::memcpy(&tmp[(size_t)e * 2], &b, 2);
+        }
+        src = tmp.data();
+      }
+    } else {
+      const uint16_t* b = (const uint16_t*)frame;
+      for (int e = 0; e < h->m; ++e)
+        if ((b[e] & 0x7f80u) == 0x7f80u) return fail(PROS_EBADFRAME, "frame entry %d is not finite", e);
+      if (!bf) {
+        tmp.resize(es * h->m);
+        for (int e = 0; e < h->m; ++e) {
+          const float f = bf16_to_f32(b[e]);
+          std::memcpy(&tmp[(size_t)e * 4], &f, 4);
+        }
+        src = tmp.data();
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(h->xstage, src, es * (size_t)h->m, hipMemcpyHostToDevice, h->stream));
+    if (!tmp.empty()) HIP_TRY(hipStreamSynchronize(h->stream));
+    x = h->xstage;
+  }
+  FrameArgs a = make_args(h, x);
+  void* args[] = {&a};
+  hipError_t e = hipLaunchCooperativeKernel(h->kfn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream);
+  if (e != hipSuccess) {
+    h->broken = true;
+    h->broken_status = PROS_EHIP;
+    return fail(PROS_EHIP, "frame kernel launch failed: %s", hipGetErrorString(e));
+  }
+  ++h->submitted;
+  if (h->prm.reorth_every > 0 && h->submitted % h->prm.reorth_every == 0) {
+    st = prost_reorth_launch(h);
+    if (st != PROS_OK) return st;
+  }
+  return PROS_OK;
+}
+
+pros_status pros_get_mask(pros_handle* h, uint8_t* out, int32_t filtered, int32_t on_device) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (!out) return fail(PROS_EINVAL, "out is NULL");
+  const uint8_t* src = filtered ? h->mask : h->lab;
+  if (on_device) {
+    HIP_TRY(hipMemcpyAsync(out, src, (size_t)h->P, hipMemcpyDeviceToDevice, h->stream));
+    return PROS_OK;
+  }
+  st = sync_and_check(h);
+  if (st != PROS_OK && st != PROS_EBADFRAME) return st;
+  HIP_TRY(hipMemcpy(out, src, (size_t)h->P, hipMemcpyDeviceToHost));
+  return st;
+}
+
+pros_status pros_get_stats(pros_handle* h, pros_stats* out) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (!out) return fail(PROS_EINVAL, "out is NULL");
+  st = sync_and_check(h);
+  if (st != PROS_OK && st != PROS_EBADFRAME) return st;
+  HIP_TRY(hipMemcpy(out, h->stats, sizeof(pros_stats), hipMemcpyDeviceToHost));
+  return st;
+}
+
+pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
+  if (!h || !out) return fail(PROS_EINVAL, "NULL argument");
+  out->workgroups = h->G;
+  out->threads = prost::kBlock;
+  out->rows_per_thread = h->NR;
+  out->pixels_per_wg = h->tpw;
+  out->barriers_per_frame = 2 * h->prm.cg_iters + 2;
+  out->reserved = 0;
+  return PROS_OK;
+}
+
+pros_status pros_reorthonormalize(pros_handle* h) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  return prost_reorth_launch(h);
+}
+
+}  // extern "C"

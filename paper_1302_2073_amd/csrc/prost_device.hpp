@@ -1,0 +1,115 @@
+// Device-side building blocks of the pROST frame kernels (gfx950).
+//
+// * storage conversions (float32 / bfloat16 with round-to-nearest-even),
+// * the per-entry cost functor phi and its majoriser weight c = phi'/r
+//   (Sec. 3.1, eqs. smoothlpnorm / weightedLPnorm),
+// * deterministic wave / workgroup / gang reductions,
+// * the gang barrier used by the persistent frame kernel: one atomic arrival
+//   per workgroup on a monotone counter, bounded spin, error word.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace prost {
+
+constexpr int kBlock = 256;            // threads per workgroup
+constexpr int kWaves = kBlock / 64;    // wavefronts per workgroup
+constexpr int kMaxK = 16;
+constexpr int kSlot = 32;              // doubles per workgroup partial slot
+
+// error bits in sync[2]
+constexpr unsigned kErrTimeout = 1u;
+constexpr unsigned kErrBadFrame = 2u;
+
+// ---------------------------------------------------------------------------
+// storage
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ld_elem(const float* p, long long i) { return p[i]; }
+__device__ __forceinline__ float ld_elem(const uint16_t* p, long long i) {
+  return __uint_as_float(((uint32_t)p[i]) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ void st_elem(float* p, long long i, float v) { p[i] = v; }
+__device__ __forceinline__ void st_elem(uint16_t* p, long long i, float v) { p[i] = f32_to_bf16_rne(v); }
+
+// ---------------------------------------------------------------------------
+// cost functor
+// ---------------------------------------------------------------------------
+struct CostParams {
+  float p;        // lp exponent
+  float half_p;   // p / 2
+  float mu;       // smoothing
+  float inv_mu;   // 1 / mu
+  int form;       // 0: (r^2+mu)^(p/2), 1: log(1 + r^2/mu)
+};
+
+// phi(r) and c(r) = phi'(r)/r.  lp: phi = s^(p/2), c = p s^(p/2-1) with
+// s = r^2 + mu.  log: phi = log(1 + r^2/mu), c = 2/s.
+__device__ __forceinline__ void cost_eval(float r, const CostParams& cp, float& phi, float& c) {
+  const float s = fmaf(r, r, cp.mu);
+  const float inv_s = __builtin_amdgcn_rcpf(s);
+  if (cp.form == 0) {
+    const float ph = __builtin_amdgcn_exp2f(cp.half_p * __builtin_amdgcn_logf(s));
+    phi = ph;
+    c = cp.p * ph * inv_s;
+  } else {
+    phi = 0.69314718055994531f * __builtin_amdgcn_logf(fmaf(r * r, cp.inv_mu, 1.0f));
+    c = 2.0f * inv_s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions (fixed order: identical results in every workgroup and run)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ long long now_ticks() { return wall_clock64(); }
+
+// Gang barrier.  Every workgroup of the gang calls it the same number of
+// times; `target` = base + G * (index of this barrier + 1).  Thread 0 makes
+// the workgroup's prior global writes visible at device scope, arrives, and
+// spins (bounded by `timeout` wall-clock ticks, also leaving early when an
+// error bit is set).  Returns false in every thread when the gang must abort.
+__device__ __forceinline__ bool gang_barrier(unsigned* sync, unsigned target, long long timeout,
+                                             int* s_ctl) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = now_ticks();
+    int ok = 1;
+    unsigned spins = 0;
+    while ((int)(__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 63u) == 0) {
+        if (__hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout) { ok = 0; break; }
+        if (now_ticks() - t0 > timeout) {
+          __hip_atomic_fetch_or(&sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ctl[0] = ok;
+  }
+  __syncthreads();
+  return s_ctl[0] != 0;
+}
+
+}  // namespace prost

@@ -1,0 +1,382 @@
+// Persistent per-frame kernel of pROST (Sec. 3.3, Steps 1-3, plus the 3x3
+// median of Sec. 3.4) for one video stream.
+//
+// One launch processes one frame.  The m x k subspace U is split into
+// workgroup tiles of `tpw` pixels (all colour entries of a pixel stay in one
+// tile); each thread keeps up to NR rows of U (K floats each) in registers for
+// the whole frame, so U is read from HBM once and written once per frame.
+// The frame's sequence of dependent reductions runs as gang-wide reductions
+// between all workgroups of the launch (cooperative launch, so all of them
+// are resident):
+//   for each CG step j:  A: g = -U^T(w phi'(r)), f = sum w phi(r)
+//                        B: d^T H d = sum w c(r) (u.d)^2
+//   eta pass:            a = U^T eta, ||eta||^2, f at the final y
+//   labels:              barrier so the median sees all labels
+// Every workgroup reduces the published partials in the same fixed order, so
+// all of them hold bit-identical k-vectors without a broadcast step.
+#pragma once
+
+#include "prost_device.hpp"
+#include "../../include/prost.h"
+
+namespace prost {
+
+struct FrameArgs {
+  void* U;               // K planes of ldU entries (storage type)
+  const void* x;         // frame, m entries (storage type)
+  uint8_t* lab;          // raw labels, P bytes (read: previous frame, write: this frame)
+  uint8_t* mask;         // median-filtered mask, P bytes
+  double* y;             // k coefficients (float64 state)
+  long long* nframe;     // frame counter
+  pros_stats* stats;     // statistics of the frame
+  double* part;          // 2 * G * kSlot doubles of workgroup partials
+  unsigned* sync;        // [0] arrival counter, [1] counter base, [2] error bits
+  long long ldU;
+  int m, P, C, W, H, k;
+  int G, tpw;
+  CostParams cp;
+  float delta, omega;
+  double t_init, t_min, tau;
+  int J;
+  int labels_after_update;
+  int weights_from_filtered;
+  long long timeout;     // wall-clock ticks a barrier may wait
+};
+
+// Workgroup + gang reduction of L float partials held by every thread.
+// Result (float64, identical in every workgroup) lands in s_out[0..L).
+template <int L>
+__device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameArgs& a, int& nbar,
+                                            unsigned base, double (*s_red)[kSlot], double* s_out,
+                                            int* s_ctl) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  // 1. per wave
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const float v = wave_sum(acc[i]);
+    if (lane == 0) s_red[wv][i] = (double)v;
+  }
+  __syncthreads();
+  double* slot = a.part + ((size_t)(nbar & 1) * a.G + blockIdx.x) * kSlot;
+  if (threadIdx.x < L) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) v += s_red[q][threadIdx.x];
+    __hip_atomic_store(&slot[threadIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // 2. gang barrier
+  ++nbar;
+  if (!gang_barrier(a.sync, base + (unsigned)a.G * (unsigned)nbar, a.timeout, s_ctl)) return false;
+  // 3. every workgroup sums all partials in the same order
+  const double* buf = a.part + (size_t)((nbar - 1) & 1) * a.G * kSlot;
+  double t[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) t[i] = 0.0;
+  for (int w = threadIdx.x; w < a.G; w += kBlock) {
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+      t[i] += __hip_atomic_load(&buf[(size_t)w * kSlot + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const double v = wave_sum(t[i]);
+    if (lane == 0) s_red[wv][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < L) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) v += s_red[q][threadIdx.x];
+    s_out[threadIdx.x] = v;
+  }
+  __syncthreads();
+  return true;
+}
+
+// Shared k-space state of one workgroup (all float64 unless noted).
+template <int K>
+struct KSpace {
+  double y[K];
+  double d[K];
+  double gp[K];     // previous gradient
+  double dp[K];     // previous direction
+  double a[K];      // U^T eta
+  double red[kSlot];
+  double gd;        // g . d of the current step
+  float df[K];      // direction (float) for the row passes
+  float vf[K];      // v = y/||y||
+  float af[K];      // a (float)
+  float yf[K];
+  float scal[8];    // row-pass scalars
+  int flag[4];      // [0] stop CG, [1] bad frame, [2] do update
+};
+
+template <int K, int NR, typename TS>
+__global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
+  __shared__ KSpace<K> ks;
+  __shared__ double s_red[kWaves][kSlot];
+  __shared__ int s_ctl[4];
+  __shared__ uint8_t s_flag[kBlock * NR];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int p0 = blockIdx.x * a.tpw;
+  const int npx = min(a.tpw, a.P - p0);
+  const int nq = npx * a.C;
+  const unsigned base = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int nbar = 0;
+  const long long n = *a.nframe;
+  const bool lead = (blockIdx.x == 0);
+
+  if (tid < K) {
+    const double yv = a.y[tid];
+    ks.y[tid] = yv;
+    ks.yf[tid] = (float)yv;
+  }
+  if (tid < 4) ks.flag[tid] = 0;
+  __syncthreads();
+
+  // ---- load the register tile: U rows, residual r = x - U y, weights ----
+  const TS* __restrict__ Ug = (const TS*)a.U;
+  const TS* __restrict__ xg = (const TS*)a.x;
+  const uint8_t* __restrict__ wsrc = a.weights_from_filtered ? a.mask : a.lab;
+  float u[NR][K];
+  float r[NR], wt[NR], cw[NR], ud[NR];
+  int eix[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int q = tid + s * kBlock;
+    eix[s] = -1;
+    wt[s] = 0.f;
+    r[s] = 0.f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) u[s][j] = 0.f;
+    if (q < nq) {
+      const int c = q / npx;
+      const int pl = q - c * npx;
+      const int e = c * a.P + p0 + pl;
+      eix[s] = e;
+      wt[s] = wsrc[p0 + pl] ? a.omega : 1.0f;
+      float acc = ld_elem(xg, e);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        u[s][j] = ld_elem(Ug, (long long)j * a.ldU + e);
+        acc = fmaf(-u[s][j], ks.yf[j], acc);
+      }
+      r[s] = acc;
+    }
+  }
+
+  // ---- Step 1: CG on y ----
+  int steps = 0, restarts = 0;
+  for (int it = 0; it < a.J; ++it) {
+    // phase A: gradient and cost at the current y
+    float acc[K + 1];
+#pragma unroll
+    for (int j = 0; j <= K; ++j) acc[j] = 0.f;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      float phi, c;
+      cost_eval(r[s], a.cp, phi, c);
+      const float wc = wt[s] * c;
+      cw[s] = wc;
+      const float wd = wc * r[s];          // w phi'(r)
+      acc[K] = fmaf(wt[s], phi, acc[K]);
+#pragma unroll
+      for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, u[s][j], acc[j]);
+    }
+    if (!gang_reduce<K + 1>(acc, a, nbar, base, s_red, ks.red, s_ctl)) return;
+    // k-space: PR+ direction (wave 0, lane j owns component j)
+    if (tid < 64) {
+      const double g = (lane < K) ? -ks.red[lane] : 0.0;
+      const double f = ks.red[K];
+      const double gg = wave_sum(g * g);
+      int stop = 0;
+      if (it == 0 && !(isfinite(f) && isfinite(gg))) {
+        stop = 1;
+        if (lane == 0) ks.flag[1] = 1;
+      }
+      if (gg == 0.0) stop = 1;
+      if (lead && lane == 0) a.stats->f[it] = f;
+      double beta = 0.0, dj = -g;
+      if (!stop && it > 0) {
+        const double gp = (lane < K) ? ks.gp[lane] : 0.0;
+        const double num = wave_sum(g * (g - gp));
+        const double den = wave_sum(gp * gp);
+        beta = fmax(0.0, num / den);
+        const double dpv = (lane < K) ? ks.dp[lane] : 0.0;
+        dj = -g + beta * dpv;
+        const double gdv = wave_sum(g * dj);
+        if (gdv >= 0.0) {
+          dj = -g;
+          if (lane == 0) ++restarts;
+        }
+      }
+      const double gd = wave_sum(g * dj);
+      if (lane < K) {
+        ks.d[lane] = dj;
+        ks.df[lane] = (float)dj;
+        ks.gp[lane] = g;
+      }
+      if (lane == 0) {
+        ks.gd = gd;
+        ks.flag[0] = stop;
+        if (lead) a.stats->beta[it] = beta;
+      }
+    }
+    __syncthreads();
+    if (ks.flag[0]) break;
+    // phase B: curvature of the majoriser along d
+    float accb[1] = {0.f};
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      float t = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j) t = fmaf(u[s][j], ks.df[j], t);
+      ud[s] = t;
+      accb[0] = fmaf(cw[s] * t, t, accb[0]);
+    }
+    if (!gang_reduce<1>(accb, a, nbar, base, s_red, ks.red, s_ctl)) return;
+    const double dHd = ks.red[0];
+    if (!(dHd > 0.0)) break;   // same decision in every workgroup
+    const double alpha = -ks.gd / dHd;
+    __syncthreads();
+    if (tid < K) {
+      ks.y[tid] += alpha * ks.d[tid];
+      ks.dp[tid] = ks.d[tid];
+    }
+    if (lead && tid == 0) a.stats->alpha[it] = alpha;
+    const float af = (float)alpha;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) r[s] = fmaf(-af, ud[s], r[s]);
+    ++steps;
+    __syncthreads();
+  }
+  const bool bad = ks.flag[1] != 0;
+
+  // ---- Step 2: eta pass (a = U^T eta, ||eta||^2, final cost) ----
+  float acce[K + 2];
+#pragma unroll
+  for (int j = 0; j < K + 2; ++j) acce[j] = 0.f;
+  if (!bad) {
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      float phi, c;
+      cost_eval(r[s], a.cp, phi, c);
+      const float eta = -wt[s] * c * r[s];
+      cw[s] = eta;
+      acce[K] = fmaf(eta, eta, acce[K]);
+      acce[K + 1] = fmaf(wt[s], phi, acce[K + 1]);
+#pragma unroll
+      for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, u[s][j], acce[j]);
+    }
+    if (!gang_reduce<K + 2>(acce, a, nbar, base, s_red, ks.red, s_ctl)) return;
+    if (tid < 64) {
+      const double av = (lane < K) ? ks.red[lane] : 0.0;
+      const double yv = (lane < K) ? ks.y[lane] : 0.0;
+      const double aa = wave_sum(av * av);
+      const double yy = wave_sum(yv * yv);
+      const double ee = ks.red[K];
+      const double zeta = sqrt(fmax(ee - aa, 0.0));
+      const double nu = sqrt(yy);
+      const double sigma = zeta * nu;
+      const double t = fmax(exp(-a.tau * (double)n) * a.t_init, a.t_min);
+      const double theta = sigma * t;
+      const int upd = (zeta > 0.0 && nu > 0.0) ? 1 : 0;
+      if (lane < K) {
+        ks.af[lane] = (float)av;
+        ks.vf[lane] = upd ? (float)(yv / nu) : 0.f;
+        ks.yf[lane] = (float)yv;
+      }
+      if (lane == 0) {
+        const double sh = sin(0.5 * theta);
+        ks.scal[0] = upd ? (float)(-2.0 * sh * sh) : 0.f;          // cos(theta) - 1
+        ks.scal[1] = upd ? (float)(sin(theta) / zeta) : 0.f;       // sin(theta) / zeta
+        ks.scal[2] = (float)nu;
+        ks.flag[2] = upd;
+        if (lead) {
+          a.stats->f[steps] = ks.red[K + 1];
+          a.stats->t = t;
+          a.stats->sigma = sigma;
+          a.stats->theta = theta;
+          a.stats->zeta = zeta;
+          a.stats->nu = nu;
+          a.stats->updated = upd;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- Step 2 update + Step 3 labels, one pass over the register tile ----
+    TS* __restrict__ Uw = (TS*)a.U;
+    const float cm1 = ks.scal[0], sz = ks.scal[1], nu_f = ks.scal[2];
+    const bool upd = ks.flag[2] != 0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int q = tid + s * kBlock;
+      if (eix[s] >= 0) {
+        float rl = r[s];
+        if (upd) {
+          float uv = 0.f, ua = 0.f;
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            uv = fmaf(u[s][j], ks.vf[j], uv);
+            ua = fmaf(u[s][j], ks.af[j], ua);
+          }
+          const float coef = fmaf(cm1, uv, -sz * (cw[s] - ua));
+#pragma unroll
+          for (int j = 0; j < K; ++j) st_elem((TS*)Uw, (long long)j * a.ldU + eix[s], fmaf(coef, ks.vf[j], u[s][j]));
+          if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
+        }
+        s_flag[q] = (fabsf(rl) >= a.delta) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    for (int pl = tid; pl < npx; pl += kBlock) {
+      uint8_t f = 0;
+      for (int c = 0; c < a.C; ++c) f |= s_flag[c * npx + pl];
+      a.lab[p0 + pl] = f;
+    }
+  }
+  // all label writes visible before the median reads its neighbours
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  ++nbar;
+  if (!gang_barrier(a.sync, base + (unsigned)a.G * (unsigned)nbar, a.timeout, s_ctl)) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+  if (!bad) {
+    // ---- 3x3 median of the labels (>= 5 of 9, edges replicated) ----
+    for (int pl = tid; pl < npx; pl += kBlock) {
+      const int pix = p0 + pl;
+      const int row = pix / a.W, col = pix - row * a.W;
+      const int r0 = max(row - 1, 0), r2 = min(row + 1, a.H - 1);
+      const int c0 = max(col - 1, 0), c2 = min(col + 1, a.W - 1);
+      int cnt = 0;
+      const int rows[3] = {r0, row, r2};
+      const int cols[3] = {c0, col, c2};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) cnt += a.lab[rows[i] * a.W + cols[j]];
+      a.mask[pix] = (cnt >= 5) ? 1 : 0;
+    }
+  }
+
+  if (lead && tid == 0) {
+    a.stats->frame = n;
+    a.stats->cg_steps = steps;
+    a.stats->restarts = restarts;
+    a.stats->bad_frame = bad ? 1 : 0;
+    if (bad) {
+      __hip_atomic_fetch_or(&a.sync[2], kErrBadFrame, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      *a.nframe = n + 1;
+    }
+    __hip_atomic_store(&a.sync[1], base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (lead && !bad && tid < K) a.y[tid] = ks.y[tid];
+}
+
+}  // namespace prost

@@ -1,0 +1,45 @@
+// Host-side definitions shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/prost.h"
+
+struct pros_handle {
+  pros_params prm;
+  int P = 0, C = 0, m = 0, k = 0;
+  long long ldU = 0;
+  int device = 0;
+  int num_cu = 0;
+  hipStream_t stream = nullptr;
+  // device memory
+  void* U = nullptr;
+  void* xstage = nullptr;
+  uint8_t* lab = nullptr;
+  uint8_t* mask = nullptr;
+  double* y = nullptr;
+  long long* nframe = nullptr;
+  pros_stats* stats = nullptr;
+  double* part = nullptr;
+  unsigned* sync = nullptr;
+  void* reorth_ws = nullptr;
+  // launch configuration
+  const void* kfn = nullptr;
+  int G = 0, tpw = 0, NR = 0;
+  long long timeout_ticks = 0;
+  // host bookkeeping
+  long long submitted = 0;
+  bool state_set = false;
+  bool broken = false;
+  pros_status broken_status = PROS_OK;
+};
+
+namespace prost_host {
+double effective_delta(const pros_params& p);
+uint16_t bf16_rne(float f);
+float bf16_to_f32(uint16_t b);
+pros_status set_error(pros_status s, const char* fmt, ...);
+}  // namespace prost_host
+
+extern "C" pros_status prost_reorth_launch(pros_handle* h);

@@ -1,0 +1,106 @@
+"""Shared helpers of the GPU parity tests: oracle trajectories on the same
+seeded inputs, state injection, comparison at the stated tolerances."""
+import functools
+import sys
+
+import numpy as np
+
+from oracle import prost_oracle as O
+from synth import video as V
+
+# Parity bar (per state-injected frame, float32 kernels vs the float64 oracle)
+TOL_Y = 1e-4          # ||y - y*|| / ||y*||
+TOL_U = 1e-4          # ||U - U*||_F / ||U*||_F
+GUARD = 1e-5          # labels compared exactly where | max_c |r'| - delta | > GUARD
+TOL_F = 1e-5          # cost values, relative
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def oracle_params(wl, **over):
+    v = wl.video
+    kw = dict(k=wl.k, mu=wl.mu, delta=wl.delta, cost=wl.cost)
+    kw.update(over)
+    return O.Params(v.width, v.height, v.channels, **kw)
+
+
+def tracker_kwargs(prm: O.Params, storage="f32"):
+    return dict(cg_iters=prm.cg_iters, cost=prm.cost, p=prm.p, mu=prm.mu, delta=prm.delta,
+                omega=prm.omega, t_init=prm.t_init, t_min=prm.t_min, i_init=prm.i_init,
+                storage=storage, labels_after_update=prm.labels_after_update,
+                weights_from_filtered=prm.weights_from_filtered)
+
+
+@functools.lru_cache(maxsize=8)
+def oracle_trajectory(name, upto, over_items=()):
+    """Oracle states before frames 0..upto of a named workload, on float32
+    frames (the kernels' input)."""
+    wl = WORKLOADS[name]()
+    prm = oracle_params(wl, **dict(over_items))
+    sv = V.SyntheticVideo(wl.video)
+    st = O.initial_state(V.initial_subspace(prm.m, prm.k, wl.video.seed), prm.P)
+    states = []
+    for n in range(upto + 1):
+        states.append(st.copy())
+        st, _ = O.track_frame(st, f32(sv.frame(n)), prm)
+    return wl, prm, sv, states
+
+
+WORKLOADS = {
+    "small_gray": V.small_gray,
+    "qvga_rgb": V.qvga_rgb,
+    "vga_rgb": V.vga_rgb,
+}
+
+
+def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
+    """Inject oracle state `st`, run one frame on the GPU and on the oracle
+    (from the state as rounded by the device), return a report dict."""
+    trk.set_state(st.U, st.y, st.labels, st.n)
+    U0, y0, l0, n0 = trk.get_state()
+    start = O.State(U0, y0, l0, l0.copy(), n0)
+    exp, info = O.track_frame(start, x64, prm)
+    if storage == "f32":
+        trk.track(x64.astype(np.float32))
+    else:
+        from paper_1302_2073_amd.tracker import bf16_bits
+        trk.track(bf16_bits(x64))
+    U1, y1, l1, n1 = trk.get_state()
+    mask = trk.mask(filtered=True)
+    stats = trk.stats()
+    U_lab = exp.U if prm.labels_after_update else start.U
+    band = O.band_pixels(U_lab, x64, exp.y, prm.thr, prm.channels, guard)
+    rep = dict(
+        n=n1, n_exp=exp.n,
+        y_rel=float(np.linalg.norm(y1 - exp.y) / max(np.linalg.norm(exp.y), 1e-300)),
+        U_rel=float(np.linalg.norm(U1 - exp.U) / np.linalg.norm(exp.U)),
+        lab_mismatch_outside_band=int(np.sum((l1 != exp.labels) & ~band)),
+        band=int(band.sum()),
+        lab_mismatch=int(np.sum(l1 != exp.labels)),
+        mask_vs_median_of_gpu_labels=int(np.sum(mask != O.median3x3(l1, prm.height, prm.width))),
+        f_rel=float(max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(stats["f"], info.cg.f))) if stats["f"] else 0.0,
+        theta_rel=float(abs(stats["theta"] - info.theta) / max(abs(info.theta), 1e-300)),
+        steps=(stats["cg_steps"], info.cg.iters),
+        U1=U1, exp=exp, info=info, stats=stats, y1=y1, labels=l1, mask=mask, start=start,
+    )
+    return rep
+
+
+def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U):
+    say(f"  n={rep['n']} y_rel={rep['y_rel']:.2e} U_rel={rep['U_rel']:.2e} band={rep['band']} "
+        f"lab_mism={rep['lab_mismatch']} outside={rep['lab_mismatch_outside_band']} "
+        f"f_rel={rep['f_rel']:.1e} theta_rel={rep['theta_rel']:.1e} steps={rep['steps']}")
+    assert rep["n"] == rep["n_exp"]
+    assert rep["steps"][0] == rep["steps"][1]
+    assert rep["y_rel"] <= tol_y
+    assert rep["U_rel"] <= tol_u
+    assert rep["lab_mismatch_outside_band"] == 0
+    assert rep["mask_vs_median_of_gpu_labels"] == 0
+    assert rep["f_rel"] <= TOL_F

@@ -1,0 +1,118 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point include/prost.h declares, and rejects bad arguments before any
+HIP call."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prost.h")
+LIBSO = os.path.join(ROOT, "paper_1302_2073_amd", "libprost.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pros_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _lib():
+    if not os.path.exists(LIBSO):
+        pytest.fail("libprost.so is not built (run __graft_entry__.build())")
+    from paper_1302_2073_amd import _lib as L
+    return L
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("pros_init", "pros_track_frame", "pros_get_mask", "pros_destroy",
+                     "pros_set_state", "pros_get_state", "pros_strerror"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", LIBSO], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (\w+)", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    L = _lib()
+    assert set(_declared()) <= set(L.exported_symbols())
+    for name in _declared():
+        assert getattr(L.lib(), name) is not None
+
+
+def test_struct_sizes_match_header():
+    L = _lib()
+    # pros_params: 6 int32 + 6 double + 6 int32 (with padding)
+    assert C.sizeof(L.pros_params) == 6 * 4 + 6 * 8 + 6 * 4
+    assert C.sizeof(L.pros_stats) == 8 + 4 * 4 + 8 * (17 + 16 + 16 + 5)
+
+
+def _default(L, w=32, h=24, c=3):
+    p = L.pros_params()
+    assert L.lib().pros_params_default(C.byref(p), w, h, c) == L.PROS_OK
+    return p
+
+
+def test_defaults_are_the_paper_parameters():
+    L = _lib()
+    p = _default(L)
+    assert (p.k, p.cg_iters, p.p, p.omega, p.t_init, p.t_min) == (15, 5, 0.25, 5e-5, 5e-3, 1e-4)
+    assert L.lib().pros_validate(C.byref(p)) == L.PROS_OK
+
+
+@pytest.mark.parametrize("field,value", [
+    ("width", 0), ("height", -1), ("channels", 0), ("channels", 5), ("k", 0), ("k", 17),
+    ("cg_iters", 0), ("cg_iters", 17), ("cost", 2), ("p", 0.0), ("p", 2.5), ("mu", 0.0),
+    ("mu", float("nan")), ("omega", -0.1), ("omega", 1.5), ("t_init", 0.0), ("t_min", -1.0),
+    ("i_init", 0), ("storage", 3), ("reorth_every", -1), ("labels_after_update", 2),
+    ("weights_from_filtered", 7), ("reserved", 1), ("delta", float("inf")),
+])
+def test_validate_rejects(field, value):
+    L = _lib()
+    p = _default(L)
+    setattr(p, field, value)
+    assert L.lib().pros_validate(C.byref(p)) == L.PROS_EINVAL
+    assert L.last_error()
+
+
+def test_k_larger_than_frame_rejected():
+    L = _lib()
+    p = _default(L, 2, 2, 1)
+    p.k = 5
+    assert L.lib().pros_validate(C.byref(p)) == L.PROS_EINVAL
+
+
+def test_init_rejects_invalid_params_without_touching_the_gpu():
+    L = _lib()
+    p = _default(L)
+    p.k = 0
+    h = C.c_void_p(123)
+    assert L.lib().pros_init(C.byref(p), None, C.byref(h)) == L.PROS_EINVAL
+    assert h.value is None
+    assert L.lib().pros_init(None, None, C.byref(h)) == L.PROS_EINVAL
+    assert L.lib().pros_init(C.byref(_default(L)), None, None) == L.PROS_EINVAL
+
+
+def test_null_handles_rejected():
+    L = _lib()
+    assert L.lib().pros_track_frame(None, None, 0, 0) == L.PROS_EINVAL
+    assert L.lib().pros_sync(None) == L.PROS_EINVAL
+    assert L.lib().pros_get_mask(None, None, 1, 0) == L.PROS_EINVAL
+    assert L.lib().pros_set_state(None, None, None, None, 0) == L.PROS_EINVAL
+    assert L.lib().pros_params_default(None, 1, 1, 1) == L.PROS_EINVAL
+    L.lib().pros_destroy(None)
+
+
+def test_strerror_covers_codes():
+    L = _lib()
+    for s in range(0, -8, -1):
+        assert L.strerror(s) and "unknown" not in L.strerror(s)
+    assert "unknown" in L.strerror(-99)

@@ -1,0 +1,182 @@
+"""GPU parity of the plain float32 frame kernel against the float64 oracle.
+
+State injection: the oracle's state before frame n is loaded into the GPU
+tracker, both process frame n, and y, U, labels, mask and cost values are
+compared (tolerances in gpu_common).  Sizes span several workgroup tiles and
+a ragged last tile; the 640x480x3 case is the benchmark's launch
+configuration."""
+import numpy as np
+import pytest
+
+from gpu_common import (GUARD, assert_parity, compare_step, f32, oracle_params, oracle_trajectory,
+                        say, tracker_kwargs)
+from oracle import prost_oracle as O
+from synth import video as V
+
+pytestmark = pytest.mark.gpu
+
+
+def _tracker(prm, storage="f32"):
+    import torch
+    from paper_1302_2073_amd import Tracker
+    assert torch.cuda.is_available()
+    return Tracker(prm.width, prm.height, prm.channels, prm.k, **tracker_kwargs(prm, storage))
+
+
+@pytest.mark.parametrize("frame", [0, 1, 2, 10, 57, 120, 199])
+def test_small_gray_step(frame):
+    wl, prm, sv, states = oracle_trajectory("small_gray", 199)
+    say(f"small_gray frame {frame}")
+    with _tracker(prm) as trk:
+        say("  launch", trk.launch_info())
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("frame", [0, 1, 12])
+def test_qvga_rgb_step(frame):
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 12)
+    say(f"qvga_rgb frame {frame}")
+    with _tracker(prm) as trk:
+        say("  launch", trk.launch_info())
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("frame", [0, 3])
+def test_vga_rgb_step(frame):
+    """640x480x3, k=15: the benchmark's workload and launch configuration."""
+    wl, prm, sv, states = oracle_trajectory("vga_rgb", 3)
+    say(f"vga_rgb frame {frame}")
+    with _tracker(prm) as trk:
+        say("  launch", trk.launch_info())
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("cost", ["lp", "log"])
+@pytest.mark.parametrize("shape", [(7, 5, 3, 4), (33, 17, 1, 1), (41, 29, 2, 16), (123, 77, 3, 9)])
+def test_random_shapes(shape, cost):
+    """Ragged sizes, k = 1 and k = 16, 1-3 channels, both cost forms."""
+    W, H, Cc, k = shape
+    rank = min(k, 3)
+    spec = V.VideoSpec(W, H, Cc, rank=rank, seed=30 + W, noise=0.01, fg_kind="rects",
+                       fg_count=2, fg_density=0.1)
+    sv = V.SyntheticVideo(spec)
+    mu = 1e-3
+    prm = O.Params(W, H, Cc, k=k, mu=mu, cost=cost, t_init=5e-3, t_min=1e-4, i_init=20)
+    st = O.initial_state(V.initial_subspace(prm.m, k, 3), prm.P)
+    for n in range(6):
+        st, _ = O.track_frame(st, f32(sv.frame(n)), prm)
+    say(f"random shape {shape} cost {cost}")
+    with _tracker(prm) as trk:
+        rep = compare_step(trk, prm, st, f32(sv.frame(6)))
+    assert_parity(rep)
+
+
+def test_labels_before_update_and_filtered_weights():
+    wl, prm0, sv, states = oracle_trajectory("small_gray", 30)
+    prm = oracle_params(wl, labels_after_update=False, weights_from_filtered=True)
+    st = states[30]
+    with _tracker(prm) as trk:
+        rep = compare_step(trk, prm, st, f32(sv.frame(30)))
+    assert_parity(rep)
+
+
+def test_device_frame_equals_host_frame():
+    import torch
+    wl, prm, sv, states = oracle_trajectory("small_gray", 20)
+    x = sv.frame(20).astype(np.float32)
+    st = states[20]
+    with _tracker(prm) as trk:
+        trk.set_state(st.U, st.y, st.labels, st.n)
+        trk.track(x)
+        a = trk.get_state()
+        ma = trk.mask()
+        trk.set_state(st.U, st.y, st.labels, st.n)
+        trk.track(torch.from_numpy(x).cuda())
+        b = trk.get_state()
+        mb = trk.mask()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert np.array_equal(ma, mb)
+
+
+def test_deterministic_bitwise():
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 2)
+    x = sv.frame(2).astype(np.float32)
+    outs = []
+    with _tracker(prm) as trk:
+        for _ in range(3):
+            trk.set_state(states[2].U, states[2].y, states[2].labels, 2)
+            trk.track(x)
+            outs.append(trk.get_state() + (trk.mask(), trk.stats()["f"]))
+    for o in outs[1:]:
+        for a, b in zip(outs[0][:5], o[:5]):
+            assert np.array_equal(a, b)
+        assert outs[0][5] == o[5]
+
+
+def test_degenerate_zero_frame_and_zero_weights():
+    """x = 0 with y = 0: zero gradient, CG stops at once, zeta = 0 so U does
+    not move; all pixels background.  omega = 0 with every pixel foreground:
+    all weights vanish, same outcome."""
+    prm = O.Params(20, 10, 3, k=3, mu=1e-3)
+    U0 = V.initial_subspace(prm.m, 3, 5)
+    st = O.initial_state(U0, prm.P)
+    with _tracker(prm) as trk:
+        rep = compare_step(trk, prm, st, np.zeros(prm.m))
+        assert rep["stats"]["cg_steps"] == 0 and rep["stats"]["updated"] == 0
+        assert np.array_equal(rep["U1"], rep["start"].U)
+        assert rep["labels"].sum() == 0
+    prm0 = O.Params(20, 10, 3, k=3, mu=1e-3, omega=0.0)
+    st1 = O.State(U0, np.ones(3) * 0.1, np.ones(prm.P, np.uint8), np.ones(prm.P, np.uint8), 4)
+    x = f32(np.random.default_rng(1).random(prm.m))
+    with _tracker(prm0) as trk:
+        rep = compare_step(trk, prm0, st1, x)
+        assert rep["stats"]["cg_steps"] == 0 and rep["stats"]["updated"] == 0
+        assert np.array_equal(rep["U1"], rep["start"].U)
+    assert_parity(rep)
+
+
+def test_bad_frame_rejected_state_unchanged():
+    import torch
+    from paper_1302_2073_amd import _lib as L
+    wl, prm, sv, states = oracle_trajectory("small_gray", 5)
+    st = states[5]
+    x = sv.frame(5).astype(np.float32)
+    x[100] = np.nan
+    with _tracker(prm) as trk:
+        trk.set_state(st.U, st.y, st.labels, st.n)
+        before = trk.get_state()
+        with pytest.raises(L.ProstError) as ei:
+            trk.track(x)                      # host frame: rejected on the host
+        assert ei.value.status == L.PROS_EBADFRAME
+        xd = torch.from_numpy(x).cuda()
+        trk.track(xd)                         # device frame: rejected by the kernel
+        assert trk.sync() == L.PROS_EBADFRAME
+        after = trk.get_state()
+        for a, b in zip(before, after):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        # the tracker keeps working afterwards
+        rep = compare_step(trk, prm, st, f32(sv.frame(5)))
+    assert_parity(rep)
+
+
+def test_free_running_small_gray():
+    """200 frames on both sides without state injection: report the drift;
+    masks disagree on at most 0.5% of pixels per frame."""
+    wl, prm, sv, states = oracle_trajectory("small_gray", 199)
+    worst = 0.0
+    with _tracker(prm) as trk:
+        trk.set_state(states[0].U, states[0].y, states[0].labels, 0)
+        for n in range(200):
+            trk.track(sv.frame(n).astype(np.float32))
+            if n + 1 < len(states) and n % 20 == 19:
+                U, y, lab, nn = trk.get_state()
+                ref = states[n + 1]
+                ang = O.principal_angles(ref.U, U).max()
+                dis = float(np.mean(lab != ref.labels))
+                worst = max(worst, dis)
+                say(f"  frame {n}: angle {ang:.2e} y_rel {np.linalg.norm(y - ref.y) / np.linalg.norm(ref.y):.2e} "
+                    f"label disagreement {dis:.4%}")
+    assert worst <= 0.005
