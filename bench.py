@@ -1,0 +1,187 @@
+"""Benchmark of the pROST per-frame hot path on one MI355X.
+
+Workload: 640x480 RGB frames (m = 921600), k = 15, 5 CG steps per frame,
+seeded synthetic video (rank-10 background, 3 moving rectangles, noise 0.01),
+frames pre-staged in HBM.  A step is one frame of every stream through
+Steps 1-3 and the median.
+
+Prints one JSON line with frames/s, the roofline of the dominant kernel and
+the float64 oracle timed on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--pool N]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, public figure
+WIDTH, HEIGHT, CH, K = 640, 480, 3, 15
+
+
+def alg_bytes(m, k, P, bu, bx):
+    """Compulsory HBM bytes of one frame: U read once and written once, the
+    frame read once, labels read and written, mask written (1 byte/pixel)."""
+    return 2 * m * k * bu + m * bx + 3 * P
+
+
+def pass_bytes(m, k, P, bu, bx, J=5):
+    """Bytes of a design that streams U and x through HBM once per
+    dependent pass (J + 2 reads of U and x, one write of U)."""
+    return (J + 3) * m * k * bu + (J + 2) * m * bx + (J + 4) * P
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1302_2073_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(f"{kernel}|{workload}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def make_frames(pool, dtype):
+    import torch
+    from synth import video as V
+    wl = V.vga_rgb()
+    sv = V.SyntheticVideo(wl.video)
+    X = np.stack([sv.frame(n) for n in range(pool)]).astype(np.float32)
+    t = torch.from_numpy(X).cuda()
+    if dtype == "bf16":
+        t = t.to(torch.bfloat16)
+    return wl, sv, t.contiguous()
+
+
+def run_plain(storage, steps, warmup, pool):
+    import torch
+    from paper_1302_2073_amd import Tracker
+    from synth import video as V
+    wl, sv, frames = make_frames(pool, storage)
+    trk = Tracker(WIDTH, HEIGHT, CH, K, mu=wl.mu, storage=storage)
+    trk.set_state(V.initial_subspace(trk.m, K, wl.video.seed))
+    stream = torch.cuda.current_stream()   # the tracker was created on this stream
+    for i in range(warmup):
+        trk.track(frames[i % pool])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        trk.track(frames[(warmup + i) % pool])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    st = trk.sync()
+    if st != 0:
+        raise RuntimeError(f"tracker error {st}")
+    ms = e0.elapsed_time(e1)
+    info = trk.launch_info()
+    stats = trk.stats()
+    trk.close()
+    return dict(ms_total=ms, ms_per_frame=ms / steps, fps=steps / (ms / 1e3), launch=info,
+                fg=None, cg_steps=stats["cg_steps"])
+
+
+def cpu_baseline(seconds=15.0):
+    """The float64 oracle on the same workload, timed on the host cores over
+    a bounded number of frames."""
+    from oracle import prost_oracle as O
+    from synth import video as V
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    wl = V.vga_rgb()
+    sv = V.SyntheticVideo(wl.video)
+    prm = O.Params(WIDTH, HEIGHT, CH, k=K, mu=wl.mu)
+    st = O.initial_state(V.initial_subspace(prm.m, K, wl.video.seed), prm.P)
+    frames = [sv.frame(n).astype(np.float32).astype(np.float64) for n in range(4)]
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        st, _ = O.track_frame(st, frames[n % len(frames)], prm)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 200:
+            break
+    return dict(value=n / el, unit="frames/s", cores=int(cores), kind="oracle",
+                sample=f"{n} frames of 640x480x3 k=15 (float64 numpy oracle, {el:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--pool", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
+              f"shards by independent streams, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    plain = run_plain("f32", args.steps, args.warmup, args.pool)
+    plain_bf16 = run_plain("bf16", args.steps, args.warmup, args.pool)
+
+    m, P = WIDTH * HEIGHT * CH, WIDTH * HEIGHT
+    b_alg = alg_bytes(m, K, P, 4, 4)
+    achieved = b_alg / (plain["ms_per_frame"] * 1e-3) / 1e9
+    traffic = measured_traffic("frame_kernel<15,8,float>", "640x480x3 k=15 f32")
+    out = {
+        "metric": "frames/sec at 640x480x3, k=15 (plain vs batched BF16); HBM GB/s vs peak",
+        "value": round(plain["fps"], 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(plain["ms_per_frame"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded rank-10 background + moving rectangles + noise, 640x480x3)",
+        "config": {"workload": "plain float32 tracker, one 640x480x3 stream, k=15, 5 CG steps",
+                   "form": "plain_f32", "launch": plain["launch"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic},
+        "forms": {
+            "plain_f32": {"fps": round(plain["fps"], 2), "ms_per_frame": round(plain["ms_per_frame"], 5),
+                          "alg_GBps": round(achieved, 1),
+                          "pass_GBps": round(pass_bytes(m, K, P, 4, 4) / (plain["ms_per_frame"] * 1e-3) / 1e9, 1)},
+            "plain_bf16": {"fps": round(plain_bf16["fps"], 2), "ms_per_frame": round(plain_bf16["ms_per_frame"], 5),
+                           "alg_GBps": round(alg_bytes(m, K, P, 2, 2) / (plain_bf16["ms_per_frame"] * 1e-3) / 1e9, 1)},
+        },
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

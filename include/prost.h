@@ -42,6 +42,12 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#if defined(__GNUC__)
+#define PROS_API __attribute__((visibility("default")))
+#else
+#define PROS_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -107,33 +113,33 @@ typedef struct pros_handle pros_handle;
  * channels video (k=15, 5 CG steps, p=0.25, omega=5e-5, t_init=5e-3,
  * t_min=1e-4, i_init=100, mu=1e-3, FP32 storage).  Returns PROS_EINVAL on a
  * NULL pointer. */
-pros_status pros_params_default(pros_params* out, int32_t width, int32_t height, int32_t channels);
+PROS_API pros_status pros_params_default(pros_params* out, int32_t width, int32_t height, int32_t channels);
 
 /* Validate a parameter set without touching the GPU.  PROS_EINVAL names no
  * field; pros_last_error() gives the reason. */
-pros_status pros_validate(const pros_params* prm);
+PROS_API pros_status pros_validate(const pros_params* prm);
 
 /* Create a tracker.  Allocates the device state on the current HIP device and
  * queues its initialisation on `hip_stream` (a hipStream_t, NULL = default):
  * U = 0 (must be set with pros_set_state before the first frame), y = 0,
  * labels = mask = 0, frame counter 0.  On error *out is NULL. */
-pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out);
+PROS_API pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out);
 
 /* Release all device memory of the handle (waits for its stream).  NULL is
  * accepted. */
-void pros_destroy(pros_handle* h);
+PROS_API void pros_destroy(pros_handle* h);
 
 /* Load tracker state from host float64 arrays: U (m x k column-major,
  * required), y (k, NULL = zeros), labels (P bytes, NULL = zeros; also used as
  * the previous filtered mask), frame counter n >= 0.  U is rounded to the
  * storage type.  Synchronous. */
-pros_status pros_set_state(pros_handle* h, const double* U, const double* y,
+PROS_API pros_status pros_set_state(pros_handle* h, const double* U, const double* y,
                            const uint8_t* labels, int64_t n);
 
 /* Copy the tracker state to host buffers (any may be NULL): U as float64
  * m x k column-major, y (k), raw labels (P bytes), frame counter.
  * Synchronises the stream and reports pending device errors. */
-pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_t* labels, int64_t* n);
+PROS_API pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_t* labels, int64_t* n);
 
 /* Process one frame (Steps 1-3 of Sec. 3.3 and the median).  `frame` holds m
  * entries of type `dtype` (PROS_F32 or PROS_BF16, must equal the storage
@@ -141,24 +147,24 @@ pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_t* labels
  * staging buffer before returning (rejected with PROS_EBADFRAME if an entry
  * is not finite); on_device = 1: device memory read in place by the queued
  * kernels.  Asynchronous. */
-pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device);
+PROS_API pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device);
 
 /* Copy the latest mask: filtered = 1 gives the 3x3-median mask F, 0 the raw
  * labels.  out holds P bytes on the host (on_device = 0, synchronises) or on
  * the device (on_device = 1, queued on the stream). */
-pros_status pros_get_mask(pros_handle* h, uint8_t* out, int32_t filtered, int32_t on_device);
+PROS_API pros_status pros_get_mask(pros_handle* h, uint8_t* out, int32_t filtered, int32_t on_device);
 
 /* Statistics of the last processed frame.  Synchronises. */
-pros_status pros_get_stats(pros_handle* h, pros_stats* out);
+PROS_API pros_status pros_get_stats(pros_handle* h, pros_stats* out);
 
 /* Wait for the handle's queued work and report pending device errors. */
-pros_status pros_sync(pros_handle* h);
+PROS_API pros_status pros_sync(pros_handle* h);
 
 /* Re-orthonormalise U now (nearest orthonormal basis U (U^T U)^{-1/2},
  * accumulated and solved in float64 on the GPU; y <- (U^T U)^{1/2} y so that
  * U y is unchanged to first order).  Asynchronous.  Also run automatically
  * every reorth_every frames. */
-pros_status pros_reorthonormalize(pros_handle* h);
+PROS_API pros_status pros_reorthonormalize(pros_handle* h);
 
 /* Launch configuration chosen for the handle (for diagnostics). */
 typedef struct pros_launch_info {
@@ -169,12 +175,100 @@ typedef struct pros_launch_info {
   int32_t barriers_per_frame;/* gang-wide reductions per frame */
   int32_t reserved;
 } pros_launch_info;
-pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out);
+PROS_API pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out);
+
+/* ---------------------------------------------------------------------------
+ * Batched form.  n independent streams (own resolution, k, parameters; one
+ * storage type) advance by one frame each per pros_batch_track, in ONE
+ * persistent cooperative kernel launch: every stream's frame is the same
+ * Steps 1-3 + median as pros_track_frame (Sec. 3.3, 3.4), its workgroup
+ * tiles form a gang for the frame's reductions, and a host-built schedule
+ * packs the gangs onto the resident workgroups in rounds.  Frames are read
+ * from a caller-registered ring of device frames: stream s reads
+ * frames[s * ring + (n_s % ring)] where n_s is its frame counter.  All
+ * streams start with U = 0; set each with pros_batch_set_state.
+ * Errors as for single streams; a failed launch makes the batch unusable.
+ * ------------------------------------------------------------------------- */
+typedef struct pros_batch pros_batch;
+
+typedef struct pros_batch_config {
+  int32_t register_budget;   /* floats of U held in registers per thread: 64 or 128 */
+  int32_t workgroups_per_cu; /* resident workgroups per CU used by the launch */
+  double tile_scale;         /* (0, 1]: fraction of the register tile each workgroup fills */
+  int32_t strategy;          /* 0: gangs packed by decreasing size, 1: in stream order */
+  int32_t workgroups;        /* out: resident workgroups of the launch */
+  int32_t rounds;            /* out: rounds of the schedule */
+  int32_t reserved;
+} pros_batch_config;
+
+/* Create a batch of n streams (per_stream[0..n-1]; reorth_every must be 0,
+ * use pros_batch_reorthonormalize).  Work is queued on hip_stream. */
+PROS_API pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_stream, pros_batch** out);
+PROS_API void pros_batch_destroy(pros_batch* b);
+/* Same contract as pros_set_state / pros_get_state for stream s. */
+PROS_API pros_status pros_batch_set_state(pros_batch* b, int32_t s, const double* U, const double* y,
+                                 const uint8_t* labels, int64_t n);
+PROS_API pros_status pros_batch_get_state(pros_batch* b, int32_t s, double* U, double* y, uint8_t* labels, int64_t* n);
+/* Register the frame ring: n * ring device pointers (host array; stream s,
+ * slot i at frames[s * ring + i]), each m_s entries of the storage type.
+ * The pointed-to frames must stay valid while batch steps run.  Synchronous. */
+PROS_API pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int32_t ring);
+/* One batch step: every stream processes its next frame.  Asynchronous. */
+PROS_API pros_status pros_batch_track(pros_batch* b);
+/* 1: capture the launch into a hipGraph on first use and replay it. */
+PROS_API pros_status pros_batch_use_graph(pros_batch* b, int32_t on);
+PROS_API pros_status pros_batch_sync(pros_batch* b);
+PROS_API pros_status pros_batch_get_mask(pros_batch* b, int32_t s, uint8_t* out, int32_t filtered, int32_t on_device);
+PROS_API pros_status pros_batch_get_stats(pros_batch* b, int32_t s, pros_stats* out);
+/* Re-orthonormalise every stream's U (as pros_reorthonormalize). */
+PROS_API pros_status pros_batch_reorthonormalize(pros_batch* b);
+/* Current launch configuration / apply one (resizes tiles, rebuilds the
+ * schedule; synchronises). */
+PROS_API pros_status pros_batch_get_config(pros_batch* b, pros_batch_config* out);
+PROS_API pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg);
+/* Autotuner: time `steps` batch steps (after one warm-up step) for every
+ * candidate configuration (register budget x workgroups per CU x tile scale
+ * x strategy), restoring every stream's state after each candidate, then
+ * apply the fastest.  Needs registered frames.  Reports the chosen
+ * configuration and its time per step (ms). */
+PROS_API pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_config* best, double* best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Differentiable cost.  h_{mu,w}(x - U y) of eqs. (weightedLPnorm),
+ * (spcacost) for a batch of B frames sharing U, and its adjoint.  For B = 1
+ * and an upstream gradient of 1, dU is the Euclidean gradient eta y^T of
+ * Sec. 3.3 (Step 2).
+ *
+ * All pointers are device pointers to row-major float32 arrays:
+ *   U (m, k), Y (B, k), X (B, m), w (m) or NULL for w = 1, mu (1 value, so
+ *   that it can be a tensor with a gradient), f (B), gout (B),
+ *   dX (B, m), dU (m, k), dY (B, k), dmu (1); any output of the backward may
+ *   be NULL to skip writing it.
+ * `workspace` is caller-owned device memory of at least
+ * pros_lpcost_workspace_size(m, k, B) bytes (partial sums; contents need
+ * not be initialised).  Work is queued on `hip_stream`; results are
+ * deterministic (fixed-order float64 reductions).  1 <= k <= PROS_MAX_K.
+ * Errors: PROS_EINVAL for NULL inputs, bad sizes or a small workspace.
+ * ------------------------------------------------------------------------- */
+PROS_API size_t pros_lpcost_workspace_size(int32_t m, int32_t k, int32_t B);
+
+/* f_b = sum_e w_e phi(X[b,e] - U[e,:] . Y[b,:]). */
+PROS_API pros_status pros_lpcost_fwd(const float* U, const float* Y, const float* X, const float* w, const float* mu,
+                            int32_t m, int32_t k, int32_t B, int32_t cost, float p, float* f,
+                            void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Adjoint of pros_lpcost_fwd for the upstream gradient gout:
+ * dX[b,e] = gout_b w_e phi'(r), dU[e,:] = -sum_b gout_b w_e phi'(r) Y[b,:],
+ * dY[b,:] = -gout_b sum_e w_e phi'(r) U[e,:], dmu = sum_b gout_b sum_e w_e dphi/dmu. */
+PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float* X, const float* w, const float* mu,
+                            int32_t m, int32_t k, int32_t B, int32_t cost, float p, const float* gout,
+                            float* dX, float* dU, float* dY, float* dmu,
+                            void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /* Text for a status code (static storage). */
-const char* pros_strerror(pros_status s);
+PROS_API const char* pros_strerror(pros_status s);
 /* Detail of the last error on the calling thread (static thread storage). */
-const char* pros_last_error(void);
+PROS_API const char* pros_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,12 @@ class pros_launch_info(C.Structure):
                 ("pixels_per_wg", C.c_int32), ("barriers_per_frame", C.c_int32), ("reserved", C.c_int32)]
 
 
+class pros_batch_config(C.Structure):
+    _fields_ = [("register_budget", C.c_int32), ("workgroups_per_cu", C.c_int32), ("tile_scale", C.c_double),
+                ("strategy", C.c_int32), ("workgroups", C.c_int32), ("rounds", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class ProstError(RuntimeError):
     def __init__(self, status, detail=""):
         self.status = status
@@ -79,6 +85,26 @@ _SIGS = {
     "pros_sync": (C.c_int, [C.c_void_p]),
     "pros_reorthonormalize": (C.c_int, [C.c_void_p]),
     "pros_get_launch_info": (C.c_int, [C.c_void_p, C.POINTER(pros_launch_info)]),
+    "pros_batch_init": (C.c_int, [C.POINTER(pros_params), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pros_batch_destroy": (None, [C.c_void_p]),
+    "pros_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "pros_batch_get_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.POINTER(C.c_int64)]),
+    "pros_batch_set_frames": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32]),
+    "pros_batch_track": (C.c_int, [C.c_void_p]),
+    "pros_batch_use_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pros_batch_sync": (C.c_int, [C.c_void_p]),
+    "pros_batch_get_mask": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32]),
+    "pros_batch_get_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(pros_stats)]),
+    "pros_batch_reorthonormalize": (C.c_int, [C.c_void_p]),
+    "pros_batch_get_config": (C.c_int, [C.c_void_p, C.POINTER(pros_batch_config)]),
+    "pros_batch_configure": (C.c_int, [C.c_void_p, C.POINTER(pros_batch_config)]),
+    "pros_batch_tune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(pros_batch_config), C.POINTER(C.c_double)]),
+    "pros_lpcost_workspace_size": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "pros_lpcost_fwd": (C.c_int, [C.c_void_p] * 5 + [C.c_int32] * 4 + [C.c_float]
+                        + [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pros_lpcost_bwd": (C.c_int, [C.c_void_p] * 5 + [C.c_int32] * 4 + [C.c_float]
+                        + [C.c_void_p] * 5 + [C.c_void_p, C.c_size_t, C.c_void_p]),
     "pros_strerror": (C.c_char_p, [C.c_int]),
     "pros_last_error": (C.c_char_p, []),
 }

@@ -68,7 +68,7 @@ float bf16_to_f32(uint16_t b) {
 
 using namespace prost_host;
 
-extern "C" {
+// Entry points keep the C linkage of their declarations in prost.h.
 
 const char* pros_strerror(pros_status s) {
   switch (s) {
@@ -136,7 +136,7 @@ pros_status pros_validate(const pros_params* p) {
   return PROS_OK;
 }
 
-static void free_handle(pros_handle* h) {
+void prost_host::free_handle(pros_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->U, h->xstage, h->lab, h->mask, h->y, h->nframe, h->stats, h->part, h->sync, h->reorth_ws};
   for (void* q : ptrs)
@@ -175,8 +175,8 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
   return PROS_OK;
 }
 
-pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out) {
-  if (!out) return fail(PROS_EINVAL, "out is NULL");
+pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream, int nr_force, int tpw_force,
+                                      int g_force, pros_handle** out) {
   *out = nullptr;
   pros_status st = pros_validate(prm);
   if (st != PROS_OK) return st;
@@ -187,7 +187,7 @@ pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** ou
   h->m = h->P * h->C;
   h->k = prm->k;
   h->ldU = ((long long)h->m + 63) / 64 * 64;
-  h->stream = (hipStream_t)hip_stream;
+  h->stream = stream;
   auto bail = [&](pros_status s) { free_handle(h); return s; };
 #define INIT_TRY(expr)                                                                    \
   do {                                                                                    \
@@ -204,8 +204,14 @@ pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** ou
   INIT_TRY(hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, h->device));
   if (wclk_khz <= 0) wclk_khz = 100000;
   h->timeout_ticks = (long long)wclk_khz * 1000LL * 2;  // 2 s per barrier wait
-  st = choose_launch(h, 0);
-  if (st != PROS_OK) return bail(st);
+  if (g_force > 0) {             // launch owned by a batch
+    h->NR = nr_force;
+    h->tpw = tpw_force;
+    h->G = g_force;
+  } else {
+    st = choose_launch(h, nr_force);
+    if (st != PROS_OK) return bail(st);
+  }
   const size_t es = (prm->storage == PROS_BF16) ? 2 : 4;
   INIT_TRY(hipMalloc(&h->U, es * (size_t)h->ldU * h->k));
   INIT_TRY(hipMalloc(&h->xstage, es * (size_t)h->m));
@@ -229,20 +235,25 @@ pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** ou
   return PROS_OK;
 }
 
+pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out) {
+  if (!out) return fail(PROS_EINVAL, "out is NULL");
+  return prost_host::create_handle(prm, (hipStream_t)hip_stream, 0, 0, 0, out);
+}
+
 void pros_destroy(pros_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
   free_handle(h);
 }
 
-static pros_status check_usable(pros_handle* h) {
+pros_status prost_host::check_usable(pros_handle* h) {
   if (!h) return fail(PROS_EINVAL, "handle is NULL");
   if (h->broken) return fail(h->broken_status, "handle unusable after an earlier error");
   return PROS_OK;
 }
 
 // Synchronise and fold device-side error bits into a status.
-static pros_status sync_and_check(pros_handle* h) {
+pros_status prost_host::sync_and_check(pros_handle* h) {
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     h->broken = true;
@@ -369,7 +380,7 @@ pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_t* labels
   return pending;
 }
 
-static FrameArgs make_args(pros_handle* h, const void* x) {
+FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   FrameArgs a;
   std::memset(&a, 0, sizeof(a));
   const pros_params& p = h->prm;
@@ -510,4 +521,4 @@ pros_status pros_reorthonormalize(pros_handle* h) {
   return prost_reorth_launch(h);
 }
 
-}  // extern "C"
+

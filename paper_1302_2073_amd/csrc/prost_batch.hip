@@ -1,0 +1,523 @@
+// Batched form (C ABI): n independent streams, one persistent cooperative
+// launch per batch step, optional hipGraph replay, and a schedule tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "../../include/prost.h"
+#include "prost_batch.hpp"
+#include "prost_host.hpp"
+
+namespace prost {
+const void* batch_kernel_f32_b64();
+const void* batch_kernel_f32_b128();
+const void* batch_kernel_bf16_b64();
+const void* batch_kernel_bf16_b128();
+}  // namespace prost
+
+using prost::BatchItem;
+using prost::FrameArgs;
+
+#define fail prost_host::set_error
+
+namespace {
+
+constexpr int kBudgets[] = {64, 128};
+
+const void* batch_fn(int storage, int budget) {
+  using namespace prost;
+  if (storage == PROS_BF16) return budget == 64 ? batch_kernel_bf16_b64() : batch_kernel_bf16_b128();
+  return budget == 64 ? batch_kernel_f32_b64() : batch_kernel_f32_b128();
+}
+
+int batch_nr(int budget, int k) {
+  const int q = budget / k;
+  return q >= 16 ? 16 : q >= 12 ? 12 : q >= 8 ? 8 : 4;
+}
+
+}  // namespace
+
+struct pros_batch {
+  int n = 0;
+  int storage = PROS_F32;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  std::vector<pros_handle*> hs;
+  // launch
+  int budget = 128;
+  int wg_per_cu = 2;
+  int nwg = 0;
+  int rounds = 0;
+  int strategy = 0;
+  double tile_scale = 1.0;
+  const void* kfn = nullptr;
+  FrameArgs* d_descs = nullptr;
+  BatchItem* d_items = nullptr;
+  const void** d_xtab = nullptr;
+  int ring = 1;
+  bool frames_set = false;
+  std::vector<FrameArgs> descs;
+  std::vector<BatchItem> items;
+  // graph
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool broken = false;
+};
+
+static void drop_graph(pros_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+static void free_batch(pros_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  for (pros_handle* h : b->hs) prost_host::free_handle(h);
+  if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_xtab) (void)hipFree((void*)b->d_xtab);
+  delete b;
+}
+
+// Build the (round, workgroup) -> (stream, tile) schedule for the current
+// launch parameters.  strategy 0: first-fit by decreasing gang size;
+// strategy 1: first-fit in stream order.
+static pros_status build_schedule(pros_batch* b) {
+  const int nwg = b->nwg;
+  std::vector<int> order(b->n);
+  std::iota(order.begin(), order.end(), 0);
+  if (b->strategy == 0)
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->hs[a]->G > b->hs[c]->G; });
+  std::vector<int> used;   // slots used per round
+  std::vector<BatchItem> items;
+  for (int s : order) {
+    const int G = b->hs[s]->G;
+    if (G > nwg) return fail(PROS_EUNSUPPORTED, "stream %d needs %d resident workgroups, the launch has %d", s, G, nwg);
+    int r = 0;
+    while (r < (int)used.size() && used[r] + G > nwg) ++r;
+    if (r == (int)used.size()) {
+      used.push_back(0);
+      items.resize(used.size() * (size_t)nwg, BatchItem{-1, 0});
+    }
+    for (int t = 0; t < G; ++t) items[(size_t)r * nwg + used[r] + t] = BatchItem{s, t};
+    used[r] += G;
+  }
+  b->rounds = (int)used.size();
+  b->items.swap(items);
+  return PROS_OK;
+}
+
+// (Re)create the per-stream tile configuration, descriptors and schedule.
+static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy) {
+  const void* f = batch_fn(b->storage, budget);
+  int occ = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0);
+  if (e != hipSuccess) return fail(PROS_EHIP, "occupancy query: %s", hipGetErrorString(e));
+  if (occ < 1) return fail(PROS_EUNSUPPORTED, "batch kernel cannot be resident");
+  const int wpc = std::min(occ, wg_per_cu);
+  const int nwg = wpc * b->num_cu;
+  for (pros_handle* h : b->hs) {
+    const int NR = batch_nr(budget, h->k);
+    int tpw = (int)std::floor(prost::kBlock * NR * tile_scale / h->C);
+    tpw = std::max(1, std::min(tpw, prost::kBlock * NR / h->C));
+    const int G = (h->P + tpw - 1) / tpw;
+    if (G > nwg) return fail(PROS_EUNSUPPORTED, "a %dx%dx%d stream at k=%d needs %d workgroups (> %d)",
+                             h->prm.width, h->prm.height, h->C, h->k, G, nwg);
+    if (G != h->G) {   // partial buffer sized by the gang
+      (void)hipFree(h->part);
+      h->part = nullptr;
+      e = hipMalloc((void**)&h->part, sizeof(double) * 2 * (size_t)G * prost::kSlot);
+      if (e != hipSuccess) return fail(PROS_ENOMEM, "partials: %s", hipGetErrorString(e));
+    }
+    h->NR = NR;
+    h->tpw = tpw;
+    h->G = G;
+  }
+  b->budget = budget;
+  b->wg_per_cu = wpc;
+  b->nwg = nwg;
+  b->kfn = f;
+  b->tile_scale = tile_scale;
+  b->strategy = strategy;
+  pros_status st = build_schedule(b);
+  if (st != PROS_OK) return st;
+  b->descs.resize(b->n);
+  for (int s = 0; s < b->n; ++s) {
+    FrameArgs a = prost_host::make_args(b->hs[s], nullptr);
+    a.xtab = b->d_xtab + (size_t)s * b->ring;
+    a.ring = b->ring;
+    b->descs[s] = a;
+  }
+  if (b->d_items) (void)hipFree(b->d_items);
+  b->d_items = nullptr;
+  e = hipMalloc((void**)&b->d_items, sizeof(BatchItem) * b->items.size());
+  if (e != hipSuccess) return fail(PROS_ENOMEM, "schedule: %s", hipGetErrorString(e));
+  e = hipMemcpy(b->d_items, b->items.data(), sizeof(BatchItem) * b->items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(PROS_EHIP, "schedule upload: %s", hipGetErrorString(e));
+  e = hipMemcpy(b->d_descs, b->descs.data(), sizeof(FrameArgs) * b->n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(PROS_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  drop_graph(b);
+  return PROS_OK;
+}
+
+static pros_status launch(pros_batch* b) {
+  FrameArgs* d = b->d_descs;
+  BatchItem* it = b->d_items;
+  int rounds = b->rounds;
+  void* args[] = {&d, &it, &rounds};
+  hipError_t e = hipLaunchCooperativeKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, b->stream);
+  if (e != hipSuccess) {
+    b->broken = true;
+    return fail(PROS_EHIP, "batch kernel launch: %s", hipGetErrorString(e));
+  }
+  return PROS_OK;
+}
+
+static pros_status check_batch(pros_batch* b) {
+  if (!b) return fail(PROS_EINVAL, "batch is NULL");
+  if (b->broken) return fail(PROS_EHIP, "batch unusable after an earlier error");
+  return PROS_OK;
+}
+
+static pros_status check_stream(pros_batch* b, int32_t s) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (s < 0 || s >= b->n) return fail(PROS_EINVAL, "stream index %d out of range", s);
+  return PROS_OK;
+}
+
+extern "C" {
+
+pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_stream, pros_batch** out) {
+  if (!out) return fail(PROS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!per_stream || n < 1) return fail(PROS_EINVAL, "need at least one stream");
+  const int storage = per_stream[0].storage;
+  for (int s = 0; s < n; ++s) {
+    pros_status st = pros_validate(&per_stream[s]);
+    if (st != PROS_OK) {
+      char why[256];
+      std::snprintf(why, sizeof(why), "%s", pros_last_error());
+      return fail(st, "stream %d: %s", s, why);
+    }
+    if (per_stream[s].storage != storage) return fail(PROS_EINVAL, "all streams of a batch share one storage type");
+    if (per_stream[s].reorth_every != 0)
+      return fail(PROS_EINVAL, "stream %d: use pros_batch_reorthonormalize in a batch", s);
+  }
+  pros_batch* b = new pros_batch();
+  b->n = n;
+  b->storage = storage;
+  b->stream = (hipStream_t)hip_stream;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return fail(PROS_EHIP, "device query: %s", hipGetErrorString(e));
+  }
+  for (int s = 0; s < n; ++s) {
+    pros_handle* h = nullptr;
+    const int NR = batch_nr(128, per_stream[s].k);
+    const int tpw = prost::kBlock * NR / per_stream[s].channels;
+    const int P = per_stream[s].width * per_stream[s].height;
+    pros_status st = prost_host::create_handle(&per_stream[s], b->stream, NR, tpw, (P + tpw - 1) / tpw, &h);
+    if (st != PROS_OK) {
+      free_batch(b);
+      return st;
+    }
+    b->hs.push_back(h);
+  }
+  e = hipMalloc((void**)&b->d_descs, sizeof(FrameArgs) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_xtab, sizeof(void*) * n);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return fail(PROS_ENOMEM, "batch tables: %s", hipGetErrorString(e));
+  }
+  pros_status st = configure(b, 128, 2, 1.0, 0);
+  if (st != PROS_OK) {
+    free_batch(b);
+    return st;
+  }
+  *out = b;
+  return PROS_OK;
+}
+
+void pros_batch_destroy(pros_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
+}
+
+pros_status pros_batch_set_state(pros_batch* b, int32_t s, const double* U, const double* y, const uint8_t* labels,
+                                 int64_t n) {
+  pros_status st = check_stream(b, s);
+  if (st != PROS_OK) return st;
+  return pros_set_state(b->hs[s], U, y, labels, n);
+}
+
+pros_status pros_batch_get_state(pros_batch* b, int32_t s, double* U, double* y, uint8_t* labels, int64_t* n) {
+  pros_status st = check_stream(b, s);
+  if (st != PROS_OK) return st;
+  return pros_get_state(b->hs[s], U, y, labels, n);
+}
+
+pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int32_t ring) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (!frames || ring < 1) return fail(PROS_EINVAL, "frames is NULL or ring < 1");
+  for (int i = 0; i < b->n * ring; ++i)
+    if (!frames[i]) return fail(PROS_EINVAL, "frame pointer %d is NULL", i);
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
+  if (ring != b->ring) {
+    (void)hipFree((void*)b->d_xtab);
+    b->d_xtab = nullptr;
+    e = hipMalloc((void**)&b->d_xtab, sizeof(void*) * (size_t)b->n * ring);
+    if (e != hipSuccess) return fail(PROS_ENOMEM, "frame table: %s", hipGetErrorString(e));
+    b->ring = ring;
+    for (int s = 0; s < b->n; ++s) {
+      b->descs[s].xtab = b->d_xtab + (size_t)s * ring;
+      b->descs[s].ring = ring;
+    }
+    e = hipMemcpy(b->d_descs, b->descs.data(), sizeof(FrameArgs) * b->n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(PROS_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+    drop_graph(b);
+  }
+  e = hipMemcpy((void*)b->d_xtab, frames, sizeof(void*) * (size_t)b->n * ring, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(PROS_EHIP, "frame table upload: %s", hipGetErrorString(e));
+  b->frames_set = true;
+  return PROS_OK;
+}
+
+pros_status pros_batch_track(pros_batch* b) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (!b->frames_set) return fail(PROS_ESTATE, "register frames with pros_batch_set_frames first");
+  for (pros_handle* h : b->hs)
+    if (!h->state_set) return fail(PROS_ESTATE, "set every stream's U before the first batch step");
+  if (b->use_graph) {
+    if (!b->gexec) {
+      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return fail(PROS_EHIP, "begin capture: %s", hipGetErrorString(e));
+      pros_status ls = launch(b);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(b->stream, &g);
+      if (ls != PROS_OK) return ls;
+      if (e != hipSuccess) {
+        b->broken = true;
+        return fail(PROS_EHIP, "end capture: %s", hipGetErrorString(e));
+      }
+      b->graph = g;
+      e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        b->broken = true;
+        return fail(PROS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+      }
+    }
+    hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+    if (e != hipSuccess) {
+      b->broken = true;
+      return fail(PROS_EHIP, "graph launch: %s", hipGetErrorString(e));
+    }
+  } else {
+    st = launch(b);
+    if (st != PROS_OK) return st;
+  }
+  for (pros_handle* h : b->hs) ++h->submitted;
+  return PROS_OK;
+}
+
+pros_status pros_batch_use_graph(pros_batch* b, int32_t on) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  b->use_graph = on != 0;
+  if (!b->use_graph) drop_graph(b);
+  return PROS_OK;
+}
+
+pros_status pros_batch_sync(pros_batch* b) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  pros_status worst = PROS_OK;
+  for (pros_handle* h : b->hs) {
+    st = pros_sync(h);
+    if (st != PROS_OK && worst == PROS_OK) worst = st;
+  }
+  return worst;
+}
+
+pros_status pros_batch_get_mask(pros_batch* b, int32_t s, uint8_t* out, int32_t filtered, int32_t on_device) {
+  pros_status st = check_stream(b, s);
+  if (st != PROS_OK) return st;
+  return pros_get_mask(b->hs[s], out, filtered, on_device);
+}
+
+pros_status pros_batch_get_stats(pros_batch* b, int32_t s, pros_stats* out) {
+  pros_status st = check_stream(b, s);
+  if (st != PROS_OK) return st;
+  return pros_get_stats(b->hs[s], out);
+}
+
+pros_status pros_batch_reorthonormalize(pros_batch* b) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  for (pros_handle* h : b->hs) {
+    st = pros_reorthonormalize(h);
+    if (st != PROS_OK) return st;
+  }
+  return PROS_OK;
+}
+
+pros_status pros_batch_get_config(pros_batch* b, pros_batch_config* out) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (!out) return fail(PROS_EINVAL, "out is NULL");
+  out->register_budget = b->budget;
+  out->workgroups_per_cu = b->wg_per_cu;
+  out->tile_scale = b->tile_scale;
+  out->strategy = b->strategy;
+  out->workgroups = b->nwg;
+  out->rounds = b->rounds;
+  return PROS_OK;
+}
+
+pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (!cfg) return fail(PROS_EINVAL, "cfg is NULL");
+  if (cfg->register_budget != 64 && cfg->register_budget != 128) return fail(PROS_EINVAL, "register_budget must be 64 or 128");
+  if (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 8) return fail(PROS_EINVAL, "workgroups_per_cu must be 1..8");
+  if (!(cfg->tile_scale > 0.0 && cfg->tile_scale <= 1.0)) return fail(PROS_EINVAL, "tile_scale must be in (0, 1]");
+  if (cfg->strategy < 0 || cfg->strategy > 1) return fail(PROS_EINVAL, "strategy must be 0 or 1");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
+  return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy);
+}
+
+// Device-side copy of every stream's state, so that tuning leaves the
+// trackers where they were.
+struct Snapshot {
+  std::vector<void*> bufs;
+  ~Snapshot() {
+    for (void* p : bufs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+static size_t state_bytes(const pros_handle* h, int which) {
+  const size_t es = (h->prm.storage == PROS_BF16) ? 2 : 4;
+  switch (which) {
+    case 0: return es * (size_t)h->ldU * h->k;
+    case 1: return sizeof(double) * PROS_MAX_K;
+    case 2: return (size_t)h->P;
+    case 3: return (size_t)h->P;
+    default: return sizeof(long long);
+  }
+}
+
+static void* state_ptr(pros_handle* h, int which) {
+  switch (which) {
+    case 0: return h->U;
+    case 1: return h->y;
+    case 2: return h->lab;
+    case 3: return h->mask;
+    default: return h->nframe;
+  }
+}
+
+static pros_status snapshot(pros_batch* b, Snapshot& sn, bool restore) {
+  if (!restore) sn.bufs.assign((size_t)b->n * 5, nullptr);
+  for (int s = 0; s < b->n; ++s)
+    for (int w = 0; w < 5; ++w) {
+      void*& buf = sn.bufs[(size_t)s * 5 + w];
+      const size_t nb = state_bytes(b->hs[s], w);
+      hipError_t e = hipSuccess;
+      if (!restore) e = hipMalloc(&buf, nb);
+      if (e == hipSuccess)
+        e = restore ? hipMemcpyAsync(state_ptr(b->hs[s], w), buf, nb, hipMemcpyDeviceToDevice, b->stream)
+                    : hipMemcpyAsync(buf, state_ptr(b->hs[s], w), nb, hipMemcpyDeviceToDevice, b->stream);
+      if (e != hipSuccess) return fail(PROS_ENOMEM, "tuner snapshot: %s", hipGetErrorString(e));
+    }
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(PROS_EHIP, "tuner sync: %s", hipGetErrorString(e));
+  return PROS_OK;
+}
+
+extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_config* best, double* best_ms) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (steps < 1) return fail(PROS_EINVAL, "steps must be >= 1");
+  if (!b->frames_set) return fail(PROS_ESTATE, "register frames with pros_batch_set_frames first");
+  for (pros_handle* h : b->hs)
+    if (!h->state_set) return fail(PROS_ESTATE, "set every stream's U before tuning");
+  Snapshot sn;
+  st = snapshot(b, sn, false);
+  if (st != PROS_OK) return st;
+  const bool graph = b->use_graph;
+  b->use_graph = false;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(PROS_EHIP, "event creation failed");
+  double bestt = 1e300;
+  pros_batch_config bc{};
+  const double scales[] = {1.0, 0.75, 0.5};
+  const int wpcs[] = {1, 2};
+  for (int budget : kBudgets)
+    for (int wpc : wpcs)
+      for (double sc : scales)
+        for (int strat = 0; strat < 2; ++strat) {
+          if (configure(b, budget, wpc, sc, strat) != PROS_OK) continue;   // does not fit
+          if (b->wg_per_cu != wpc) continue;                               // duplicate of a smaller grid
+          st = launch(b);                                                   // warm-up
+          for (int i = 0; i < steps && st == PROS_OK; ++i) {
+            if (i == 0) (void)hipEventRecord(e0, b->stream);
+            st = launch(b);
+          }
+          (void)hipEventRecord(e1, b->stream);
+          hipError_t e = hipEventSynchronize(e1);
+          if (st != PROS_OK || e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st != PROS_OK ? st : fail(PROS_EHIP, "tuner: %s", hipGetErrorString(e));
+          }
+          pros_status ds = pros_batch_sync(b);
+          if (ds != PROS_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return ds;
+          }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          const double per = ms / steps;
+          if (per < bestt) {
+            bestt = per;
+            bc.register_budget = budget;
+            bc.workgroups_per_cu = wpc;
+            bc.tile_scale = sc;
+            bc.strategy = strat;
+          }
+          st = snapshot(b, sn, true);
+          if (st != PROS_OK) break;
+        }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->use_graph = graph;
+  if (st != PROS_OK) return st;
+  if (bestt >= 1e300) return fail(PROS_EUNSUPPORTED, "no candidate configuration fits");
+  st = configure(b, bc.register_budget, bc.workgroups_per_cu, bc.tile_scale, bc.strategy);
+  if (st != PROS_OK) return st;
+  if (best) pros_batch_get_config(b, best);
+  if (best_ms) *best_ms = bestt;
+  return PROS_OK;
+}
+
+}  // extern "C"

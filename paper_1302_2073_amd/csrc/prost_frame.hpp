@@ -23,7 +23,9 @@ namespace prost {
 
 struct FrameArgs {
   void* U;               // K planes of ldU entries (storage type)
-  const void* x;         // frame, m entries (storage type)
+  const void* x;         // frame, m entries (storage type); used when xtab is NULL
+  const void* const* xtab;  // ring of `ring` frame pointers, frame n at xtab[n % ring]
+  int ring;
   uint8_t* lab;          // raw labels, P bytes (read: previous frame, write: this frame)
   uint8_t* mask;         // median-filtered mask, P bytes
   double* y;             // k coefficients (float64 state)
@@ -46,7 +48,7 @@ struct FrameArgs {
 // Workgroup + gang reduction of L float partials held by every thread.
 // Result (float64, identical in every workgroup) lands in s_out[0..L).
 template <int L>
-__device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameArgs& a, int& nbar,
+__device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
                                             unsigned base, double (*s_red)[kSlot], double* s_out,
                                             int* s_ctl) {
   const int lane = threadIdx.x & 63;
@@ -58,7 +60,7 @@ __device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameAr
     if (lane == 0) s_red[wv][i] = (double)v;
   }
   __syncthreads();
-  double* slot = a.part + ((size_t)(nbar & 1) * a.G + blockIdx.x) * kSlot;
+  double* slot = a.part + ((size_t)(nbar & 1) * a.G + tile) * kSlot;
   if (threadIdx.x < L) {
     double v = 0.0;
 #pragma unroll
@@ -95,6 +97,7 @@ __device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameAr
 }
 
 // Shared k-space state of one workgroup (all float64 unless noted).
+constexpr int kMaxNR = 16;
 template <int K>
 struct KSpace {
   double y[K];
@@ -112,22 +115,32 @@ struct KSpace {
   int flag[4];      // [0] stop CG, [1] bad frame, [2] do update
 };
 
+// Workgroup-shared scratch of one frame tile (sized for the largest k / NR).
+struct FrameSmem {
+  KSpace<kMaxK> ks;
+  double red[kWaves][kSlot];
+  int ctl[4];
+  uint8_t flag[kBlock * kMaxNR];
+};
+
+// One workgroup's share of one frame: tile `tile` (0 .. a.G-1) of the
+// stream described by `a`.  Returns false when the gang aborted.
 template <int K, int NR, typename TS>
-__global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
-  __shared__ KSpace<K> ks;
-  __shared__ double s_red[kWaves][kSlot];
-  __shared__ int s_ctl[4];
-  __shared__ uint8_t s_flag[kBlock * NR];
+__device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
+  KSpace<kMaxK>& ks = sm.ks;
+  double (*s_red)[kSlot] = sm.red;
+  int* s_ctl = sm.ctl;
+  uint8_t* s_flag = sm.flag;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int p0 = blockIdx.x * a.tpw;
+  const int p0 = tile * a.tpw;
   const int npx = min(a.tpw, a.P - p0);
   const int nq = npx * a.C;
   const unsigned base = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int nbar = 0;
   const long long n = *a.nframe;
-  const bool lead = (blockIdx.x == 0);
+  const bool lead = (tile == 0);
 
   if (tid < K) {
     const double yv = a.y[tid];
@@ -139,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
 
   // ---- load the register tile: U rows, residual r = x - U y, weights ----
   const TS* __restrict__ Ug = (const TS*)a.U;
-  const TS* __restrict__ xg = (const TS*)a.x;
+  const TS* __restrict__ xg = (const TS*)(a.xtab ? a.xtab[n % a.ring] : a.x);
   const uint8_t* __restrict__ wsrc = a.weights_from_filtered ? a.mask : a.lab;
   float u[NR][K];
   float r[NR], wt[NR], cw[NR], ud[NR];
@@ -186,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, u[s][j], acc[j]);
     }
-    if (!gang_reduce<K + 1>(acc, a, nbar, base, s_red, ks.red, s_ctl)) return;
+    if (!gang_reduce<K + 1>(acc, a, tile, nbar, base, s_red, ks.red, s_ctl)) return false;
     // k-space: PR+ direction (wave 0, lane j owns component j)
     if (tid < 64) {
       const double g = (lane < K) ? -ks.red[lane] : 0.0;
@@ -237,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
       ud[s] = t;
       accb[0] = fmaf(cw[s] * t, t, accb[0]);
     }
-    if (!gang_reduce<1>(accb, a, nbar, base, s_red, ks.red, s_ctl)) return;
+    if (!gang_reduce<1>(accb, a, tile, nbar, base, s_red, ks.red, s_ctl)) return false;
     const double dHd = ks.red[0];
     if (!(dHd > 0.0)) break;   // same decision in every workgroup
     const double alpha = -ks.gd / dHd;
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
 #pragma unroll
       for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, u[s][j], acce[j]);
     }
-    if (!gang_reduce<K + 2>(acce, a, nbar, base, s_red, ks.red, s_ctl)) return;
+    if (!gang_reduce<K + 2>(acce, a, tile, nbar, base, s_red, ks.red, s_ctl)) return false;
     if (tid < 64) {
       const double av = (lane < K) ? ks.red[lane] : 0.0;
       const double yv = (lane < K) ? ks.y[lane] : 0.0;
@@ -342,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
   // all label writes visible before the median reads its neighbours
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   ++nbar;
-  if (!gang_barrier(a.sync, base + (unsigned)a.G * (unsigned)nbar, a.timeout, s_ctl)) return;
+  if (!gang_barrier(a.sync, base + (unsigned)a.G * (unsigned)nbar, a.timeout, s_ctl)) return false;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
   if (!bad) {
@@ -377,6 +390,14 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
                        __HIP_MEMORY_SCOPE_AGENT);
   }
   if (lead && !bad && tid < K) a.y[tid] = ks.y[tid];
+  __syncthreads();   // shared scratch may be reused by the next tile
+  return true;
+}
+
+template <int K, int NR, typename TS>
+__global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
+  __shared__ FrameSmem sm;
+  frame_tile<K, NR, TS>(a, blockIdx.x, sm);
 }
 
 }  // namespace prost

@@ -182,7 +182,7 @@ static hipError_t launch_apply(int k, TS* U, long long ldU, int m, const double*
 
 }  // namespace prost
 
-extern "C" pros_status prost_reorth_launch(pros_handle* h) {
+pros_status prost_reorth_launch(pros_handle* h) {
   using namespace prost;
   const int nb = (int)std::min<long long>(kGramBlocks, ((long long)h->m + kGramRows - 1) / kGramRows);
   if (!h->reorth_ws) {

@@ -35,11 +35,21 @@ struct pros_handle {
   pros_status broken_status = PROS_OK;
 };
 
+namespace prost { struct FrameArgs; }
+
 namespace prost_host {
 double effective_delta(const pros_params& p);
+// Allocate and zero a tracker's device state.  g_force > 0 fixes the tile
+// configuration (used by batches); otherwise it is chosen for the frame kernel.
+pros_status create_handle(const pros_params* prm, hipStream_t stream, int nr_force, int tpw_force, int g_force,
+                          pros_handle** out);
+void free_handle(pros_handle* h);
+pros_status check_usable(pros_handle* h);
+pros_status sync_and_check(pros_handle* h);
+prost::FrameArgs make_args(pros_handle* h, const void* x);
 uint16_t bf16_rne(float f);
 float bf16_to_f32(uint16_t b);
 pros_status set_error(pros_status s, const char* fmt, ...);
 }  // namespace prost_host
 
-extern "C" pros_status prost_reorth_launch(pros_handle* h);
+pros_status prost_reorth_launch(pros_handle* h);

@@ -164,3 +164,149 @@ def bf16_bits(a):
 
 def bf16_to_f64(b):
     return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+class BatchTracker:
+    """Many independent streams advanced by one persistent launch per step
+    (pros_batch_*).  `specs` is a list of dicts with width, height, channels,
+    k and any make_params keyword; all streams share one storage type."""
+
+    def __init__(self, specs, storage="f32", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("BatchTracker needs a HIP GPU")
+        n = len(specs)
+        arr = (L.pros_params * n)()
+        self.shapes = []
+        for i, sp in enumerate(specs):
+            sp = dict(sp)
+            w, h, c, k = sp.pop("width"), sp.pop("height"), sp.pop("channels"), sp.pop("k")
+            arr[i] = make_params(w, h, c, k, storage=storage, **sp)
+            self.shapes.append((w, h, c, k))
+        self.n = n
+        self.storage = storage
+        b = C.c_void_p()
+        L.check(L.lib().pros_batch_init(arr, n, _stream_handle(stream), C.byref(b)))
+        self._b = b
+        self._frames = None
+
+    def close(self):
+        if getattr(self, "_b", None):
+            L.lib().pros_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _dims(self, s):
+        w, h, c, k = self.shapes[s]
+        return w * h, w * h * c, k
+
+    def set_state(self, s, U, y=None, labels=None, n=0):
+        P, m, k = self._dims(s)
+        Ucm = np.ascontiguousarray(np.asarray(U, np.float64).T)
+        assert Ucm.shape == (k, m)
+        yv = None if y is None else np.ascontiguousarray(np.asarray(y, np.float64))
+        lab = None if labels is None else np.ascontiguousarray(np.asarray(labels, np.uint8))
+        L.check(L.lib().pros_batch_set_state(self._b, s, _ptr(Ucm), None if yv is None else _ptr(yv),
+                                             None if lab is None else _ptr(lab), int(n)))
+
+    def get_state(self, s):
+        P, m, k = self._dims(s)
+        Ucm = np.empty((k, m), np.float64)
+        y = np.empty(k, np.float64)
+        lab = np.empty(P, np.uint8)
+        n = C.c_int64()
+        L.check(L.lib().pros_batch_get_state(self._b, s, _ptr(Ucm), _ptr(y), _ptr(lab), C.byref(n)))
+        return Ucm.T.copy(), y, lab, int(n.value)
+
+    def set_frames(self, frames):
+        """frames[s][i]: device tensor of stream s, ring slot i (all streams
+        the same ring length).  The tensors are kept alive here."""
+        ring = len(frames[0])
+        ptrs = (C.c_void_p * (self.n * ring))()
+        for s in range(self.n):
+            assert len(frames[s]) == ring
+            for i, t in enumerate(frames[s]):
+                assert t.is_cuda and t.is_contiguous() and t.numel() == self._dims(s)[1]
+                ptrs[s * ring + i] = t.data_ptr()
+        L.check(L.lib().pros_batch_set_frames(self._b, ptrs, ring))
+        self._frames = frames
+
+    def step(self):
+        L.check(L.lib().pros_batch_track(self._b))
+
+    def use_graph(self, on=True):
+        L.check(L.lib().pros_batch_use_graph(self._b, int(bool(on))))
+
+    def sync(self):
+        return L.lib().pros_batch_sync(self._b)
+
+    def mask(self, s, filtered=True):
+        P, _, _ = self._dims(s)
+        buf = np.empty(P, np.uint8)
+        L.check(L.lib().pros_batch_get_mask(self._b, s, _ptr(buf), int(filtered), 0))
+        return buf
+
+    def stats(self, s):
+        st = L.pros_stats()
+        L.check(L.lib().pros_batch_get_stats(self._b, s, C.byref(st)))
+        return dict(frame=st.frame, cg_steps=st.cg_steps, f=list(st.f[:st.cg_steps + 1]), theta=st.theta,
+                    updated=st.updated, bad_frame=st.bad_frame)
+
+    def config(self):
+        c = L.pros_batch_config()
+        L.check(L.lib().pros_batch_get_config(self._b, C.byref(c)))
+        return dict(register_budget=c.register_budget, workgroups_per_cu=c.workgroups_per_cu,
+                    tile_scale=c.tile_scale, strategy=c.strategy, workgroups=c.workgroups, rounds=c.rounds)
+
+    def configure(self, register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0):
+        c = L.pros_batch_config(register_budget, workgroups_per_cu, tile_scale, strategy, 0, 0, 0)
+        L.check(L.lib().pros_batch_configure(self._b, C.byref(c)))
+
+    def tune(self, steps=5, cache=None):
+        """Pick the fastest launch configuration by timing candidates
+        (pros_batch_tune).  With a cache path (or PROST_TUNE_CACHE), a JSON
+        file keyed by device, storage and stream shapes remembers the choice."""
+        import json
+        import os
+        import torch
+        path = cache or os.environ.get("PROST_TUNE_CACHE")
+        key = "|".join([torch.cuda.get_device_properties(0).gcnArchName, self.storage,
+                        ";".join("x".join(map(str, s)) for s in self.shapes)])
+        if path and os.path.exists(path):
+            try:
+                db = json.load(open(path))
+            except ValueError:
+                db = {}
+            if key in db:
+                self.configure(**db[key]["config"])
+                return db[key]
+        best = L.pros_batch_config()
+        ms = C.c_double()
+        L.check(L.lib().pros_batch_tune(self._b, int(steps), C.byref(best), C.byref(ms)))
+        rec = dict(config=dict(register_budget=best.register_budget, workgroups_per_cu=best.workgroups_per_cu,
+                               tile_scale=best.tile_scale, strategy=best.strategy),
+                   ms_per_step=ms.value, workgroups=best.workgroups, rounds=best.rounds)
+        if path:
+            db = {}
+            if os.path.exists(path):
+                try:
+                    db = json.load(open(path))
+                except ValueError:
+                    db = {}
+            db[key] = rec
+            tmp = path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(db, f, indent=1)
+            os.replace(tmp, path)
+        return rec

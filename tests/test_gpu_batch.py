@@ -1,0 +1,198 @@
+"""GPU parity of the batched form: uneven streams advanced by one persistent
+launch per step, each stream against its own float64 oracle run."""
+import numpy as np
+import pytest
+
+from gpu_common import GUARD, TOL_U, TOL_Y, f32, say
+from oracle import prost_oracle as O
+from synth import video as V
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(80, 60, 1, 5), (64, 48, 3, 10), (160, 120, 3, 15), (37, 23, 3, 16), (33, 17, 2, 1)]
+
+
+def _streams(shapes=SHAPES, warm=4):
+    out = []
+    for i, (W, H, Cc, k) in enumerate(shapes):
+        spec = V.VideoSpec(W, H, Cc, rank=min(k, 3), seed=40, stream=i, noise=0.01, fg_kind="rects",
+                           fg_count=2, fg_density=0.08)
+        sv = V.SyntheticVideo(spec)
+        prm = O.Params(W, H, Cc, k=k, mu=1e-3, i_init=20)
+        st = O.initial_state(V.initial_subspace(prm.m, k, 40, i), prm.P)
+        for n in range(warm):
+            st, _ = O.track_frame(st, f32(sv.frame(n)), prm)
+        out.append((sv, prm, st))
+    return out
+
+
+def _specs(streams):
+    return [dict(width=p.width, height=p.height, channels=p.channels, k=p.k, mu=p.mu, i_init=p.i_init)
+            for _, p, _ in streams]
+
+
+def _frames_tensor(streams, n0, ring, dtype="f32"):
+    import torch
+    from paper_1302_2073_amd.tracker import bf16_bits
+    fr = []
+    for sv, prm, _ in streams:
+        row = []
+        for i in range(ring):
+            x = sv.frame(n0 + i)
+            if dtype == "f32":
+                row.append(torch.from_numpy(x.astype(np.float32)).cuda())
+            else:
+                row.append(torch.from_numpy(bf16_bits(x).view(np.int16)).cuda().view(torch.bfloat16))
+        fr.append(row)
+    return fr
+
+
+def _check_stream(bt, s, prm, start_state, x64):
+    exp, info = O.track_frame(start_state, x64, prm)
+    U1, y1, l1, n1 = bt.get_state(s)
+    band = O.band_pixels(exp.U, x64, exp.y, prm.thr, prm.channels, GUARD)
+    y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
+    U_rel = np.linalg.norm(U1 - exp.U) / np.linalg.norm(exp.U)
+    mism = int(np.sum((l1 != exp.labels) & ~band))
+    mask = bt.mask(s)
+    say(f"  stream {s} {prm.width}x{prm.height}x{prm.channels} k={prm.k}: y {y_rel:.1e} U {U_rel:.1e} "
+        f"labels outside band {mism} (band {int(band.sum())})")
+    assert n1 == exp.n
+    assert y_rel <= TOL_Y and U_rel <= TOL_U and mism == 0
+    assert np.array_equal(mask, O.median3x3(l1, prm.height, prm.width))
+    return exp
+
+
+def _load(bt, streams):
+    starts = []
+    for s, (sv, prm, st) in enumerate(streams):
+        bt.set_state(s, st.U, st.y, st.labels, st.n)
+        U0, y0, l0, n0 = bt.get_state(s)
+        starts.append(O.State(U0, y0, l0, l0.copy(), n0))
+    return starts
+
+
+@pytest.mark.parametrize("cfg", [dict(register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0),
+                                 dict(register_budget=64, workgroups_per_cu=1, tile_scale=0.5, strategy=1)])
+def test_batch_step_matches_oracle_per_stream(cfg):
+    from paper_1302_2073_amd.tracker import BatchTracker
+    streams = _streams()
+    with BatchTracker(_specs(streams)) as bt:
+        bt.configure(**cfg)
+        say("  config", bt.config())
+        fr = _frames_tensor(streams, 4, 2)
+        bt.set_frames(fr)
+        starts = _load(bt, streams)
+        bt.step()
+        assert bt.sync() == 0
+        nxt = []
+        for s, (sv, prm, st) in enumerate(streams):
+            nxt.append(_check_stream(bt, s, prm, starts[s], f32(sv.frame(4))))
+        # second step reads ring slot 1, continuing from the GPU's own state
+        starts2 = []
+        for s in range(len(streams)):
+            U0, y0, l0, n0 = bt.get_state(s)
+            starts2.append(O.State(U0, y0, l0, l0.copy(), n0))
+        bt.step()
+        for s, (sv, prm, st) in enumerate(streams):
+            _check_stream(bt, s, prm, starts2[s], f32(sv.frame(5)))
+
+
+def test_graph_replay_is_bitwise_equal_to_launches():
+    from paper_1302_2073_amd.tracker import BatchTracker
+    streams = _streams(SHAPES[:3])
+    res = []
+    for graph in (False, True):
+        with BatchTracker(_specs(streams)) as bt:
+            bt.set_frames(_frames_tensor(streams, 4, 3))
+            _load(bt, streams)
+            bt.use_graph(graph)
+            for _ in range(4):
+                bt.step()
+                assert bt.sync() == 0     # eager work between replays
+            res.append([bt.get_state(s) for s in range(len(streams))])
+    for a, b in zip(*res):
+        for x, y in zip(a, b):
+            assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_tuner_restores_state_and_keeps_parity(tmp_path):
+    from paper_1302_2073_amd.tracker import BatchTracker
+    streams = _streams(SHAPES[:4])
+    with BatchTracker(_specs(streams)) as bt:
+        bt.set_frames(_frames_tensor(streams, 4, 1))
+        starts = _load(bt, streams)
+        before = [bt.get_state(s) for s in range(len(streams))]
+        rec = bt.tune(steps=2, cache=str(tmp_path / "tune.json"))
+        say("  tuned", rec)
+        after = [bt.get_state(s) for s in range(len(streams))]
+        for a, b in zip(before, after):
+            for x, y in zip(a, b):
+                assert np.array_equal(np.asarray(x), np.asarray(y))
+        bt.step()
+        for s, (sv, prm, st) in enumerate(streams):
+            _check_stream(bt, s, prm, starts[s], f32(sv.frame(4)))
+        rec2 = bt.tune(steps=2, cache=str(tmp_path / "tune.json"))   # from the cache
+        assert rec2["config"] == rec["config"]
+
+
+def test_batch_bf16_matches_oracle():
+    from paper_1302_2073_amd.tracker import BatchTracker
+
+    def rne(a):
+        f = np.asarray(a, np.float32)
+        u = f.view(np.uint32).astype(np.uint64)
+        return ((((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)).view(np.float32).astype(np.float64)
+
+    streams = _streams(SHAPES[:4])
+    with BatchTracker(_specs(streams), storage="bf16") as bt:
+        bt.set_frames(_frames_tensor(streams, 4, 1, "bf16"))
+        starts = _load(bt, streams)
+        bt.step()
+        for s, (sv, prm, st) in enumerate(streams):
+            x = rne(sv.frame(4))
+            exp, _ = O.track_frame(starts[s], x, prm)
+            U1, y1, l1, n1 = bt.get_state(s)
+            y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
+            e = rne(exp.U)
+            ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(e), 1e-38))) - 7)
+            over = int(np.sum(np.abs(U1 - e) > ulp * 1.0000001 + 1e-45))
+            say(f"  bf16 stream {s}: y {y_rel:.1e}, U entries beyond 1 ulp: {over}")
+            assert y_rel <= 1e-4 and over == 0
+
+
+def test_mixed_streams_workload_parity_sample():
+    """Four streams of the 64-stream mixed workload (one of each resolution
+    plus the largest k) inside the full 64-stream launch."""
+    from paper_1302_2073_amd.tracker import BatchTracker
+    wls = V.mixed_streams(64)
+    check = []
+    seen = set()
+    for i, wl in enumerate(wls):
+        key = (wl.video.width, wl.k)
+        if wl.video.width not in {w for w, _ in seen} or (wl.k == 15 and 15 not in {k for _, k in seen}):
+            check.append(i)
+            seen.add(key)
+        if len(check) == 4:
+            break
+    specs = [dict(width=w.video.width, height=w.video.height, channels=3, k=w.k, mu=w.mu) for w in wls]
+    import torch
+    with BatchTracker(specs, storage="f32") as bt:
+        say("  config", bt.config())
+        frames = []
+        svs = []
+        for i, wl in enumerate(wls):
+            sv = V.SyntheticVideo(wl.video)
+            svs.append(sv)
+            frames.append([torch.from_numpy(sv.frame(0).astype(np.float32)).cuda()])
+            bt.set_state(i, V.initial_subspace(wl.video.m, wl.k, 4, i))
+        bt.set_frames(frames)
+        bt.step()
+        assert bt.sync() == 0
+        for i in check:
+            wl = wls[i]
+            v = wl.video
+            prm = O.Params(v.width, v.height, 3, k=wl.k, mu=wl.mu)
+            U0 = V.initial_subspace(v.m, wl.k, 4, i).astype(np.float32).astype(np.float64)
+            st = O.initial_state(U0, prm.P)
+            _check_stream(bt, i, prm, st, f32(svs[i].frame(0)))

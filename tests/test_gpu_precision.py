@@ -1,0 +1,117 @@
+"""Precision form: bfloat16 storage of U and frames with float32 arithmetic,
+and the float64 re-orthonormalisation of U on the GPU."""
+import numpy as np
+import pytest
+
+from gpu_common import GUARD, compare_step, oracle_params, say, tracker_kwargs
+from oracle import prost_oracle as O
+from synth import video as V
+
+pytestmark = pytest.mark.gpu
+
+
+def rne_bf16(a):
+    f = np.asarray(a, np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_ulp(a):
+    a = np.abs(np.asarray(a, np.float64))
+    e = np.floor(np.log2(np.maximum(a, 1e-38)))
+    return np.exp2(e - 7)
+
+
+def _tracker(prm, storage):
+    from paper_1302_2073_amd import Tracker
+    return Tracker(prm.width, prm.height, prm.channels, prm.k, **tracker_kwargs(prm, storage))
+
+
+def _bf16_step(name, frame, upto):
+    from gpu_common import oracle_trajectory
+    wl, prm, sv, states = oracle_trajectory(name, upto)
+    st = states[frame]
+    x = rne_bf16(sv.frame(frame))
+    with _tracker(prm, "bf16") as trk:
+        rep = compare_step(trk, prm, st, x, storage="bf16")
+    exp = rne_bf16(rep["exp"].U)
+    diff = np.abs(rep["U1"] - exp)
+    ulp = np.maximum(bf16_ulp(exp), bf16_ulp(rep["U1"]))
+    over = int(np.sum(diff > ulp * (1 + 1e-12)))
+    n1ulp = int(np.sum(diff > 0))
+    say(f"  bf16 {name} frame {frame}: y_rel={rep['y_rel']:.2e} U entries off by 1 ulp: {n1ulp} "
+        f"(> 1 ulp: {over}) of {diff.size}; label mismatches outside band {rep['lab_mismatch_outside_band']} "
+        f"band {rep['band']}")
+    assert rep["n"] == rep["n_exp"]
+    assert rep["y_rel"] <= 1e-4
+    assert over == 0
+    assert rep["lab_mismatch_outside_band"] == 0
+    assert rep["mask_vs_median_of_gpu_labels"] == 0
+
+
+@pytest.mark.parametrize("frame", [0, 1, 40, 150])
+def test_bf16_small_gray(frame):
+    _bf16_step("small_gray", frame, 150)
+
+
+@pytest.mark.parametrize("frame", [0, 2])
+def test_bf16_vga_rgb(frame):
+    _bf16_step("vga_rgb", frame, 2)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("shape", [(80, 60, 1, 5), (160, 120, 3, 15), (37, 23, 3, 16)])
+def test_reorthonormalize_matches_polar_factor(shape, storage):
+    W, H, Cc, k = shape
+    m = W * H * Cc
+    rng = np.random.default_rng([W, k])
+    U = V.random_orthonormal(m, k, rng)
+    U = U + 3e-3 * rng.standard_normal((m, k)) / np.sqrt(m)
+    y = rng.standard_normal(k)
+    prm = O.Params(W, H, Cc, k=k)
+    with _tracker(prm, storage) as trk:
+        trk.set_state(U, y, None, 0)
+        U0, y0, _, _ = trk.get_state()
+        trk.reorthonormalize()
+        U1, y1, _, _ = trk.get_state()
+    Ul, Gp = O.lowdin(U0)
+    yl = Gp @ y0
+    orth0, orth1 = O.orthonormality_error(U0), O.orthonormality_error(U1)
+    err = np.linalg.norm(U1 - Ul) / np.linalg.norm(Ul)
+    say(f"  reorth {shape} {storage}: ||U^T U - I|| {orth0:.2e} -> {orth1:.2e}; vs polar {err:.2e}; "
+        f"y {np.linalg.norm(y1 - yl) / np.linalg.norm(yl):.2e}")
+    if storage == "f32":
+        assert err <= 1e-6 and orth1 <= 1e-5
+    else:
+        diff = np.abs(U1 - rne_bf16(Ul))
+        assert np.all(diff <= np.maximum(bf16_ulp(Ul), bf16_ulp(U1)) * (1 + 1e-12))
+    assert np.linalg.norm(y1 - yl) / np.linalg.norm(yl) <= 1e-12
+
+
+def test_bf16_free_running_with_reorth_reports_drift():
+    """The literal bfloat16 tracker over 150 frames of the 80x60 workload with
+    re-orthonormalisation every 50 frames, next to the float64 oracle:
+    orthonormality is restored at every re-orthonormalisation and the labels
+    stay close (<= 0.5% disagreement)."""
+    from gpu_common import oracle_trajectory
+    wl, prm, sv, states = oracle_trajectory("small_gray", 150)
+    kw = tracker_kwargs(prm, "bf16")
+    kw["reorth_every"] = 50
+    from paper_1302_2073_amd import Tracker
+    from paper_1302_2073_amd.tracker import bf16_bits
+    worst = 0.0
+    with Tracker(prm.width, prm.height, prm.channels, prm.k, **kw) as trk:
+        trk.set_state(states[0].U, states[0].y, states[0].labels, 0)
+        for n in range(150):
+            trk.track(bf16_bits(sv.frame(n)))
+            if n % 25 == 24 or n == 149:
+                U, y, lab, _ = trk.get_state()
+                ref = states[n + 1]
+                dis = float(np.mean(lab != ref.labels))
+                worst = max(worst, dis)
+                say(f"  frame {n}: angle {O.principal_angles(ref.U, U).max():.2e} "
+                    f"orth {O.orthonormality_error(U):.2e} labels {dis:.4%}")
+                if n % 50 == 49:
+                    assert O.orthonormality_error(U) < 5e-3
+    assert worst <= 0.005
