@@ -15,10 +15,28 @@
 #include "prost_host.hpp"
 
 namespace prost {
-const void* batch_kernel_f32_b64();
-const void* batch_kernel_f32_b128();
-const void* batch_kernel_bf16_b64();
-const void* batch_kernel_bf16_b128();
+const void* batch_kernel_k2(int, int);
+const void* batch_kernel_k4(int, int);
+const void* batch_kernel_k5(int, int);
+const void* batch_kernel_k8(int, int);
+const void* batch_kernel_k10(int, int);
+const void* batch_kernel_k12(int, int);
+const void* batch_kernel_k15(int, int);
+const void* batch_kernel_k16(int, int);
+
+const void* batch_kernel_ptr(int bf16, int K, int budget) {
+  switch (K) {
+    case 2: return batch_kernel_k2(bf16, budget);
+    case 4: return batch_kernel_k4(bf16, budget);
+    case 5: return batch_kernel_k5(bf16, budget);
+    case 8: return batch_kernel_k8(bf16, budget);
+    case 10: return batch_kernel_k10(bf16, budget);
+    case 12: return batch_kernel_k12(bf16, budget);
+    case 15: return batch_kernel_k15(bf16, budget);
+    case 16: return batch_kernel_k16(bf16, budget);
+    default: return nullptr;
+  }
+}
 }  // namespace prost
 
 using prost::BatchItem;
@@ -27,26 +45,15 @@ using prost::FrameArgs;
 #define fail prost_host::set_error
 
 namespace {
-
 constexpr int kBudgets[] = {64, 128};
-
-const void* batch_fn(int storage, int budget) {
-  using namespace prost;
-  if (storage == PROS_BF16) return budget == 64 ? batch_kernel_bf16_b64() : batch_kernel_bf16_b128();
-  return budget == 64 ? batch_kernel_f32_b64() : batch_kernel_f32_b128();
-}
-
-int batch_nr(int budget, int k) {
-  const int q = budget / k;
-  return q >= 16 ? 16 : q >= 12 ? 12 : q >= 8 ? 8 : 4;
-}
-
 }  // namespace
 
 struct pros_batch {
   int n = 0;
   int storage = PROS_F32;
+  int kclass = 16;               // compiled subspace class covering every stream's k
   hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;   // graphs are captured here, replayed on `stream`
   int num_cu = 0;
   std::vector<pros_handle*> hs;
   // launch
@@ -81,6 +88,7 @@ static void drop_graph(pros_batch* b) {
 static void free_batch(pros_batch* b) {
   if (!b) return;
   drop_graph(b);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   for (pros_handle* h : b->hs) prost_host::free_handle(h);
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_items) (void)hipFree(b->d_items);
@@ -118,7 +126,8 @@ static pros_status build_schedule(pros_batch* b) {
 
 // (Re)create the per-stream tile configuration, descriptors and schedule.
 static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy) {
-  const void* f = batch_fn(b->storage, budget);
+  const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget);
+  if (!f) return fail(PROS_EUNSUPPORTED, "no batch kernel for k class %d", b->kclass);
   int occ = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0);
   if (e != hipSuccess) return fail(PROS_EHIP, "occupancy query: %s", hipGetErrorString(e));
@@ -126,7 +135,7 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
   const int wpc = std::min(occ, wg_per_cu);
   const int nwg = wpc * b->num_cu;
   for (pros_handle* h : b->hs) {
-    const int NR = batch_nr(budget, h->k);
+    const int NR = prost::batch_nr(budget, b->kclass);
     int tpw = (int)std::floor(prost::kBlock * NR * tile_scale / h->C);
     tpw = std::max(1, std::min(tpw, prost::kBlock * NR / h->C));
     const int G = (h->P + tpw - 1) / tpw;
@@ -169,12 +178,12 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
   return PROS_OK;
 }
 
-static pros_status launch(pros_batch* b) {
+static pros_status launch(pros_batch* b, hipStream_t on) {
   FrameArgs* d = b->d_descs;
   BatchItem* it = b->d_items;
   int rounds = b->rounds;
   void* args[] = {&d, &it, &rounds};
-  hipError_t e = hipLaunchCooperativeKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, b->stream);
+  hipError_t e = hipLaunchCooperativeKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on);
   if (e != hipSuccess) {
     b->broken = true;
     return fail(PROS_EHIP, "batch kernel launch: %s", hipGetErrorString(e));
@@ -224,9 +233,17 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
     free_batch(b);
     return fail(PROS_EHIP, "device query: %s", hipGetErrorString(e));
   }
+  int kmax = 1;
+  for (int s = 0; s < n; ++s) kmax = std::max(kmax, (int)per_stream[s].k);
+  b->kclass = prost::batch_class(kmax);
+  e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return fail(PROS_EHIP, "capture stream: %s", hipGetErrorString(e));
+  }
   for (int s = 0; s < n; ++s) {
     pros_handle* h = nullptr;
-    const int NR = batch_nr(128, per_stream[s].k);
+    const int NR = prost::batch_nr(128, b->kclass);
     const int tpw = prost::kBlock * NR / per_stream[s].channels;
     const int P = per_stream[s].width * per_stream[s].height;
     pros_status st = prost_host::create_handle(&per_stream[s], b->stream, NR, tpw, (P + tpw - 1) / tpw, &h);
@@ -306,11 +323,11 @@ pros_status pros_batch_track(pros_batch* b) {
     if (!h->state_set) return fail(PROS_ESTATE, "set every stream's U before the first batch step");
   if (b->use_graph) {
     if (!b->gexec) {
-      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return fail(PROS_EHIP, "begin capture: %s", hipGetErrorString(e));
-      pros_status ls = launch(b);
+      pros_status ls = launch(b, b->capture_stream);
       hipGraph_t g = nullptr;
-      e = hipStreamEndCapture(b->stream, &g);
+      e = hipStreamEndCapture(b->capture_stream, &g);
       if (ls != PROS_OK) return ls;
       if (e != hipSuccess) {
         b->broken = true;
@@ -329,7 +346,7 @@ pros_status pros_batch_track(pros_batch* b) {
       return fail(PROS_EHIP, "graph launch: %s", hipGetErrorString(e));
     }
   } else {
-    st = launch(b);
+    st = launch(b, b->stream);
     if (st != PROS_OK) return st;
   }
   for (pros_handle* h : b->hs) ++h->submitted;
@@ -477,10 +494,10 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
         for (int strat = 0; strat < 2; ++strat) {
           if (configure(b, budget, wpc, sc, strat) != PROS_OK) continue;   // does not fit
           if (b->wg_per_cu != wpc) continue;                               // duplicate of a smaller grid
-          st = launch(b);                                                   // warm-up
+          st = launch(b, b->stream);                                        // warm-up
           for (int i = 0; i < steps && st == PROS_OK; ++i) {
             if (i == 0) (void)hipEventRecord(e0, b->stream);
-            st = launch(b);
+            st = launch(b, b->stream);
           }
           (void)hipEventRecord(e1, b->stream);
           hipError_t e = hipEventSynchronize(e1);

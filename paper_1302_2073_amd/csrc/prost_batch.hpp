@@ -1,5 +1,5 @@
-// Batched form: many independent video streams (uneven resolution and k)
-// advance by one frame each in ONE persistent cooperative launch.
+// Batched form: many independent video streams advance by one frame each in
+// ONE persistent cooperative launch.
 //
 // Every stream is split into workgroup tiles exactly as in the single-stream
 // kernel and owns a gang of workgroups for the frame's gang-wide reductions.
@@ -8,6 +8,10 @@
 // Gangs of one round are disjoint sets of workgroups, so every gang is
 // resident; streams of a round do not wait for each other, and a workgroup
 // moves to its next item as soon as its current stream's frame is done.
+//
+// One kernel serves every stream with k <= K: columns k..K-1 of the register
+// tile are zero, which leaves the method's arithmetic unchanged (their
+// gradient entries, directions, y entries and geodesic components are all 0).
 #pragma once
 
 #include "prost_frame.hpp"
@@ -19,41 +23,32 @@ struct BatchItem {
   int tile;
 };
 
-// Register rows per thread for subspace dimension K at a register budget of
-// about BUDGET floats of U per thread.
-template <int BUDGET>
-struct BatchNR {
-  template <int K>
-  static constexpr int nr() {
-    return (BUDGET / K >= 16) ? 16 : (BUDGET / K >= 12) ? 12 : (BUDGET / K >= 8) ? 8 : 4;
-  }
-};
+// Subspace-dimension classes with a batch kernel, and register rows per
+// thread for a budget of about `budget` floats of U per thread.
+constexpr int kBatchClasses[] = {2, 4, 5, 8, 10, 12, 15, 16};
+constexpr int kNumBatchClasses = 8;
 
-template <typename TS, int BUDGET>
-__device__ __forceinline__ bool batch_dispatch(const FrameArgs& a, int tile, FrameSmem& sm) {
-  using NRs = BatchNR<BUDGET>;
-  switch (a.k) {
-#define PROST_BATCH_CASE(KK) \
-    case KK: return frame_tile<KK, NRs::template nr<KK>(), TS>(a, tile, sm);
-    PROST_BATCH_CASE(1) PROST_BATCH_CASE(2) PROST_BATCH_CASE(3) PROST_BATCH_CASE(4)
-    PROST_BATCH_CASE(5) PROST_BATCH_CASE(6) PROST_BATCH_CASE(7) PROST_BATCH_CASE(8)
-    PROST_BATCH_CASE(9) PROST_BATCH_CASE(10) PROST_BATCH_CASE(11) PROST_BATCH_CASE(12)
-    PROST_BATCH_CASE(13) PROST_BATCH_CASE(14) PROST_BATCH_CASE(15) PROST_BATCH_CASE(16)
-#undef PROST_BATCH_CASE
-    default: return true;
-  }
+__host__ __device__ constexpr int batch_nr(int budget, int K) {
+  return (budget / K >= 16) ? 16 : (budget / K < 1 ? 1 : budget / K);
 }
 
-template <typename TS, int BUDGET>
-__global__ __launch_bounds__(kBlock) void batch_kernel(const FrameArgs* __restrict__ descs,
+__host__ __device__ constexpr int batch_class(int k) {
+  return k <= 2 ? 2 : k <= 4 ? 4 : k <= 5 ? 5 : k <= 8 ? 8 : k <= 10 ? 10 : k <= 12 ? 12 : k <= 15 ? 15 : 16;
+}
+
+template <typename TS, int K, int NR>
+__global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __restrict__ descs,
                                                        const BatchItem* __restrict__ items, int rounds) {
   __shared__ FrameSmem sm;
   for (int r = 0; r < rounds; ++r) {
     const BatchItem it = items[(size_t)r * gridDim.x + blockIdx.x];
     if (it.stream < 0) continue;
     const FrameArgs a = descs[it.stream];
-    if (!batch_dispatch<TS, BUDGET>(a, it.tile, sm)) return;
+    if (!frame_tile<K, NR, TS>(a, it.tile, sm)) return;
   }
 }
+
+// Kernel for (storage, class K, budget); nullptr if not built.
+const void* batch_kernel_ptr(int storage_bf16, int K, int budget);
 
 }  // namespace prost

@@ -1,0 +1,13 @@
+// Batched-form kernels for subspace class K = 15 (both storage types, both
+// register budgets).
+#include "prost_batch.hpp"
+
+namespace prost {
+const void* batch_kernel_k15(int storage_bf16, int budget) {
+  if (storage_bf16)
+    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr(64, 15)>
+                        : (const void*)&batch_kernel<uint16_t, 15, batch_nr(128, 15)>;
+  return budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15)>
+                      : (const void*)&batch_kernel<float, 15, batch_nr(128, 15)>;
+}
+}  // namespace prost

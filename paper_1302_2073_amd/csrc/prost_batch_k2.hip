@@ -1,0 +1,13 @@
+// Batched-form kernels for subspace class K = 2 (both storage types, both
+// register budgets).
+#include "prost_batch.hpp"
+
+namespace prost {
+const void* batch_kernel_k2(int storage_bf16, int budget) {
+  if (storage_bf16)
+    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 2, batch_nr(64, 2)>
+                        : (const void*)&batch_kernel<uint16_t, 2, batch_nr(128, 2)>;
+  return budget == 64 ? (const void*)&batch_kernel<float, 2, batch_nr(64, 2)>
+                      : (const void*)&batch_kernel<float, 2, batch_nr(128, 2)>;
+}
+}  // namespace prost

@@ -1,0 +1,13 @@
+// Batched-form kernels for subspace class K = 5 (both storage types, both
+// register budgets).
+#include "prost_batch.hpp"
+
+namespace prost {
+const void* batch_kernel_k5(int storage_bf16, int budget) {
+  if (storage_bf16)
+    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 5, batch_nr(64, 5)>
+                        : (const void*)&batch_kernel<uint16_t, 5, batch_nr(128, 5)>;
+  return budget == 64 ? (const void*)&batch_kernel<float, 5, batch_nr(64, 5)>
+                      : (const void*)&batch_kernel<float, 5, batch_nr(128, 5)>;
+}
+}  // namespace prost

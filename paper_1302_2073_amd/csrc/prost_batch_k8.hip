@@ -1,0 +1,13 @@
+// Batched-form kernels for subspace class K = 8 (both storage types, both
+// register budgets).
+#include "prost_batch.hpp"
+
+namespace prost {
+const void* batch_kernel_k8(int storage_bf16, int budget) {
+  if (storage_bf16)
+    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 8, batch_nr(64, 8)>
+                        : (const void*)&batch_kernel<uint16_t, 8, batch_nr(128, 8)>;
+  return budget == 64 ? (const void*)&batch_kernel<float, 8, batch_nr(64, 8)>
+                      : (const void*)&batch_kernel<float, 8, batch_nr(128, 8)>;
+}
+}  // namespace prost

@@ -75,10 +75,13 @@ __device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameAr
   double t[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) t[i] = 0.0;
+  // plain (cached) loads: the barrier's acquire fence invalidated stale lines,
+  // so the first workgroup of each XCD pulls the partials into its L2 and the
+  // others hit there
   for (int w = threadIdx.x; w < a.G; w += kBlock) {
+    const double* src = buf + (size_t)w * kSlot;
 #pragma unroll
-    for (int i = 0; i < L; ++i)
-      t[i] += __hip_atomic_load(&buf[(size_t)w * kSlot + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = 0; i < L; ++i) t[i] += src[i];
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) {
@@ -143,7 +146,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   const bool lead = (tile == 0);
 
   if (tid < K) {
-    const double yv = a.y[tid];
+    const double yv = (tid < a.k) ? a.y[tid] : 0.0;
     ks.y[tid] = yv;
     ks.yf[tid] = (float)yv;
   }
@@ -174,7 +177,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       float acc = ld_elem(xg, e);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        u[s][j] = ld_elem(Ug, (long long)j * a.ldU + e);
+        if (j < a.k) u[s][j] = ld_elem(Ug, (long long)j * a.ldU + e);   // columns >= k stay 0
         acc = fmaf(-u[s][j], ks.yf[j], acc);
       }
       r[s] = acc;
@@ -339,7 +342,8 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
           }
           const float coef = fmaf(cm1, uv, -sz * (cw[s] - ua));
 #pragma unroll
-          for (int j = 0; j < K; ++j) st_elem((TS*)Uw, (long long)j * a.ldU + eix[s], fmaf(coef, ks.vf[j], u[s][j]));
+          for (int j = 0; j < K; ++j)
+            if (j < a.k) st_elem((TS*)Uw, (long long)j * a.ldU + eix[s], fmaf(coef, ks.vf[j], u[s][j]));
           if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
         }
         s_flag[q] = (fabsf(rl) >= a.delta) ? 1 : 0;
@@ -389,7 +393,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     __hip_atomic_store(&a.sync[1], base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (lead && !bad && tid < K) a.y[tid] = ks.y[tid];
+  if (lead && !bad && tid < a.k) a.y[tid] = ks.y[tid];
   __syncthreads();   // shared scratch may be reused by the next tile
   return true;
 }
