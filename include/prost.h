@@ -105,6 +105,7 @@ typedef struct pros_stats {
   double theta;                  /* geodesic angle sigma * t */
   double zeta;                   /* ||pi(eta)|| */
   double nu;                     /* ||y|| */
+  int64_t fg_pixels;             /* pixels labelled foreground (raw labels) */
 } pros_stats;
 
 typedef struct pros_handle pros_handle;
@@ -173,7 +174,7 @@ typedef struct pros_launch_info {
   int32_t rows_per_thread;   /* register-resident rows of U per thread */
   int32_t pixels_per_wg;     /* pixels of one workgroup tile */
   int32_t barriers_per_frame;/* gang-wide reductions per frame */
-  int32_t reserved;
+  int32_t sync_mode;         /* 0: counter barrier, 1: tagged gather/broadcast */
 } pros_launch_info;
 PROS_API pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out);
 
@@ -196,9 +197,9 @@ typedef struct pros_batch_config {
   int32_t workgroups_per_cu; /* resident workgroups per CU used by the launch */
   double tile_scale;         /* (0, 1]: fraction of the register tile each workgroup fills */
   int32_t strategy;          /* 0: gangs packed by decreasing size, 1: in stream order */
+  int32_t sync_mode;         /* gang exchange, as in pros_set_launch */
   int32_t workgroups;        /* out: resident workgroups of the launch */
   int32_t rounds;            /* out: rounds of the schedule */
-  int32_t reserved;
 } pros_batch_config;
 
 /* Create a batch of n streams (per_stream[0..n-1]; reorth_every must be 0,
@@ -264,6 +265,15 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
                             int32_t m, int32_t k, int32_t B, int32_t cost, float p, const float* gout,
                             float* dX, float* dU, float* dY, float* dmu,
                             void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Launch tuning of a single-stream handle: rows_per_thread (0 = automatic,
+ * else 1, 2, 4, 8 or 16; the frame's pixels must fit the resident
+ * workgroups) and the gang exchange used for the frame's reductions:
+ * 0 = one arrival counter per gang and every workgroup reading all partial
+ * sums, 1 = epoch-tagged partial sums gathered by the gang's first
+ * workgroup and broadcast back (default).  Results are identical.
+ * Synchronises. */
+PROS_API pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode);
 
 /* Text for a status code (static storage). */
 PROS_API const char* pros_strerror(pros_status s);

@@ -48,19 +48,19 @@ class pros_stats(C.Structure):
         ("f", C.c_double * (PROS_MAX_CG + 1)), ("alpha", C.c_double * PROS_MAX_CG),
         ("beta", C.c_double * PROS_MAX_CG),
         ("t", C.c_double), ("sigma", C.c_double), ("theta", C.c_double),
-        ("zeta", C.c_double), ("nu", C.c_double),
+        ("zeta", C.c_double), ("nu", C.c_double), ("fg_pixels", C.c_int64),
     ]
 
 
 class pros_launch_info(C.Structure):
     _fields_ = [("workgroups", C.c_int32), ("threads", C.c_int32), ("rows_per_thread", C.c_int32),
-                ("pixels_per_wg", C.c_int32), ("barriers_per_frame", C.c_int32), ("reserved", C.c_int32)]
+                ("pixels_per_wg", C.c_int32), ("barriers_per_frame", C.c_int32), ("sync_mode", C.c_int32)]
 
 
 class pros_batch_config(C.Structure):
     _fields_ = [("register_budget", C.c_int32), ("workgroups_per_cu", C.c_int32), ("tile_scale", C.c_double),
-                ("strategy", C.c_int32), ("workgroups", C.c_int32), ("rounds", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("strategy", C.c_int32), ("sync_mode", C.c_int32), ("workgroups", C.c_int32),
+                ("rounds", C.c_int32)]
 
 
 class ProstError(RuntimeError):
@@ -85,6 +85,7 @@ _SIGS = {
     "pros_sync": (C.c_int, [C.c_void_p]),
     "pros_reorthonormalize": (C.c_int, [C.c_void_p]),
     "pros_get_launch_info": (C.c_int, [C.c_void_p, C.POINTER(pros_launch_info)]),
+    "pros_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "pros_batch_init": (C.c_int, [C.POINTER(pros_params), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pros_batch_destroy": (None, [C.c_void_p]),
     "pros_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),

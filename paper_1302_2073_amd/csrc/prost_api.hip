@@ -220,7 +220,7 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
   INIT_TRY(hipMalloc((void**)&h->y, sizeof(double) * PROS_MAX_K));
   INIT_TRY(hipMalloc((void**)&h->nframe, sizeof(long long)));
   INIT_TRY(hipMalloc((void**)&h->stats, sizeof(pros_stats)));
-  INIT_TRY(hipMalloc((void**)&h->part, sizeof(double) * 2 * (size_t)h->G * prost::kSlot));
+  INIT_TRY(hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)h->G + prost::kReplicas) * prost::kSlot));
   INIT_TRY(hipMalloc((void**)&h->sync, 64));
   INIT_TRY(hipMemsetAsync(h->U, 0, es * (size_t)h->ldU * h->k, h->stream));
   INIT_TRY(hipMemsetAsync(h->lab, 0, (size_t)h->P, h->stream));
@@ -416,6 +416,7 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.labels_after_update = p.labels_after_update;
   a.weights_from_filtered = p.weights_from_filtered;
   a.timeout = h->timeout_ticks;
+  a.sync_mode = h->sync_mode;
   return a;
 }
 
@@ -511,7 +512,32 @@ pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
   out->rows_per_thread = h->NR;
   out->pixels_per_wg = h->tpw;
   out->barriers_per_frame = 2 * h->prm.cg_iters + 2;
-  out->reserved = 0;
+  out->sync_mode = h->sync_mode;
+  return PROS_OK;
+}
+
+pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (sync_mode != 0 && sync_mode != 1) return fail(PROS_EINVAL, "sync_mode must be 0 or 1");
+  if (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 && rows_per_thread != 4 &&
+      rows_per_thread != 8 && rows_per_thread != 16)
+    return fail(PROS_EINVAL, "rows_per_thread must be 0 (automatic), 1, 2, 4, 8 or 16");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int oldG = h->G;
+  st = choose_launch(h, rows_per_thread);
+  if (st != PROS_OK) return st;
+  if (h->G > oldG) {
+    (void)hipFree(h->part);
+    h->part = nullptr;
+    hipError_t e = hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)h->G + prost::kReplicas) * prost::kSlot);
+    if (e != hipSuccess) {
+      h->broken = true;
+      h->broken_status = PROS_ENOMEM;
+      return fail(PROS_ENOMEM, "partials: %s", hipGetErrorString(e));
+    }
+  }
+  h->sync_mode = sync_mode;
   return PROS_OK;
 }
 

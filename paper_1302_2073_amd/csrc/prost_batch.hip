@@ -62,6 +62,7 @@ struct pros_batch {
   int nwg = 0;
   int rounds = 0;
   int strategy = 0;
+  int sync_mode = 1;
   double tile_scale = 1.0;
   const void* kfn = nullptr;
   FrameArgs* d_descs = nullptr;
@@ -125,7 +126,7 @@ static pros_status build_schedule(pros_batch* b) {
 }
 
 // (Re)create the per-stream tile configuration, descriptors and schedule.
-static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy) {
+static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy, int sync_mode) {
   const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget);
   if (!f) return fail(PROS_EUNSUPPORTED, "no batch kernel for k class %d", b->kclass);
   int occ = 0;
@@ -144,12 +145,13 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
     if (G != h->G) {   // partial buffer sized by the gang
       (void)hipFree(h->part);
       h->part = nullptr;
-      e = hipMalloc((void**)&h->part, sizeof(double) * 2 * (size_t)G * prost::kSlot);
+      e = hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)G + prost::kReplicas) * prost::kSlot);
       if (e != hipSuccess) return fail(PROS_ENOMEM, "partials: %s", hipGetErrorString(e));
     }
     h->NR = NR;
     h->tpw = tpw;
     h->G = G;
+    h->sync_mode = sync_mode;
   }
   b->budget = budget;
   b->wg_per_cu = wpc;
@@ -157,6 +159,7 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
   b->kfn = f;
   b->tile_scale = tile_scale;
   b->strategy = strategy;
+  b->sync_mode = sync_mode;
   pros_status st = build_schedule(b);
   if (st != PROS_OK) return st;
   b->descs.resize(b->n);
@@ -259,7 +262,7 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
     free_batch(b);
     return fail(PROS_ENOMEM, "batch tables: %s", hipGetErrorString(e));
   }
-  pros_status st = configure(b, 128, 2, 1.0, 0);
+  pros_status st = configure(b, 128, 2, 1.0, 0, 1);
   if (st != PROS_OK) {
     free_batch(b);
     return st;
@@ -402,6 +405,7 @@ pros_status pros_batch_get_config(pros_batch* b, pros_batch_config* out) {
   out->workgroups_per_cu = b->wg_per_cu;
   out->tile_scale = b->tile_scale;
   out->strategy = b->strategy;
+  out->sync_mode = b->sync_mode;
   out->workgroups = b->nwg;
   out->rounds = b->rounds;
   return PROS_OK;
@@ -415,9 +419,10 @@ pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg) {
   if (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 8) return fail(PROS_EINVAL, "workgroups_per_cu must be 1..8");
   if (!(cfg->tile_scale > 0.0 && cfg->tile_scale <= 1.0)) return fail(PROS_EINVAL, "tile_scale must be in (0, 1]");
   if (cfg->strategy < 0 || cfg->strategy > 1) return fail(PROS_EINVAL, "strategy must be 0 or 1");
+  if (cfg->sync_mode < 0 || cfg->sync_mode > 1) return fail(PROS_EINVAL, "sync_mode must be 0 or 1");
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
-  return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy);
+  return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy, cfg->sync_mode);
 }
 
 // Device-side copy of every stream's state, so that tuning leaves the
@@ -488,11 +493,12 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
   pros_batch_config bc{};
   const double scales[] = {1.0, 0.75, 0.5};
   const int wpcs[] = {1, 2};
+  for (int sm = 0; sm < 2; ++sm)
   for (int budget : kBudgets)
     for (int wpc : wpcs)
       for (double sc : scales)
         for (int strat = 0; strat < 2; ++strat) {
-          if (configure(b, budget, wpc, sc, strat) != PROS_OK) continue;   // does not fit
+          if (configure(b, budget, wpc, sc, strat, sm) != PROS_OK) continue;   // does not fit
           if (b->wg_per_cu != wpc) continue;                               // duplicate of a smaller grid
           st = launch(b, b->stream);                                        // warm-up
           for (int i = 0; i < steps && st == PROS_OK; ++i) {
@@ -521,6 +527,7 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
             bc.workgroups_per_cu = wpc;
             bc.tile_scale = sc;
             bc.strategy = strat;
+            bc.sync_mode = sm;
           }
           st = snapshot(b, sn, true);
           if (st != PROS_OK) break;
@@ -530,7 +537,7 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
   b->use_graph = graph;
   if (st != PROS_OK) return st;
   if (bestt >= 1e300) return fail(PROS_EUNSUPPORTED, "no candidate configuration fits");
-  st = configure(b, bc.register_budget, bc.workgroups_per_cu, bc.tile_scale, bc.strategy);
+  st = configure(b, bc.register_budget, bc.workgroups_per_cu, bc.tile_scale, bc.strategy, bc.sync_mode);
   if (st != PROS_OK) return st;
   if (best) pros_batch_get_config(b, best);
   if (best_ms) *best_ms = bestt;

@@ -80,6 +80,27 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ long long now_ticks() { return wall_clock64(); }
 
+// Epoch tags carried in the low 8 mantissa bits of a float64 partial sum:
+// an aligned 8-byte store is single-copy atomic, so a reader that sees the
+// current tag also sees the value written with it, without a flag or fence.
+// Clearing 8 of 52 mantissa bits changes a sum by at most 2^-44 relative.
+__device__ __forceinline__ double tag_value(double v, unsigned ep) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return __longlong_as_double((long long)((b & ~0xFFull) | (ep & 0xFFu)));
+}
+__device__ __forceinline__ unsigned tag_of(double v) {
+  return (unsigned)((unsigned long long)__double_as_longlong(v) & 0xFFull);
+}
+__device__ __forceinline__ double untag(double v) {
+  return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & ~0xFFull));
+}
+__device__ __forceinline__ double ld_tagged(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_tagged(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Gang barrier.  Every workgroup of the gang calls it the same number of
 // times; `target` = base + G * (index of this barrier + 1).  Thread 0 makes
 // the workgroup's prior global writes visible at device scope, arrives, and

@@ -31,8 +31,8 @@ struct FrameArgs {
   double* y;             // k coefficients (float64 state)
   long long* nframe;     // frame counter
   pros_stats* stats;     // statistics of the frame
-  double* part;          // 2 * G * kSlot doubles of workgroup partials
-  unsigned* sync;        // [0] arrival counter, [1] counter base, [2] error bits
+  double* part;          // (2 * G + kReplicas) * kSlot doubles of workgroup partials
+  unsigned* sync;        // [0] arrival counter, [1] counter base, [2] error bits, [3] epoch base
   long long ldU;
   int m, P, C, W, H, k;
   int G, tpw;
@@ -43,14 +43,131 @@ struct FrameArgs {
   int labels_after_update;
   int weights_from_filtered;
   long long timeout;     // wall-clock ticks a barrier may wait
+  int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast
 };
+
+constexpr int kReplicas = 8;   // copies of a gathered result (spread the pollers)
 
 // Workgroup + gang reduction of L float partials held by every thread.
 // Result (float64, identical in every workgroup) lands in s_out[0..L).
+// Tagged gather/broadcast: every workgroup publishes its tagged partial
+// vector; the gang's tile 0 polls all of them, sums them in tile order and
+// publishes the tagged totals in kReplicas copies that the other workgroups
+// poll.  No shared counter, so no serialised atomics on one address.
+// `fenced` adds release/acquire fences around the exchange so that plain
+// global writes made before it (labels) are visible after it.
 template <int L>
-__device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
-                                            unsigned base, double (*s_red)[kSlot], double* s_out,
-                                            int* s_ctl) {
+__device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const FrameArgs& a, const int tile,
+                                                   int& nbar, unsigned ebase, double (*s_red)[kSlot],
+                                                   double* s_out, int* s_ctl, bool fenced) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  ++nbar;
+  const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
+  double* slots = a.part;                                 // G slots
+  double* rep = a.part + (size_t)2 * a.G * kSlot;         // kReplicas slots
+  if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (tid < L) st_tagged(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
+  if (tile == 0) {
+    const long long t0 = now_ticks();
+    double t[L];
+    while (true) {
+#pragma unroll
+      for (int i = 0; i < L; ++i) t[i] = 0.0;
+      int ok = 1;
+      for (int w = tid; w < a.G; w += kBlock) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          const double x = ld_tagged(&slots[(size_t)w * kSlot + i]);
+          ok &= (tag_of(x) == ep) ? 1 : 0;
+          t[i] += untag(x);
+        }
+      }
+      if (__syncthreads_and(ok)) break;
+      const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
+                                      (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
+      if (__syncthreads_or(late)) {
+        if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const double v = wave_sum(t[i]);
+      if (lane == 0) s_red[wv][i] = v;
+    }
+    __syncthreads();
+    if (tid < L) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) v += s_red[q][tid];
+      s_out[tid] = untag(tag_value(v, ep));   // what every other workgroup will read
+    }
+    if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    __syncthreads();
+    for (int q = tid; q < kReplicas * L; q += kBlock) {
+      const int r = q / L, i = q - r * L;
+      st_tagged(&rep[(size_t)r * kSlot + i], tag_value(s_out[i], ep));
+    }
+    __syncthreads();
+    return true;
+  }
+  // other workgroups: poll their replica
+  if (tid == 0) s_ctl[1] = 0;
+  __syncthreads();
+  if (tid < L) {
+    const double* src = &rep[(size_t)(tile % kReplicas) * kSlot + tid];
+    const long long t0 = now_ticks();
+    unsigned spins = 0;
+    while (true) {
+      const double x = ld_tagged(src);
+      if (tag_of(x) == ep) {
+        s_out[tid] = untag(x);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 63u) == 0) {
+        if ((__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout) ||
+            now_ticks() - t0 > a.timeout) {
+          __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_ctl[1] = 1;
+          break;
+        }
+      }
+    }
+  }
+  if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return s_ctl[1] == 0;
+}
+
+// Workgroup sum of L float partials (one value per thread each), float64
+// result in wg_sum[0..L) (shared).
+template <int L>
+__device__ __forceinline__ void wg_reduce(const float (&acc)[L], double (*s_red)[kSlot], double* wg_sum) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const float v = wave_sum(acc[i]);
+    if (lane == 0) s_red[wv][i] = (double)v;
+  }
+  __syncthreads();
+  if (threadIdx.x < L) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) v += s_red[q][threadIdx.x];
+    wg_sum[threadIdx.x] = v;
+  }
+  __syncthreads();
+}
+
+template <int L>
+__device__ __forceinline__ bool gang_reduce_counter(const float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
+                                                    unsigned base, double (*s_red)[kSlot], double* s_out,
+                                                    int* s_ctl) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   // 1. per wave
@@ -99,6 +216,19 @@ __device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameAr
   return true;
 }
 
+// Gang-wide sum of L float partials: every workgroup of the gang ends with
+// the same float64 totals in s_out[0..L).
+template <int L>
+__device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
+                                            unsigned base, unsigned ebase, double (*s_red)[kSlot], double* s_wg,
+                                            double* s_out, int* s_ctl, bool fenced = false) {
+  if (a.sync_mode == 1) {
+    wg_reduce<L>(acc, s_red, s_wg);
+    return gang_reduce_tagged<L>(s_wg, a, tile, nbar, ebase, s_red, s_out, s_ctl, fenced);
+  }
+  return gang_reduce_counter<L>(acc, a, tile, nbar, base, s_red, s_out, s_ctl);
+}
+
 // Shared k-space state of one workgroup (all float64 unless noted).
 constexpr int kMaxNR = 16;
 template <int K>
@@ -122,6 +252,7 @@ struct KSpace {
 struct FrameSmem {
   KSpace<kMaxK> ks;
   double red[kWaves][kSlot];
+  double wg[kSlot];
   int ctl[4];
   uint8_t flag[kBlock * kMaxNR];
 };
@@ -141,6 +272,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   const int npx = min(a.tpw, a.P - p0);
   const int nq = npx * a.C;
   const unsigned base = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned ebase = __hip_atomic_load(&a.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int nbar = 0;
   const long long n = *a.nframe;
   const bool lead = (tile == 0);
@@ -202,7 +334,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, u[s][j], acc[j]);
     }
-    if (!gang_reduce<K + 1>(acc, a, tile, nbar, base, s_red, ks.red, s_ctl)) return false;
+    if (!gang_reduce<K + 1>(acc, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl)) return false;
     // k-space: PR+ direction (wave 0, lane j owns component j)
     if (tid < 64) {
       const double g = (lane < K) ? -ks.red[lane] : 0.0;
@@ -253,7 +385,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       ud[s] = t;
       accb[0] = fmaf(cw[s] * t, t, accb[0]);
     }
-    if (!gang_reduce<1>(accb, a, tile, nbar, base, s_red, ks.red, s_ctl)) return false;
+    if (!gang_reduce<1>(accb, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl)) return false;
     const double dHd = ks.red[0];
     if (!(dHd > 0.0)) break;   // same decision in every workgroup
     const double alpha = -ks.gd / dHd;
@@ -270,6 +402,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     __syncthreads();
   }
   const bool bad = ks.flag[1] != 0;
+  int fg = 0;
 
   // ---- Step 2: eta pass (a = U^T eta, ||eta||^2, final cost) ----
   float acce[K + 2];
@@ -287,7 +420,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, u[s][j], acce[j]);
     }
-    if (!gang_reduce<K + 2>(acce, a, tile, nbar, base, s_red, ks.red, s_ctl)) return false;
+    if (!gang_reduce<K + 2>(acce, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl)) return false;
     if (tid < 64) {
       const double av = (lane < K) ? ks.red[lane] : 0.0;
       const double yv = (lane < K) ? ks.y[lane] : 0.0;
@@ -354,13 +487,18 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       uint8_t f = 0;
       for (int c = 0; c < a.C; ++c) f |= s_flag[c * npx + pl];
       a.lab[p0 + pl] = f;
+      fg += f;
     }
   }
-  // all label writes visible before the median reads its neighbours
+  // all label writes visible before the median reads its neighbours; the
+  // exchange also sums the foreground count
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  ++nbar;
-  if (!gang_barrier(a.sync, base + (unsigned)a.G * (unsigned)nbar, a.timeout, s_ctl)) return false;
+  {
+    float accf[1] = {(float)fg};
+    if (!gang_reduce<1>(accf, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl, true)) return false;
+  }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const double fg_total = ks.red[0];
 
   if (!bad) {
     // ---- 3x3 median of the labels (>= 5 of 9, edges replicated) ----
@@ -390,8 +528,12 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     } else {
       *a.nframe = n + 1;
     }
-    __hip_atomic_store(&a.sync[1], base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    a.stats->fg_pixels = (long long)fg_total;
+    if (a.sync_mode == 1)
+      __hip_atomic_store(&a.sync[3], ebase + (unsigned)nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_store(&a.sync[1], base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
   if (lead && !bad && tid < a.k) a.y[tid] = ks.y[tid];
   __syncthreads();   // shared scratch may be reused by the next tile

@@ -27,6 +27,7 @@ struct pros_handle {
   // launch configuration
   const void* kfn = nullptr;
   int G = 0, tpw = 0, NR = 0;
+  int sync_mode = 1;       // 0: counter barrier, 1: tagged gather/broadcast
   long long timeout_ticks = 0;
   // host bookkeeping
   long long submitted = 0;

@@ -139,7 +139,7 @@ class Tracker:
         return dict(frame=s.frame, cg_steps=steps, restarts=s.restarts, updated=s.updated,
                     bad_frame=s.bad_frame, f=list(s.f[:steps + 1]), alpha=list(s.alpha[:steps]),
                     beta=list(s.beta[:steps]), t=s.t, sigma=s.sigma, theta=s.theta,
-                    zeta=s.zeta, nu=s.nu)
+                    zeta=s.zeta, nu=s.nu, fg_pixels=s.fg_pixels)
 
     def sync(self):
         return L.lib().pros_sync(self._h)
@@ -151,7 +151,11 @@ class Tracker:
         li = L.pros_launch_info()
         L.check(L.lib().pros_get_launch_info(self._h, C.byref(li)))
         return dict(workgroups=li.workgroups, threads=li.threads, rows_per_thread=li.rows_per_thread,
-                    pixels_per_wg=li.pixels_per_wg, barriers_per_frame=li.barriers_per_frame)
+                    pixels_per_wg=li.pixels_per_wg, barriers_per_frame=li.barriers_per_frame,
+                    sync_mode=li.sync_mode)
+
+    def set_launch(self, rows_per_thread=0, sync_mode=1):
+        L.check(L.lib().pros_set_launch(self._h, int(rows_per_thread), int(sync_mode)))
 
 
 def bf16_bits(a):
@@ -267,10 +271,11 @@ class BatchTracker:
         c = L.pros_batch_config()
         L.check(L.lib().pros_batch_get_config(self._b, C.byref(c)))
         return dict(register_budget=c.register_budget, workgroups_per_cu=c.workgroups_per_cu,
-                    tile_scale=c.tile_scale, strategy=c.strategy, workgroups=c.workgroups, rounds=c.rounds)
+                    tile_scale=c.tile_scale, strategy=c.strategy, sync_mode=c.sync_mode,
+                    workgroups=c.workgroups, rounds=c.rounds)
 
-    def configure(self, register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0):
-        c = L.pros_batch_config(register_budget, workgroups_per_cu, tile_scale, strategy, 0, 0, 0)
+    def configure(self, register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0, sync_mode=1):
+        c = L.pros_batch_config(register_budget, workgroups_per_cu, tile_scale, strategy, sync_mode, 0, 0)
         L.check(L.lib().pros_batch_configure(self._b, C.byref(c)))
 
     def tune(self, steps=5, cache=None):
@@ -295,7 +300,7 @@ class BatchTracker:
         ms = C.c_double()
         L.check(L.lib().pros_batch_tune(self._b, int(steps), C.byref(best), C.byref(ms)))
         rec = dict(config=dict(register_budget=best.register_budget, workgroups_per_cu=best.workgroups_per_cu,
-                               tile_scale=best.tile_scale, strategy=best.strategy),
+                               tile_scale=best.tile_scale, strategy=best.strategy, sync_mode=best.sync_mode),
                    ms_per_step=ms.value, workgroups=best.workgroups, rounds=best.rounds)
         if path:
             db = {}

@@ -52,7 +52,7 @@ def test_struct_sizes_match_header():
     L = _lib()
     # pros_params: 6 int32 + 6 double + 6 int32 (with padding)
     assert C.sizeof(L.pros_params) == 6 * 4 + 6 * 8 + 6 * 4
-    assert C.sizeof(L.pros_stats) == 8 + 4 * 4 + 8 * (17 + 16 + 16 + 5)
+    assert C.sizeof(L.pros_stats) == 8 + 4 * 4 + 8 * (17 + 16 + 16 + 5) + 8
 
 
 def _default(L, w=32, h=24, c=3):

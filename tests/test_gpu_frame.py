@@ -180,3 +180,17 @@ def test_free_running_small_gray():
                 say(f"  frame {n}: angle {ang:.2e} y_rel {np.linalg.norm(y - ref.y) / np.linalg.norm(ref.y):.2e} "
                     f"label disagreement {dis:.4%}")
     assert worst <= 0.005
+
+
+@pytest.mark.parametrize("sync_mode", [0, 1])
+@pytest.mark.parametrize("nr", [1, 4, 8])
+def test_launch_variants(nr, sync_mode):
+    """Register rows per thread (gang size 904 / 226 / 113 workgroups) and
+    both gang exchanges give the same frame."""
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 12)
+    with _tracker(prm) as trk:
+        trk.set_launch(nr, sync_mode)
+        say(f"qvga launch {trk.launch_info()}")
+        rep = compare_step(trk, prm, states[12], f32(sv.frame(12)))
+        assert rep["stats"]["fg_pixels"] == int(rep["labels"].sum())
+    assert_parity(rep)
