@@ -541,7 +541,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 }
 
 template <int K, int NR, typename TS>
-__global__ __launch_bounds__(kBlock) void frame_kernel(FrameArgs a) {
+__global__ __launch_bounds__(kBlock, 2) void frame_kernel(FrameArgs a) {
   __shared__ FrameSmem sm;
   frame_tile<K, NR, TS>(a, blockIdx.x, sm);
 }
