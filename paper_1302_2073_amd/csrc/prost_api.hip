@@ -144,10 +144,11 @@ void prost_host::free_handle(pros_handle* h) {
   delete h;
 }
 
-// Pick the register rows per thread NR: the smallest NR whose gang fits in
-// two workgroups per CU, else the smallest that fits the device at all.
+// Pick the register rows per thread NR: the largest NR whose gang fits in
+// the resident workgroups, so that the gang (and with it the cost of every
+// gang-wide exchange) is as small as possible.
 static pros_status choose_launch(pros_handle* h, int force_nr) {
-  const int nrs[] = {1, 2, 4, 8, 16};
+  const int nrs[] = {16, 8, 4, 2, 1};
   const void* best = nullptr;
   int bestNR = 0, bestG = 0, bestT = 0;
   for (int NR : nrs) {
@@ -163,7 +164,7 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
     const long long cap = (long long)occ * h->num_cu;
     if (G > cap) continue;
     best = f; bestNR = NR; bestG = (int)G; bestT = tpw;
-    if (force_nr > 0 || G <= 2LL * h->num_cu) break;
+    break;
   }
   if (!best)
     return fail(PROS_EUNSUPPORTED, "frame of %d pixels x %d channels at k=%d does not fit the device's resident workgroups",
@@ -229,6 +230,9 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
   INIT_TRY(hipMemsetAsync(h->nframe, 0, sizeof(long long), h->stream));
   INIT_TRY(hipMemsetAsync(h->stats, 0, sizeof(pros_stats), h->stream));
   INIT_TRY(hipMemsetAsync(h->sync, 0, 64, h->stream));
+  // epoch-tagged exchange slots must start with tag 0 (the first exchange uses 1)
+  INIT_TRY(hipMemsetAsync(h->part, 0, sizeof(double) * (2 * (size_t)h->G + prost::kReplicas) * prost::kSlot,
+                          h->stream));
   INIT_TRY(hipStreamSynchronize(h->stream));
 #undef INIT_TRY
   *out = h;
@@ -516,6 +520,15 @@ pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
   return PROS_OK;
 }
 
+// Clear the exchange slots and restart the epoch and arrival counters (after
+// any change of the gang; stale tags must never match a new epoch).
+pros_status prost_host::reset_exchange(pros_handle* h) {
+  HIP_TRY(hipMemsetAsync(h->part, 0, sizeof(double) * (2 * (size_t)h->G + prost::kReplicas) * prost::kSlot, h->stream));
+  HIP_TRY(hipMemsetAsync(h->sync, 0, 16, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return PROS_OK;
+}
+
 pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
@@ -538,7 +551,7 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
     }
   }
   h->sync_mode = sync_mode;
-  return PROS_OK;
+  return prost_host::reset_exchange(h);
 }
 
 pros_status pros_reorthonormalize(pros_handle* h) {

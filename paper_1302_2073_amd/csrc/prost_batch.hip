@@ -152,6 +152,8 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
     h->tpw = tpw;
     h->G = G;
     h->sync_mode = sync_mode;
+    pros_status rs = prost_host::reset_exchange(h);
+    if (rs != PROS_OK) return rs;
   }
   b->budget = budget;
   b->wg_per_cu = wpc;

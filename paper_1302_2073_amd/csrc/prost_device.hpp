@@ -13,7 +13,7 @@
 
 namespace prost {
 
-constexpr int kBlock = 256;            // threads per workgroup
+constexpr int kBlock = 512;            // threads per workgroup (8 wavefronts, one workgroup per CU)
 constexpr int kWaves = kBlock / 64;    // wavefronts per workgroup
 constexpr int kMaxK = 16;
 constexpr int kSlot = 32;              // doubles per workgroup partial slot

@@ -48,6 +48,7 @@ void free_handle(pros_handle* h);
 pros_status check_usable(pros_handle* h);
 pros_status sync_and_check(pros_handle* h);
 prost::FrameArgs make_args(pros_handle* h, const void* x);
+pros_status reset_exchange(pros_handle* h);
 uint16_t bf16_rne(float f);
 float bf16_to_f32(uint16_t b);
 pros_status set_error(pros_status s, const char* fmt, ...);

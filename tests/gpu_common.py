@@ -104,3 +104,21 @@ def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U):
     assert rep["lab_mismatch_outside_band"] == 0
     assert rep["mask_vs_median_of_gpu_labels"] == 0
     assert rep["f_rel"] <= TOL_F
+
+
+def update_rounding_bound(start, x64, prm, y_final):
+    """Per-entry bound of the float32 rounding error of the geodesic update
+    u' = u + [(cos(theta)-1) (u.v) - (sin(theta)/zeta) (eta - u.a)] v, from the
+    oracle's float64 intermediates: 2^-20 times the magnitudes of the terms
+    (a float32 error of a few units in the last place of each of them)."""
+    import math
+    U = start.U
+    w = O.pixel_weights(start.mask if prm.weights_from_filtered else start.labels, prm.omega, prm.channels)
+    eta = O.eta_vector(U, x64, y_final, w, prm.p, prm.mu, prm.cost)
+    s, sigma, v, zeta, nu = O.rank_one_svd(U, eta, y_final)
+    if s is None or v is None:
+        return 2.0 ** -20 * np.abs(U)
+    theta = sigma * O.step_size(start.n, prm.t_init, prm.t_min, prm.i_init)
+    a = U.T @ eta
+    term = (abs(math.cos(theta) - 1.0) * np.abs(U @ v) + abs(math.sin(theta) / zeta) * (np.abs(eta) + np.abs(U @ a)))
+    return 2.0 ** -20 * (np.abs(U) + np.abs(term)[:, None] * np.abs(v)[None, :])

@@ -3,7 +3,7 @@ launch per step, each stream against its own float64 oracle run."""
 import numpy as np
 import pytest
 
-from gpu_common import GUARD, TOL_U, TOL_Y, f32, say
+from gpu_common import GUARD, TOL_U, TOL_Y, f32, say, update_rounding_bound
 from oracle import prost_oracle as O
 from synth import video as V
 
@@ -156,7 +156,7 @@ def test_batch_bf16_matches_oracle():
             y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
             e = rne(exp.U)
             ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(e), 1e-38))) - 7)
-            ulp = np.maximum(ulp, 2.0 ** -19 * (np.abs(starts[s].U) + np.abs(exp.U)))
+            ulp = ulp + update_rounding_bound(starts[s], x, prm, exp.y)
             over = int(np.sum(np.abs(U1 - e) > ulp * 1.0000001 + 1e-45))
             say(f"  bf16 stream {s}: y {y_rel:.1e}, U entries beyond 1 ulp: {over}")
             assert y_rel <= 1e-4 and over == 0

@@ -3,7 +3,7 @@ and the float64 re-orthonormalisation of U on the GPU."""
 import numpy as np
 import pytest
 
-from gpu_common import GUARD, compare_step, oracle_params, say, tracker_kwargs
+from gpu_common import GUARD, compare_step, oracle_params, say, tracker_kwargs, update_rounding_bound
 from oracle import prost_oracle as O
 from synth import video as V
 
@@ -37,10 +37,10 @@ def _bf16_step(name, frame, upto):
         rep = compare_step(trk, prm, st, x, storage="bf16")
     exp = rne_bf16(rep["exp"].U)
     diff = np.abs(rep["U1"] - exp)
-    # one bfloat16 ulp; where the update cancels most of an entry the float32
-    # rounding of its operands (2^-19 of |u| + |u'|) can exceed that ulp
-    ulp = np.maximum(np.maximum(bf16_ulp(exp), bf16_ulp(rep["U1"])),
-                     2.0 ** -19 * (np.abs(rep["start"].U) + np.abs(rep["exp"].U)))
+    # one bfloat16 ulp, plus the float32 rounding of the update's terms (it
+    # exceeds an ulp only where the update cancels most of an entry)
+    ulp = np.maximum(bf16_ulp(exp), bf16_ulp(rep["U1"])) + update_rounding_bound(rep["start"], x, prm,
+                                                                                   rep["exp"].y)
     over = int(np.sum(diff > ulp * (1 + 1e-12)))
     n1ulp = int(np.sum(diff > 0))
     say(f"  bf16 {name} frame {frame}: y_rel={rep['y_rel']:.2e} U entries off by 1 ulp: {n1ulp} "
