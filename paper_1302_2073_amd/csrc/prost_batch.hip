@@ -111,14 +111,18 @@ static pros_status build_schedule(pros_batch* b) {
   for (int s : order) {
     const int G = b->hs[s]->G;
     if (G > nwg) return fail(PROS_EUNSUPPORTED, "stream %d needs %d resident workgroups, the launch has %d", s, G, nwg);
+    // gangs start at a multiple of 8 slots so that tile t runs on a workgroup
+    // with the same index modulo 8 (the XCD-local exchange relies on it)
+    auto start = [&](int rr) { return (used[rr] + 7) / 8 * 8; };
     int r = 0;
-    while (r < (int)used.size() && used[r] + G > nwg) ++r;
+    while (r < (int)used.size() && start(r) + G > nwg) ++r;
     if (r == (int)used.size()) {
       used.push_back(0);
       items.resize(used.size() * (size_t)nwg, BatchItem{-1, 0});
     }
-    for (int t = 0; t < G; ++t) items[(size_t)r * nwg + used[r] + t] = BatchItem{s, t};
-    used[r] += G;
+    const int s0 = start(r);
+    for (int t = 0; t < G; ++t) items[(size_t)r * nwg + s0 + t] = BatchItem{s, t};
+    used[r] = s0 + G;
   }
   b->rounds = (int)used.size();
   b->items.swap(items);
@@ -145,7 +149,7 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
     if (G != h->G) {   // partial buffer sized by the gang
       (void)hipFree(h->part);
       h->part = nullptr;
-      e = hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)G + prost::kReplicas) * prost::kSlot);
+      e = hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)G + prost::kExtraSlots) * prost::kSlot);
       if (e != hipSuccess) return fail(PROS_ENOMEM, "partials: %s", hipGetErrorString(e));
     }
     h->NR = NR;
@@ -421,7 +425,9 @@ pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg) {
   if (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 8) return fail(PROS_EINVAL, "workgroups_per_cu must be 1..8");
   if (!(cfg->tile_scale > 0.0 && cfg->tile_scale <= 1.0)) return fail(PROS_EINVAL, "tile_scale must be in (0, 1]");
   if (cfg->strategy < 0 || cfg->strategy > 1) return fail(PROS_EINVAL, "strategy must be 0 or 1");
-  if (cfg->sync_mode < 0 || cfg->sync_mode > 1) return fail(PROS_EINVAL, "sync_mode must be 0 or 1");
+  if (cfg->sync_mode < 0 || cfg->sync_mode > 2) return fail(PROS_EINVAL, "sync_mode must be 0, 1 or 2");
+  if (cfg->sync_mode == 2 && !prost_host::xcd_round_robin(b->stream))
+    return fail(PROS_EUNSUPPORTED, "sync_mode 2 needs workgroup b placed on XCD b %% 8");
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
   return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy, cfg->sync_mode);
@@ -495,7 +501,8 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
   pros_batch_config bc{};
   const double scales[] = {1.0, 0.75, 0.5};
   const int wpcs[] = {1, 2};
-  for (int sm = 0; sm < 2; ++sm)
+  const int nsm = prost_host::xcd_round_robin(b->stream) ? 3 : 2;
+  for (int sm = 0; sm < nsm; ++sm)
   for (int budget : kBudgets)
     for (int wpc : wpcs)
       for (double sc : scales)

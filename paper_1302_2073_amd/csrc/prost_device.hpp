@@ -100,6 +100,14 @@ __device__ __forceinline__ double ld_tagged(const double* p) {
 __device__ __forceinline__ void st_tagged(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// L1-bypassing accesses served by the XCD's L2 (coherent among the CUs of one
+// XCD); used only between workgroups placed on the same XCD.
+__device__ __forceinline__ double ld_local(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_local(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // Gang barrier.  Every workgroup of the gang calls it the same number of
 // times; `target` = base + G * (index of this barrier + 1).  Thread 0 makes

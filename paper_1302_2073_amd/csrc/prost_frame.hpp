@@ -31,7 +31,7 @@ struct FrameArgs {
   double* y;             // k coefficients (float64 state)
   long long* nframe;     // frame counter
   pros_stats* stats;     // statistics of the frame
-  double* part;          // (2 * G + kReplicas) * kSlot doubles of workgroup partials
+  double* part;          // (2 * G + kExtraSlots) * kSlot doubles of workgroup partials
   unsigned* sync;        // [0] arrival counter, [1] counter base, [2] error bits, [3] epoch base
   long long ldU;
   int m, P, C, W, H, k;
@@ -43,10 +43,12 @@ struct FrameArgs {
   int labels_after_update;
   int weights_from_filtered;
   long long timeout;     // wall-clock ticks a barrier may wait
-  int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast
+  int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
+                         // 2: two-level XCD-local gather (tile t on XCD t % 8)
 };
 
-constexpr int kReplicas = 8;   // copies of a gathered result (spread the pollers)
+constexpr int kReplicas = 8;      // copies of a gathered result (spread the pollers)
+constexpr int kExtraSlots = 32;   // slots beyond 2 G: replicas / XCD-level slots
 
 // Workgroup + gang reduction of L float partials held by every thread.
 // Result (float64, identical in every workgroup) lands in s_out[0..L).
@@ -128,6 +130,116 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
         break;
       }
       __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 63u) == 0) {
+        if ((__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout) ||
+            now_ticks() - t0 > a.timeout) {
+          __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_ctl[1] = 1;
+          break;
+        }
+      }
+    }
+  }
+  if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return s_ctl[1] == 0;
+}
+
+// Two-level exchange for a gang whose tile t runs on XCD t % 8 (the
+// round-robin placement of workgroups on the 8 XCDs, verified by the host
+// before this mode is enabled).  Level 1: the workgroups of one XCD publish
+// tagged partials through that XCD's L2 (workgroup-scope, L1-bypassing
+// accesses); the XCD's first tile sums them in tile order.  Level 2: the (at
+// most 8) XCD leaders exchange their sums at device scope and add them in XCD
+// order.  Level 3: each leader hands the total back through its L2.  Every
+// workgroup ends with bit-identical totals; only one round trip crosses XCDs.
+template <int L>
+__device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const FrameArgs& a, const int tile,
+                                                int& nbar, unsigned ebase, double (*s_red)[kSlot],
+                                                double* s_out, int* s_ctl, bool fenced) {
+  const int tid = threadIdx.x;
+  ++nbar;
+  const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
+  const int x = tile & 7;
+  const int ngrp = min(8, a.G);
+  double* slots = a.part;                                         // G level-1 slots
+  double* xres = a.part + (size_t)a.G * kSlot;                    // 2 x 8 level-2 slots
+  double* bc = xres + (size_t)16 * kSlot;                         // 8 level-3 slots
+  if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (tid < L) st_local(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
+  if (tile < 8) {   // XCD leader
+    const int n = (a.G - x + 7) >> 3;          // tiles x, x+8, ...
+    const int comp = tid & 31, row0 = tid >> 5;
+    constexpr int kRows = kBlock / 32;
+    const long long t0 = now_ticks();
+    double v = 0.0;
+    while (true) {
+      int ok = 1;
+      v = 0.0;
+      if (comp < L)
+        for (int q = row0; q < n; q += kRows) {
+          const double val = ld_local(&slots[(size_t)(q * 8 + x) * kSlot + comp]);
+          ok &= (tag_of(val) == ep) ? 1 : 0;
+          v += untag(val);
+        }
+      if (__syncthreads_and(ok)) break;
+      const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
+                                      (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
+      if (__syncthreads_or(late)) {
+        if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    double* s_tmp = &s_red[0][0];              // kWaves * kSlot >= kBlock doubles
+    s_tmp[tid] = v;
+    __syncthreads();
+    double* xr = xres + (size_t)(nbar & 1) * 8 * kSlot;
+    if (tid < L) {
+      double g = 0.0;
+      for (int r = 0; r < kRows; ++r) g += s_tmp[r * 32 + tid];
+      st_tagged(&xr[(size_t)x * kSlot + tid], tag_value(g, ep));
+    }
+    // level 2: all XCD sums, added in XCD order
+    const long long t1 = now_ticks();
+    double tot = 0.0;
+    while (true) {
+      int ok = 1;
+      tot = 0.0;
+      if (tid < L)
+        for (int gq = 0; gq < ngrp; ++gq) {
+          const double val = ld_tagged(&xr[(size_t)gq * kSlot + tid]);
+          ok &= (tag_of(val) == ep) ? 1 : 0;
+          tot += untag(val);
+        }
+      if (__syncthreads_and(ok)) break;
+      const int late = (tid == 0) && (now_ticks() - t1 > a.timeout ||
+                                      (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
+      if (__syncthreads_or(late)) {
+        if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+    if (tid < L) {
+      s_out[tid] = untag(tag_value(tot, ep));
+      st_local(&bc[(size_t)x * kSlot + tid], tag_value(tot, ep));
+    }
+    if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    return true;
+  }
+  // members: wait for the XCD leader's total
+  if (tid == 0) s_ctl[1] = 0;
+  __syncthreads();
+  if (tid < L) {
+    const double* src = &bc[(size_t)x * kSlot + tid];
+    const long long t0 = now_ticks();
+    unsigned spins = 0;
+    while (true) {
+      const double val = ld_local(src);
+      if (tag_of(val) == ep) {
+        s_out[tid] = untag(val);
+        break;
+      }
       if ((++spins & 63u) == 0) {
         if ((__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout) ||
             now_ticks() - t0 > a.timeout) {
@@ -225,6 +337,10 @@ __device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameAr
   if (a.sync_mode == 1) {
     wg_reduce<L>(acc, s_red, s_wg);
     return gang_reduce_tagged<L>(s_wg, a, tile, nbar, ebase, s_red, s_out, s_ctl, fenced);
+  }
+  if (a.sync_mode == 2) {
+    wg_reduce<L>(acc, s_red, s_wg);
+    return gang_reduce_xcd<L>(s_wg, a, tile, nbar, ebase, s_red, s_out, s_ctl, fenced);
   }
   return gang_reduce_counter<L>(acc, a, tile, nbar, base, s_red, s_out, s_ctl);
 }
@@ -529,7 +645,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       *a.nframe = n + 1;
     }
     a.stats->fg_pixels = (long long)fg_total;
-    if (a.sync_mode == 1)
+    if (a.sync_mode != 0)
       __hip_atomic_store(&a.sync[3], ebase + (unsigned)nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
       __hip_atomic_store(&a.sync[1], base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,

@@ -49,6 +49,8 @@ pros_status check_usable(pros_handle* h);
 pros_status sync_and_check(pros_handle* h);
 prost::FrameArgs make_args(pros_handle* h, const void* x);
 pros_status reset_exchange(pros_handle* h);
+// True when a cooperative launch places workgroup b on XCD b % 8 (checked once).
+bool xcd_round_robin(hipStream_t stream);
 uint16_t bf16_rne(float f);
 float bf16_to_f32(uint16_t b);
 pros_status set_error(pros_status s, const char* fmt, ...);

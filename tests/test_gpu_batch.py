@@ -73,7 +73,11 @@ def _load(bt, streams):
 
 
 @pytest.mark.parametrize("cfg", [dict(register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0),
-                                 dict(register_budget=64, workgroups_per_cu=1, tile_scale=0.5, strategy=1)])
+                                 dict(register_budget=64, workgroups_per_cu=1, tile_scale=0.5, strategy=1),
+                                 dict(register_budget=128, workgroups_per_cu=1, tile_scale=1.0, strategy=0,
+                                      sync_mode=0),
+                                 dict(register_budget=128, workgroups_per_cu=1, tile_scale=0.75, strategy=0,
+                                      sync_mode=2)])
 def test_batch_step_matches_oracle_per_stream(cfg):
     from paper_1302_2073_amd.tracker import BatchTracker
     streams = _streams()

@@ -182,14 +182,20 @@ def test_free_running_small_gray():
     assert worst <= 0.005
 
 
-@pytest.mark.parametrize("sync_mode", [0, 1])
+@pytest.mark.parametrize("sync_mode", [0, 1, 2])
 @pytest.mark.parametrize("nr", [1, 4, 8])
 def test_launch_variants(nr, sync_mode):
-    """Register rows per thread (gang size 904 / 226 / 113 workgroups) and
-    both gang exchanges give the same frame."""
+    """Register rows per thread (gangs of 452 / 113 / 57 workgroups) and the
+    three gang exchanges give the same frame."""
+    from paper_1302_2073_amd import _lib as L
     wl, prm, sv, states = oracle_trajectory("qvga_rgb", 12)
     with _tracker(prm) as trk:
-        trk.set_launch(nr, sync_mode)
+        try:
+            trk.set_launch(nr, sync_mode)
+        except L.ProstError as e:
+            if e.status == L.PROS_EUNSUPPORTED and sync_mode == 2:
+                pytest.skip("workgroups are not placed round-robin over XCDs on this device")
+            raise
         say(f"qvga launch {trk.launch_info()}")
         rep = compare_step(trk, prm, states[12], f32(sv.frame(12)))
         assert rep["stats"]["fg_pixels"] == int(rep["labels"].sum())
