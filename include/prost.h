@@ -271,9 +271,15 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
  * workgroups) and the gang exchange used for the frame's reductions:
  * 0 = one arrival counter per gang and every workgroup reading all partial
  * sums, 1 = epoch-tagged partial sums gathered by the gang's first
- * workgroup and broadcast back (default).  Results are identical.
+ * workgroup and broadcast back (default), 2 = the same in two levels
+ * (groups of tiles t = x mod 8).  Results agree to float64 rounding.
  * Synchronises. */
 PROS_API pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode);
+
+/* Diagnostics: record wall-clock timestamps (64 per workgroup tile, int64,
+ * device memory of at least 64 * workgroups entries) around every gang-wide
+ * exchange of the following frames; NULL stops recording. */
+PROS_API pros_status pros_debug_trace(pros_handle* h, long long* device_buffer);
 
 /* Text for a status code (static storage). */
 PROS_API const char* pros_strerror(pros_status s);

@@ -86,6 +86,7 @@ _SIGS = {
     "pros_reorthonormalize": (C.c_int, [C.c_void_p]),
     "pros_get_launch_info": (C.c_int, [C.c_void_p, C.POINTER(pros_launch_info)]),
     "pros_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pros_debug_trace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pros_batch_init": (C.c_int, [C.POINTER(pros_params), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pros_batch_destroy": (None, [C.c_void_p]),
     "pros_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),

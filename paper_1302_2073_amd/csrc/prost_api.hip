@@ -422,6 +422,7 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.weights_from_filtered = p.weights_from_filtered;
   a.timeout = h->timeout_ticks;
   a.sync_mode = h->sync_mode;
+  a.trace = h->trace;
   return a;
 }
 
@@ -521,35 +522,6 @@ pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
   return PROS_OK;
 }
 
-// Workgroup placement check for sync_mode 2: a cooperative launch of the
-// largest resident grid records each workgroup's XCD (hardware register
-// XCC_ID); the mode is allowed only when workgroup b runs on XCD b % 8.
-__global__ void xcd_probe_kernel(int* out) {
-  if (threadIdx.x == 0) out[blockIdx.x] = (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
-}
-
-static int g_xcd_ok = -1;   // -1 unknown, 0 no, 1 yes
-
-bool prost_host::xcd_round_robin(hipStream_t stream) {
-  if (g_xcd_ok >= 0) return g_xcd_ok == 1;
-  int dev = 0, ncu = 0, occ = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return false;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)xcd_probe_kernel, 64, 0) != hipSuccess) return false;
-  const int G = std::min(occ, 8) * ncu;
-  int* d = nullptr;
-  if (hipMalloc(&d, sizeof(int) * G) != hipSuccess) return false;
-  std::vector<int> h(G, -1);
-  void* args[] = {&d};
-  bool ok = hipLaunchCooperativeKernel((const void*)xcd_probe_kernel, dim3(G), dim3(64), args, 0, stream) == hipSuccess &&
-            hipStreamSynchronize(stream) == hipSuccess &&
-            hipMemcpy(h.data(), d, sizeof(int) * G, hipMemcpyDeviceToHost) == hipSuccess;
-  (void)hipFree(d);
-  for (int b = 0; ok && b < G; ++b) ok = (h[b] == b % 8);
-  g_xcd_ok = ok ? 1 : 0;
-  return ok;
-}
-
 // Clear the exchange slots and restart the epoch and arrival counters (after
 // any change of the gang; stale tags must never match a new epoch).
 pros_status prost_host::reset_exchange(pros_handle* h) {
@@ -563,8 +535,6 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
   if (sync_mode < 0 || sync_mode > 2) return fail(PROS_EINVAL, "sync_mode must be 0, 1 or 2");
-  if (sync_mode == 2 && !prost_host::xcd_round_robin(h->stream))
-    return fail(PROS_EUNSUPPORTED, "sync_mode 2 needs workgroup b placed on XCD b %% 8");
   if (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 && rows_per_thread != 4 &&
       rows_per_thread != 8 && rows_per_thread != 16)
     return fail(PROS_EINVAL, "rows_per_thread must be 0 (automatic), 1, 2, 4, 8 or 16");
@@ -584,6 +554,13 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   }
   h->sync_mode = sync_mode;
   return prost_host::reset_exchange(h);
+}
+
+pros_status pros_debug_trace(pros_handle* h, long long* device_buffer) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  h->trace = device_buffer;
+  return PROS_OK;
 }
 
 pros_status pros_reorthonormalize(pros_handle* h) {

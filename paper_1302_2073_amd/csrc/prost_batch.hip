@@ -111,8 +111,8 @@ static pros_status build_schedule(pros_batch* b) {
   for (int s : order) {
     const int G = b->hs[s]->G;
     if (G > nwg) return fail(PROS_EUNSUPPORTED, "stream %d needs %d resident workgroups, the launch has %d", s, G, nwg);
-    // gangs start at a multiple of 8 slots so that tile t runs on a workgroup
-    // with the same index modulo 8 (the XCD-local exchange relies on it)
+    // gangs start at a multiple of 8 slots (tile t on a workgroup with the
+    // same index modulo 8, i.e. on one XCD with consecutive round-robin placement)
     auto start = [&](int rr) { return (used[rr] + 7) / 8 * 8; };
     int r = 0;
     while (r < (int)used.size() && start(r) + G > nwg) ++r;
@@ -426,8 +426,6 @@ pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg) {
   if (!(cfg->tile_scale > 0.0 && cfg->tile_scale <= 1.0)) return fail(PROS_EINVAL, "tile_scale must be in (0, 1]");
   if (cfg->strategy < 0 || cfg->strategy > 1) return fail(PROS_EINVAL, "strategy must be 0 or 1");
   if (cfg->sync_mode < 0 || cfg->sync_mode > 2) return fail(PROS_EINVAL, "sync_mode must be 0, 1 or 2");
-  if (cfg->sync_mode == 2 && !prost_host::xcd_round_robin(b->stream))
-    return fail(PROS_EUNSUPPORTED, "sync_mode 2 needs workgroup b placed on XCD b %% 8");
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
   return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy, cfg->sync_mode);
@@ -501,8 +499,7 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
   pros_batch_config bc{};
   const double scales[] = {1.0, 0.75, 0.5};
   const int wpcs[] = {1, 2};
-  const int nsm = prost_host::xcd_round_robin(b->stream) ? 3 : 2;
-  for (int sm = 0; sm < nsm; ++sm)
+  for (int sm = 0; sm < 3; ++sm)
   for (int budget : kBudgets)
     for (int wpc : wpcs)
       for (double sc : scales)

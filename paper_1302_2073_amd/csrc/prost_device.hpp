@@ -78,6 +78,50 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over the first 16 lanes (k-space vectors live in lanes 0..15); every
+// lane of each 16-lane row ends with its row's total.
+__device__ __forceinline__ double row16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// Reduce-scatter of L values across the 64 lanes of a wavefront: at each of
+// log2(P) stages (P = L rounded up to a power of two) a lane keeps one half of
+// its values and adds the partner's copy of that half, so the work halves
+// every stage (P - 1 exchanges instead of 6 L).  On return lane l holds the
+// wavefront total of component `comp`; lanes whose low 6 - log2(P) bits are
+// zero hold each component exactly once.  Fixed order, deterministic.
+template <int L, typename T>
+__device__ __forceinline__ T wave_reduce_scatter(T (&a)[L], int& comp) {
+  constexpr int P = pow2_at_least(L);
+  constexpr int S = ilog2(P);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    const int half = P >> (st + 1);
+    const int o = 32 >> st;
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {      // in place; entries >= L are zero
+      const T lo = a[i];
+      const T hi = (i + half < L) ? a[(i + half < L) ? i + half : 0] : T(0);
+      const T send = up ? lo : hi;
+      const T keep = up ? hi : lo;
+      a[i] = keep + __shfl_xor(send, o, 64);
+    }
+    if (up) base += half;
+  }
+#pragma unroll
+  for (int o = 32 >> S; o > 0; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+  comp = base;
+  return a[0];
+}
+
 __device__ __forceinline__ long long now_ticks() { return wall_clock64(); }
 
 // Epoch tags carried in the low 8 mantissa bits of a float64 partial sum:
@@ -99,14 +143,6 @@ __device__ __forceinline__ double ld_tagged(const double* p) {
 }
 __device__ __forceinline__ void st_tagged(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// L1-bypassing accesses served by the XCD's L2 (coherent among the CUs of one
-// XCD); used only between workgroups placed on the same XCD.
-__device__ __forceinline__ double ld_local(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void st_local(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Gang barrier.  Every workgroup of the gang calls it the same number of

@@ -43,12 +43,43 @@ struct FrameArgs {
   int labels_after_update;
   int weights_from_filtered;
   long long timeout;     // wall-clock ticks a barrier may wait
+  long long* trace;      // optional per-tile timestamps (diagnostics), 64 per tile
   int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
-                         // 2: two-level XCD-local gather (tile t on XCD t % 8)
+                         // 2: two-level tagged gather (groups of tiles with equal t % 8)
 };
 
 constexpr int kReplicas = 8;      // copies of a gathered result (spread the pollers)
 constexpr int kExtraSlots = 32;   // slots beyond 2 G: replicas / XCD-level slots
+
+// Shared k-space state of one workgroup (all float64 unless noted).
+constexpr int kMaxNR = 16;
+template <int K>
+struct KSpace {
+  double y[K];
+  double d[K];
+  double gp[K];     // previous gradient
+  double dp[K];     // previous direction
+  double a[K];      // U^T eta
+  double red[kSlot];
+  double gd;        // g . d of the current step
+  float df[K];      // direction (float) for the row passes
+  float vf[K];      // v = y/||y||
+  float af[K];      // a (float)
+  float yf[K];
+  float scal[8];    // row-pass scalars
+  int flag[4];      // [0] stop CG, [1] bad frame, [2] do update
+};
+
+// Workgroup-shared scratch of one frame tile (sized for the largest k / NR).
+struct FrameSmem {
+  KSpace<kMaxK> ks;
+  double red[kWaves][kSlot];
+  double wg[kSlot];
+  double big[kBlock];          // one float64 per thread (gathers)
+  int ctl[4];
+  uint8_t flag[kBlock * kMaxNR];
+};
+
 
 // Workgroup + gang reduction of L float partials held by every thread.
 // Result (float64, identical in every workgroup) lands in s_out[0..L).
@@ -60,7 +91,7 @@ constexpr int kExtraSlots = 32;   // slots beyond 2 G: replicas / XCD-level slot
 // global writes made before it (labels) are visible after it.
 template <int L>
 __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const FrameArgs& a, const int tile,
-                                                   int& nbar, unsigned ebase, double (*s_red)[kSlot],
+                                                   int& nbar, unsigned ebase, double* s_big,
                                                    double* s_out, int* s_ctl, bool fenced) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -73,19 +104,18 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
   if (tid < L) st_tagged(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
   if (tile == 0) {
     const long long t0 = now_ticks();
-    double t[L];
+    constexpr int kRows = kBlock / 32;
+    const int comp = tid & 31, row0 = tid >> 5;
+    double v = 0.0;
     while (true) {
-#pragma unroll
-      for (int i = 0; i < L; ++i) t[i] = 0.0;
       int ok = 1;
-      for (int w = tid; w < a.G; w += kBlock) {
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-          const double x = ld_tagged(&slots[(size_t)w * kSlot + i]);
+      v = 0.0;
+      if (comp < L)
+        for (int w = row0; w < a.G; w += kRows) {
+          const double x = ld_tagged(&slots[(size_t)w * kSlot + comp]);
           ok &= (tag_of(x) == ep) ? 1 : 0;
-          t[i] += untag(x);
+          v += untag(x);
         }
-      }
       if (__syncthreads_and(ok)) break;
       const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
                                       (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
@@ -95,17 +125,13 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
       }
       __builtin_amdgcn_s_sleep(1);
     }
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      const double v = wave_sum(t[i]);
-      if (lane == 0) s_red[wv][i] = v;
-    }
+    s_big[tid] = v;
     __syncthreads();
     if (tid < L) {
-      double v = 0.0;
+      double tot = 0.0;
 #pragma unroll
-      for (int q = 0; q < kWaves; ++q) v += s_red[q][tid];
-      s_out[tid] = untag(tag_value(v, ep));   // what every other workgroup will read
+      for (int r = 0; r < kRows; ++r) tot += s_big[r * 32 + tid];
+      s_out[tid] = untag(tag_value(tot, ep));   // what every other workgroup will read
     }
     if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     __syncthreads();
@@ -145,17 +171,15 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
   return s_ctl[1] == 0;
 }
 
-// Two-level exchange for a gang whose tile t runs on XCD t % 8 (the
-// round-robin placement of workgroups on the 8 XCDs, verified by the host
-// before this mode is enabled).  Level 1: the workgroups of one XCD publish
-// tagged partials through that XCD's L2 (workgroup-scope, L1-bypassing
-// accesses); the XCD's first tile sums them in tile order.  Level 2: the (at
-// most 8) XCD leaders exchange their sums at device scope and add them in XCD
-// order.  Level 3: each leader hands the total back through its L2.  Every
-// workgroup ends with bit-identical totals; only one round trip crosses XCDs.
+// Two-level tagged exchange: the tiles t = x, x + 8, x + 16, ... form group x
+// (x < 8); group x's first tile gathers their tagged partials and sums them
+// in tile order, the (at most 8) group leaders exchange their sums and add
+// them in group order, and each leader hands the total back to its group.
+// Fewer pollers per cache line and a fan-in of G/8 per leader instead of G.
+// Every workgroup ends with bit-identical totals.
 template <int L>
-__device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const FrameArgs& a, const int tile,
-                                                int& nbar, unsigned ebase, double (*s_red)[kSlot],
+__device__ __forceinline__ bool gang_reduce_2level(const double* wg_sum, const FrameArgs& a, const int tile,
+                                                int& nbar, unsigned ebase, double* s_big,
                                                 double* s_out, int* s_ctl, bool fenced) {
   const int tid = threadIdx.x;
   ++nbar;
@@ -166,7 +190,7 @@ __device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const Fram
   double* xres = a.part + (size_t)a.G * kSlot;                    // 2 x 8 level-2 slots
   double* bc = xres + (size_t)16 * kSlot;                         // 8 level-3 slots
   if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (tid < L) st_local(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
+  if (tid < L) st_tagged(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
   if (tile < 8) {   // XCD leader
     const int n = (a.G - x + 7) >> 3;          // tiles x, x+8, ...
     const int comp = tid & 31, row0 = tid >> 5;
@@ -178,7 +202,7 @@ __device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const Fram
       v = 0.0;
       if (comp < L)
         for (int q = row0; q < n; q += kRows) {
-          const double val = ld_local(&slots[(size_t)(q * 8 + x) * kSlot + comp]);
+          const double val = ld_tagged(&slots[(size_t)(q * 8 + x) * kSlot + comp]);
           ok &= (tag_of(val) == ep) ? 1 : 0;
           v += untag(val);
         }
@@ -190,7 +214,7 @@ __device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const Fram
         return false;
       }
     }
-    double* s_tmp = &s_red[0][0];              // kWaves * kSlot >= kBlock doubles
+    double* s_tmp = s_big;
     s_tmp[tid] = v;
     __syncthreads();
     double* xr = xres + (size_t)(nbar & 1) * 8 * kSlot;
@@ -221,7 +245,7 @@ __device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const Fram
     }
     if (tid < L) {
       s_out[tid] = untag(tag_value(tot, ep));
-      st_local(&bc[(size_t)x * kSlot + tid], tag_value(tot, ep));
+      st_tagged(&bc[(size_t)x * kSlot + tid], tag_value(tot, ep));
     }
     if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
@@ -235,7 +259,7 @@ __device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const Fram
     const long long t0 = now_ticks();
     unsigned spins = 0;
     while (true) {
-      const double val = ld_local(src);
+      const double val = ld_tagged(src);
       if (tag_of(val) == ep) {
         s_out[tid] = untag(val);
         break;
@@ -258,14 +282,13 @@ __device__ __forceinline__ bool gang_reduce_xcd(const double* wg_sum, const Fram
 // Workgroup sum of L float partials (one value per thread each), float64
 // result in wg_sum[0..L) (shared).
 template <int L>
-__device__ __forceinline__ void wg_reduce(const float (&acc)[L], double (*s_red)[kSlot], double* wg_sum) {
+__device__ __forceinline__ void wg_reduce(float (&acc)[L], double (*s_red)[kSlot], double* wg_sum) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const float v = wave_sum(acc[i]);
-    if (lane == 0) s_red[wv][i] = (double)v;
-  }
+  int comp;
+  const float v = wave_reduce_scatter<L>(acc, comp);
+  constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
+  if ((lane & kLowMask) == 0 && comp < L) s_red[wv][comp] = (double)v;
   __syncthreads();
   if (threadIdx.x < L) {
     double v = 0.0;
@@ -277,16 +300,17 @@ __device__ __forceinline__ void wg_reduce(const float (&acc)[L], double (*s_red)
 }
 
 template <int L>
-__device__ __forceinline__ bool gang_reduce_counter(const float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
-                                                    unsigned base, double (*s_red)[kSlot], double* s_out,
-                                                    int* s_ctl) {
+__device__ __forceinline__ bool gang_reduce_counter(float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
+                                                    unsigned base, double (*s_red)[kSlot], double* s_big,
+                                                    double* s_out, int* s_ctl) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
+  constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
   // 1. per wave
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const float v = wave_sum(acc[i]);
-    if (lane == 0) s_red[wv][i] = (double)v;
+  {
+    int comp;
+    const float v = wave_reduce_scatter<L>(acc, comp);
+    if ((lane & kLowMask) == 0 && comp < L) s_red[wv][comp] = (double)v;
   }
   __syncthreads();
   double* slot = a.part + ((size_t)(nbar & 1) * a.G + tile) * kSlot;
@@ -299,30 +323,24 @@ __device__ __forceinline__ bool gang_reduce_counter(const float (&acc)[L], const
   // 2. gang barrier
   ++nbar;
   if (!gang_barrier(a.sync, base + (unsigned)a.G * (unsigned)nbar, a.timeout, s_ctl)) return false;
-  // 3. every workgroup sums all partials in the same order
+  // 3. every workgroup sums all partials in the same order: thread t adds
+  // component t % 32 of slots t / 32, t / 32 + kRows, ... (contiguous loads),
+  // then the kRows partial sums of each component are added in order.
+  // Plain (cached) loads: the barrier's acquire fence invalidated stale lines,
+  // so the first workgroup of each XCD pulls the partials into its L2.
   const double* buf = a.part + (size_t)((nbar - 1) & 1) * a.G * kSlot;
-  double t[L];
-#pragma unroll
-  for (int i = 0; i < L; ++i) t[i] = 0.0;
-  // plain (cached) loads: the barrier's acquire fence invalidated stale lines,
-  // so the first workgroup of each XCD pulls the partials into its L2 and the
-  // others hit there
-  for (int w = threadIdx.x; w < a.G; w += kBlock) {
-    const double* src = buf + (size_t)w * kSlot;
-#pragma unroll
-    for (int i = 0; i < L; ++i) t[i] += src[i];
-  }
-#pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const double v = wave_sum(t[i]);
-    if (lane == 0) s_red[wv][i] = v;
-  }
+  constexpr int kRows = kBlock / 32;
+  const int comp = threadIdx.x & 31, row0 = threadIdx.x >> 5;
+  double v = 0.0;
+  if (comp < L)
+    for (int w = row0; w < a.G; w += kRows) v += buf[(size_t)w * kSlot + comp];
+  s_big[threadIdx.x] = v;
   __syncthreads();
   if (threadIdx.x < L) {
-    double v = 0.0;
+    double tot = 0.0;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) v += s_red[q][threadIdx.x];
-    s_out[threadIdx.x] = v;
+    for (int r = 0; r < kRows; ++r) tot += s_big[r * 32 + threadIdx.x];
+    s_out[threadIdx.x] = tot;
   }
   __syncthreads();
   return true;
@@ -331,47 +349,34 @@ __device__ __forceinline__ bool gang_reduce_counter(const float (&acc)[L], const
 // Gang-wide sum of L float partials: every workgroup of the gang ends with
 // the same float64 totals in s_out[0..L).
 template <int L>
-__device__ __forceinline__ bool gang_reduce(const float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
-                                            unsigned base, unsigned ebase, double (*s_red)[kSlot], double* s_wg,
-                                            double* s_out, int* s_ctl, bool fenced = false) {
+__device__ __forceinline__ bool gang_reduce_impl(float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
+                                                 unsigned base, unsigned ebase, FrameSmem& sm, double* s_out,
+                                                 bool fenced) {
   if (a.sync_mode == 1) {
-    wg_reduce<L>(acc, s_red, s_wg);
-    return gang_reduce_tagged<L>(s_wg, a, tile, nbar, ebase, s_red, s_out, s_ctl, fenced);
+    wg_reduce<L>(acc, sm.red, sm.wg);
+    return gang_reduce_tagged<L>(sm.wg, a, tile, nbar, ebase, sm.big, s_out, sm.ctl, fenced);
   }
   if (a.sync_mode == 2) {
-    wg_reduce<L>(acc, s_red, s_wg);
-    return gang_reduce_xcd<L>(s_wg, a, tile, nbar, ebase, s_red, s_out, s_ctl, fenced);
+    wg_reduce<L>(acc, sm.red, sm.wg);
+    return gang_reduce_2level<L>(sm.wg, a, tile, nbar, ebase, sm.big, s_out, sm.ctl, fenced);
   }
-  return gang_reduce_counter<L>(acc, a, tile, nbar, base, s_red, s_out, s_ctl);
+  return gang_reduce_counter<L>(acc, a, tile, nbar, base, sm.red, sm.big, s_out, sm.ctl);
 }
 
-// Shared k-space state of one workgroup (all float64 unless noted).
-constexpr int kMaxNR = 16;
-template <int K>
-struct KSpace {
-  double y[K];
-  double d[K];
-  double gp[K];     // previous gradient
-  double dp[K];     // previous direction
-  double a[K];      // U^T eta
-  double red[kSlot];
-  double gd;        // g . d of the current step
-  float df[K];      // direction (float) for the row passes
-  float vf[K];      // v = y/||y||
-  float af[K];      // a (float)
-  float yf[K];
-  float scal[8];    // row-pass scalars
-  int flag[4];      // [0] stop CG, [1] bad frame, [2] do update
-};
+__device__ __forceinline__ void trace_point(const FrameArgs& a, int tile, int idx) {
+  if (a.trace && threadIdx.x == 0 && idx < 64) a.trace[(size_t)tile * 64 + idx] = wall_clock64();
+}
 
-// Workgroup-shared scratch of one frame tile (sized for the largest k / NR).
-struct FrameSmem {
-  KSpace<kMaxK> ks;
-  double red[kWaves][kSlot];
-  double wg[kSlot];
-  int ctl[4];
-  uint8_t flag[kBlock * kMaxNR];
-};
+template <int L>
+__device__ __forceinline__ bool gang_reduce(float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
+                                            unsigned base, unsigned ebase, FrameSmem& sm, double* s_out,
+                                            bool fenced = false) {
+  trace_point(a, tile, 2 + 2 * nbar);
+  const bool ok = gang_reduce_impl<L>(acc, a, tile, nbar, base, ebase, sm, s_out, fenced);
+  trace_point(a, tile, 1 + 2 * nbar);
+  return ok;
+}
+
 
 // One workgroup's share of one frame: tile `tile` (0 .. a.G-1) of the
 // stream described by `a`.  Returns false when the gang aborted.
@@ -401,6 +406,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   if (tid < 4) ks.flag[tid] = 0;
   __syncthreads();
 
+  trace_point(a, tile, 0);
   // ---- load the register tile: U rows, residual r = x - U y, weights ----
   const TS* __restrict__ Ug = (const TS*)a.U;
   const TS* __restrict__ xg = (const TS*)(a.xtab ? a.xtab[n % a.ring] : a.x);
@@ -450,12 +456,12 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, u[s][j], acc[j]);
     }
-    if (!gang_reduce<K + 1>(acc, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl)) return false;
+    if (!gang_reduce<K + 1>(acc, a, tile, nbar, base, ebase, sm, ks.red)) return false;
     // k-space: PR+ direction (wave 0, lane j owns component j)
     if (tid < 64) {
       const double g = (lane < K) ? -ks.red[lane] : 0.0;
       const double f = ks.red[K];
-      const double gg = wave_sum(g * g);
+      const double gg = row16_sum(g * g);
       int stop = 0;
       if (it == 0 && !(isfinite(f) && isfinite(gg))) {
         stop = 1;
@@ -466,18 +472,18 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       double beta = 0.0, dj = -g;
       if (!stop && it > 0) {
         const double gp = (lane < K) ? ks.gp[lane] : 0.0;
-        const double num = wave_sum(g * (g - gp));
-        const double den = wave_sum(gp * gp);
+        const double num = row16_sum(g * (g - gp));
+        const double den = row16_sum(gp * gp);
         beta = fmax(0.0, num / den);
         const double dpv = (lane < K) ? ks.dp[lane] : 0.0;
         dj = -g + beta * dpv;
-        const double gdv = wave_sum(g * dj);
+        const double gdv = row16_sum(g * dj);
         if (gdv >= 0.0) {
           dj = -g;
           if (lane == 0) ++restarts;
         }
       }
-      const double gd = wave_sum(g * dj);
+      const double gd = row16_sum(g * dj);
       if (lane < K) {
         ks.d[lane] = dj;
         ks.df[lane] = (float)dj;
@@ -501,7 +507,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       ud[s] = t;
       accb[0] = fmaf(cw[s] * t, t, accb[0]);
     }
-    if (!gang_reduce<1>(accb, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl)) return false;
+    if (!gang_reduce<1>(accb, a, tile, nbar, base, ebase, sm, ks.red)) return false;
     const double dHd = ks.red[0];
     if (!(dHd > 0.0)) break;   // same decision in every workgroup
     const double alpha = -ks.gd / dHd;
@@ -536,12 +542,12 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, u[s][j], acce[j]);
     }
-    if (!gang_reduce<K + 2>(acce, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl)) return false;
+    if (!gang_reduce<K + 2>(acce, a, tile, nbar, base, ebase, sm, ks.red)) return false;
     if (tid < 64) {
       const double av = (lane < K) ? ks.red[lane] : 0.0;
       const double yv = (lane < K) ? ks.y[lane] : 0.0;
-      const double aa = wave_sum(av * av);
-      const double yy = wave_sum(yv * yv);
+      const double aa = row16_sum(av * av);
+      const double yy = row16_sum(yv * yv);
       const double ee = ks.red[K];
       const double zeta = sqrt(fmax(ee - aa, 0.0));
       const double nu = sqrt(yy);
@@ -611,7 +617,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   {
     float accf[1] = {(float)fg};
-    if (!gang_reduce<1>(accf, a, tile, nbar, base, ebase, s_red, sm.wg, ks.red, s_ctl, true)) return false;
+    if (!gang_reduce<1>(accf, a, tile, nbar, base, ebase, sm, ks.red, true)) return false;
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const double fg_total = ks.red[0];
@@ -634,6 +640,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     }
   }
 
+  trace_point(a, tile, 63);
   if (lead && tid == 0) {
     a.stats->frame = n;
     a.stats->cg_steps = steps;

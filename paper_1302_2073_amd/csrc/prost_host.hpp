@@ -27,7 +27,8 @@ struct pros_handle {
   // launch configuration
   const void* kfn = nullptr;
   int G = 0, tpw = 0, NR = 0;
-  int sync_mode = 1;       // 0: counter barrier, 1: tagged gather/broadcast
+  int sync_mode = 1;       // 0: counter barrier, 1: tagged gather/broadcast, 2: two-level tagged
+  long long* trace = nullptr;   // optional per-tile timestamps (diagnostics)
   long long timeout_ticks = 0;
   // host bookkeeping
   long long submitted = 0;
@@ -49,8 +50,7 @@ pros_status check_usable(pros_handle* h);
 pros_status sync_and_check(pros_handle* h);
 prost::FrameArgs make_args(pros_handle* h, const void* x);
 pros_status reset_exchange(pros_handle* h);
-// True when a cooperative launch places workgroup b on XCD b % 8 (checked once).
-bool xcd_round_robin(hipStream_t stream);
+
 uint16_t bf16_rne(float f);
 float bf16_to_f32(uint16_t b);
 pros_status set_error(pros_status s, const char* fmt, ...);

@@ -187,15 +187,9 @@ def test_free_running_small_gray():
 def test_launch_variants(nr, sync_mode):
     """Register rows per thread (gangs of 452 / 113 / 57 workgroups) and the
     three gang exchanges give the same frame."""
-    from paper_1302_2073_amd import _lib as L
     wl, prm, sv, states = oracle_trajectory("qvga_rgb", 12)
     with _tracker(prm) as trk:
-        try:
-            trk.set_launch(nr, sync_mode)
-        except L.ProstError as e:
-            if e.status == L.PROS_EUNSUPPORTED and sync_mode == 2:
-                pytest.skip("workgroups are not placed round-robin over XCDs on this device")
-            raise
+        trk.set_launch(nr, sync_mode)
         say(f"qvga launch {trk.launch_info()}")
         rep = compare_step(trk, prm, states[12], f32(sv.frame(12)))
         assert rep["stats"]["fg_pixels"] == int(rep["labels"].sum())
