@@ -105,7 +105,8 @@ typedef struct pros_stats {
   double theta;                  /* geodesic angle sigma * t */
   double zeta;                   /* ||pi(eta)|| */
   double nu;                     /* ||y|| */
-  int64_t fg_pixels;             /* pixels labelled foreground (raw labels) */
+  int64_t fg_pixels;             /* pixels labelled foreground (raw labels); set
+                                    when the mask is computed on demand */
 } pros_stats;
 
 typedef struct pros_handle pros_handle;
@@ -151,7 +152,9 @@ PROS_API pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_
 PROS_API pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device);
 
 /* Copy the latest mask: filtered = 1 gives the 3x3-median mask F, 0 the raw
- * labels.  out holds P bytes on the host (on_device = 0, synchronises) or on
+ * labels.  The median of a frame's labels is computed at the start of the
+ * next frame's kernel, or here (one small kernel) when the mask of the
+ * latest frame is asked for first.  out holds P bytes on the host (on_device = 0, synchronises) or on
  * the device (on_device = 1, queued on the stream). */
 PROS_API pros_status pros_get_mask(pros_handle* h, uint8_t* out, int32_t filtered, int32_t on_device);
 
@@ -272,7 +275,9 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
  * 0 = one arrival counter per gang and every workgroup reading all partial
  * sums, 1 = epoch-tagged partial sums gathered by the gang's first
  * workgroup and broadcast back (default), 2 = the same in two levels
- * (groups of tiles t = x mod 8).  Results agree to float64 rounding.
+ * (groups of tiles t = x mod 8; every workgroup reads the 8 group sums),
+ * 3 = every workgroup reads all tagged partials (one hop, G^2 reads).
+ * Results agree to float64 rounding.
  * Synchronises. */
 PROS_API pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode);
 

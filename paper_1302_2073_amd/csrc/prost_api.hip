@@ -69,6 +69,31 @@ float bf16_to_f32(uint16_t b) {
 
 using namespace prost_host;
 
+// Mask of the latest frame on demand: 3x3 median of the raw labels and the
+// count of foreground labels (integer atomics: order-independent).
+__global__ void median_kernel(const uint8_t* __restrict__ lab, uint8_t* __restrict__ mask, int W, int H, int P,
+                              long long* __restrict__ fg) {
+  __shared__ unsigned cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const int p0 = blockIdx.x * blockDim.x;
+  const int npx = min((int)blockDim.x, P - p0);
+  prost::median3x3_range(lab, mask, W, H, p0, npx);
+  if ((int)threadIdx.x < npx && lab[p0 + threadIdx.x]) atomicAdd(&cnt, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt) atomicAdd((unsigned long long*)fg, (unsigned long long)cnt);
+}
+
+pros_status prost_host::refresh_mask(pros_handle* h) {
+  if (!h->mask_stale) return PROS_OK;
+  HIP_TRY(hipMemsetAsync(&h->stats->fg_pixels, 0, sizeof(long long), h->stream));
+  hipLaunchKernelGGL(median_kernel, dim3((h->P + 255) / 256), dim3(256), 0, h->stream, (const uint8_t*)h->lab,
+                     h->mask, h->prm.width, h->prm.height, h->P, (long long*)&h->stats->fg_pixels);
+  HIP_TRY(hipGetLastError());
+  h->mask_stale = false;
+  return PROS_OK;
+}
+
 // Entry points keep the C linkage of their declarations in prost.h.
 
 const char* pros_strerror(pros_status s) {
@@ -341,6 +366,7 @@ pros_status pros_set_state(pros_handle* h, const double* U, const double* y, con
   HIP_TRY(hipDeviceSynchronize());
   h->submitted = n;
   h->state_set = true;
+  h->mask_stale = true;
   return PROS_OK;
 }
 
@@ -479,6 +505,7 @@ pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, i
     return fail(PROS_EHIP, "frame kernel launch failed: %s", hipGetErrorString(e));
   }
   ++h->submitted;
+  h->mask_stale = true;
   if (h->prm.reorth_every > 0 && h->submitted % h->prm.reorth_every == 0) {
     st = prost_reorth_launch(h);
     if (st != PROS_OK) return st;
@@ -490,6 +517,10 @@ pros_status pros_get_mask(pros_handle* h, uint8_t* out, int32_t filtered, int32_
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
   if (!out) return fail(PROS_EINVAL, "out is NULL");
+  if (filtered) {
+    st = prost_host::refresh_mask(h);
+    if (st != PROS_OK) return st;
+  }
   const uint8_t* src = filtered ? h->mask : h->lab;
   if (on_device) {
     HIP_TRY(hipMemcpyAsync(out, src, (size_t)h->P, hipMemcpyDeviceToDevice, h->stream));
@@ -505,6 +536,8 @@ pros_status pros_get_stats(pros_handle* h, pros_stats* out) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
   if (!out) return fail(PROS_EINVAL, "out is NULL");
+  st = prost_host::refresh_mask(h);
+  if (st != PROS_OK) return st;
   st = sync_and_check(h);
   if (st != PROS_OK && st != PROS_EBADFRAME) return st;
   HIP_TRY(hipMemcpy(out, h->stats, sizeof(pros_stats), hipMemcpyDeviceToHost));
@@ -517,7 +550,7 @@ pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
   out->threads = prost::kBlock;
   out->rows_per_thread = h->NR;
   out->pixels_per_wg = h->tpw;
-  out->barriers_per_frame = 2 * h->prm.cg_iters + 2;
+  out->barriers_per_frame = 2 * h->prm.cg_iters + 1;
   out->sync_mode = h->sync_mode;
   return PROS_OK;
 }
@@ -534,7 +567,7 @@ pros_status prost_host::reset_exchange(pros_handle* h) {
 pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
-  if (sync_mode < 0 || sync_mode > 2) return fail(PROS_EINVAL, "sync_mode must be 0, 1 or 2");
+  if (sync_mode < 0 || sync_mode > 3) return fail(PROS_EINVAL, "sync_mode must be 0..3");
   if (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 && rows_per_thread != 4 &&
       rows_per_thread != 8 && rows_per_thread != 16)
     return fail(PROS_EINVAL, "rows_per_thread must be 0 (automatic), 1, 2, 4, 8 or 16");

@@ -358,7 +358,10 @@ pros_status pros_batch_track(pros_batch* b) {
     st = launch(b, b->stream);
     if (st != PROS_OK) return st;
   }
-  for (pros_handle* h : b->hs) ++h->submitted;
+  for (pros_handle* h : b->hs) {
+    ++h->submitted;
+    h->mask_stale = true;
+  }
   return PROS_OK;
 }
 
@@ -425,7 +428,7 @@ pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg) {
   if (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 8) return fail(PROS_EINVAL, "workgroups_per_cu must be 1..8");
   if (!(cfg->tile_scale > 0.0 && cfg->tile_scale <= 1.0)) return fail(PROS_EINVAL, "tile_scale must be in (0, 1]");
   if (cfg->strategy < 0 || cfg->strategy > 1) return fail(PROS_EINVAL, "strategy must be 0 or 1");
-  if (cfg->sync_mode < 0 || cfg->sync_mode > 2) return fail(PROS_EINVAL, "sync_mode must be 0, 1 or 2");
+  if (cfg->sync_mode < 0 || cfg->sync_mode > 3) return fail(PROS_EINVAL, "sync_mode must be 0..3");
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
   return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy, cfg->sync_mode);
@@ -499,7 +502,7 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
   pros_batch_config bc{};
   const double scales[] = {1.0, 0.75, 0.5};
   const int wpcs[] = {1, 2};
-  for (int sm = 0; sm < 3; ++sm)
+  for (int sm = 0; sm < 4; ++sm)
   for (int budget : kBudgets)
     for (int wpc : wpcs)
       for (double sc : scales)

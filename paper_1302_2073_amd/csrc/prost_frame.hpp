@@ -11,7 +11,9 @@
 //   for each CG step j:  A: g = -U^T(w phi'(r)), f = sum w phi(r)
 //                        B: d^T H d = sum w c(r) (u.d)^2
 //   eta pass:            a = U^T eta, ||eta||^2, f at the final y
-//   labels:              barrier so the median sees all labels
+// The 3x3 median of a frame's labels runs at the start of the next launch
+// (or in median_kernel when the mask is asked for first), which saves the
+// exchange that would otherwise separate the label writes from the median.
 // Every workgroup reduces the published partials in the same fixed order, so
 // all of them hold bit-identical k-vectors without a broadcast step.
 #pragma once
@@ -45,7 +47,8 @@ struct FrameArgs {
   long long timeout;     // wall-clock ticks a barrier may wait
   long long* trace;      // optional per-tile timestamps (diagnostics), 64 per tile
   int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
-                         // 2: two-level tagged gather (groups of tiles with equal t % 8)
+                         // 2: two-level tagged gather (groups of tiles with equal t % 8),
+                         // 3: every workgroup reads all tagged partials
 };
 
 constexpr int kReplicas = 8;      // copies of a gathered result (spread the pollers)
@@ -171,28 +174,67 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
   return s_ctl[1] == 0;
 }
 
+// Tagged all-read helpers: poll n tagged slots (stride kSlot) until every
+// component carries the epoch, summing component c in slot order.  Thread
+// layout: component tid % 32, slots tid / 32, tid / 32 + kRows, ...; the kRows
+// partial sums are then added in order.  Uniform exit; false on timeout.
+template <int L>
+__device__ __forceinline__ bool poll_sum_slots(const double* slots, int nslots, unsigned ep, const FrameArgs& a,
+                                               double* s_big, double* out) {
+  const int tid = threadIdx.x;
+  constexpr int kRows = kBlock / 32;
+  const int comp = tid & 31, row0 = tid >> 5;
+  const long long t0 = now_ticks();
+  double v = 0.0;
+  while (true) {
+    int ok = 1;
+    v = 0.0;
+    if (comp < L)
+      for (int q = row0; q < nslots; q += kRows) {
+        const double val = ld_tagged(&slots[(size_t)q * kSlot + comp]);
+        ok &= (tag_of(val) == ep) ? 1 : 0;
+        v += untag(val);
+      }
+    if (__syncthreads_and(ok)) break;
+    const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
+                                    (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
+    if (__syncthreads_or(late)) {
+      if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  s_big[tid] = v;
+  __syncthreads();
+  if (tid < L) {
+    double tot = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) tot += s_big[r * 32 + tid];
+    out[tid] = tot;
+  }
+  __syncthreads();
+  return true;
+}
+
 // Two-level tagged exchange: the tiles t = x, x + 8, x + 16, ... form group x
-// (x < 8); group x's first tile gathers their tagged partials and sums them
-// in tile order, the (at most 8) group leaders exchange their sums and add
-// them in group order, and each leader hands the total back to its group.
-// Fewer pollers per cache line and a fan-in of G/8 per leader instead of G.
-// Every workgroup ends with bit-identical totals.
+// (x < 8); group x's first tile gathers their tagged partials and publishes
+// the group sum; every workgroup then reads the (at most 8) group sums and
+// adds them in group order.  Two hops; every workgroup ends with
+// bit-identical totals.
 template <int L>
 __device__ __forceinline__ bool gang_reduce_2level(const double* wg_sum, const FrameArgs& a, const int tile,
-                                                int& nbar, unsigned ebase, double* s_big,
-                                                double* s_out, int* s_ctl, bool fenced) {
+                                                   int& nbar, unsigned ebase, double* s_big,
+                                                   double* s_out, int* s_ctl, bool fenced) {
   const int tid = threadIdx.x;
   ++nbar;
   const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
   const int x = tile & 7;
   const int ngrp = min(8, a.G);
-  double* slots = a.part;                                         // G level-1 slots
-  double* xres = a.part + (size_t)a.G * kSlot;                    // 2 x 8 level-2 slots
-  double* bc = xres + (size_t)16 * kSlot;                         // 8 level-3 slots
+  double* slots = a.part;                                            // G level-1 slots
+  double* gs = a.part + (size_t)a.G * kSlot + (size_t)(nbar & 1) * 8 * kSlot;   // 2 x 8 group sums
   if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (tid < L) st_tagged(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
-  if (tile < 8) {   // XCD leader
-    const int n = (a.G - x + 7) >> 3;          // tiles x, x+8, ...
+  if (tile < 8) {   // group leader: members x, x + 8, ... (slot stride 8)
+    const int n = (a.G - x + 7) >> 3;
     const int comp = tid & 31, row0 = tid >> 5;
     constexpr int kRows = kBlock / 32;
     const long long t0 = now_ticks();
@@ -214,69 +256,35 @@ __device__ __forceinline__ bool gang_reduce_2level(const double* wg_sum, const F
         return false;
       }
     }
-    double* s_tmp = s_big;
-    s_tmp[tid] = v;
+    s_big[tid] = v;
     __syncthreads();
-    double* xr = xres + (size_t)(nbar & 1) * 8 * kSlot;
     if (tid < L) {
       double g = 0.0;
-      for (int r = 0; r < kRows; ++r) g += s_tmp[r * 32 + tid];
-      st_tagged(&xr[(size_t)x * kSlot + tid], tag_value(g, ep));
+      for (int r = 0; r < kRows; ++r) g += s_big[r * 32 + tid];
+      st_tagged(&gs[(size_t)x * kSlot + tid], tag_value(g, ep));
     }
-    // level 2: all XCD sums, added in XCD order
-    const long long t1 = now_ticks();
-    double tot = 0.0;
-    while (true) {
-      int ok = 1;
-      tot = 0.0;
-      if (tid < L)
-        for (int gq = 0; gq < ngrp; ++gq) {
-          const double val = ld_tagged(&xr[(size_t)gq * kSlot + tid]);
-          ok &= (tag_of(val) == ep) ? 1 : 0;
-          tot += untag(val);
-        }
-      if (__syncthreads_and(ok)) break;
-      const int late = (tid == 0) && (now_ticks() - t1 > a.timeout ||
-                                      (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
-      if (__syncthreads_or(late)) {
-        if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-    if (tid < L) {
-      s_out[tid] = untag(tag_value(tot, ep));
-      st_tagged(&bc[(size_t)x * kSlot + tid], tag_value(tot, ep));
-    }
-    if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
-    return true;
   }
-  // members: wait for the XCD leader's total
-  if (tid == 0) s_ctl[1] = 0;
-  __syncthreads();
-  if (tid < L) {
-    const double* src = &bc[(size_t)x * kSlot + tid];
-    const long long t0 = now_ticks();
-    unsigned spins = 0;
-    while (true) {
-      const double val = ld_tagged(src);
-      if (tag_of(val) == ep) {
-        s_out[tid] = untag(val);
-        break;
-      }
-      if ((++spins & 63u) == 0) {
-        if ((__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout) ||
-            now_ticks() - t0 > a.timeout) {
-          __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s_ctl[1] = 1;
-          break;
-        }
-      }
-    }
-  }
+  if (!poll_sum_slots<L>(gs, ngrp, ep, a, s_big, s_out)) return false;
   if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  __syncthreads();
-  return s_ctl[1] == 0;
+  return true;
+}
+
+// One-hop tagged exchange: every workgroup publishes its tagged partial and
+// reads all G of them directly (G^2 small reads, one round trip).
+template <int L>
+__device__ __forceinline__ bool gang_reduce_allread(const double* wg_sum, const FrameArgs& a, const int tile,
+                                                    int& nbar, unsigned ebase, double* s_big,
+                                                    double* s_out, bool fenced) {
+  const int tid = threadIdx.x;
+  ++nbar;
+  const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
+  double* slots = a.part + (size_t)(nbar & 1) * a.G * kSlot;      // double-buffered
+  if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (tid < L) st_tagged(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
+  if (!poll_sum_slots<L>(slots, a.G, ep, a, s_big, s_out)) return false;
+  if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
 }
 
 // Workgroup sum of L float partials (one value per thread each), float64
@@ -360,6 +368,10 @@ __device__ __forceinline__ bool gang_reduce_impl(float (&acc)[L], const FrameArg
     wg_reduce<L>(acc, sm.red, sm.wg);
     return gang_reduce_2level<L>(sm.wg, a, tile, nbar, ebase, sm.big, s_out, sm.ctl, fenced);
   }
+  if (a.sync_mode == 3) {
+    wg_reduce<L>(acc, sm.red, sm.wg);
+    return gang_reduce_allread<L>(sm.wg, a, tile, nbar, ebase, sm.big, s_out, fenced);
+  }
   return gang_reduce_counter<L>(acc, a, tile, nbar, base, sm.red, sm.big, s_out, sm.ctl);
 }
 
@@ -377,6 +389,24 @@ __device__ __forceinline__ bool gang_reduce(float (&acc)[L], const FrameArgs& a,
   return ok;
 }
 
+
+// 3x3 median of binary labels (>= 5 of the 9 neighbours, edges replicated,
+// Sec. 3.4) for pixels [p0, p0 + npx) of a W x H image.
+__device__ __forceinline__ void median3x3_range(const uint8_t* __restrict__ lab, uint8_t* __restrict__ mask, int W,
+                                                int H, int p0, int npx) {
+  for (int pl = threadIdx.x; pl < npx; pl += blockDim.x) {
+    const int pix = p0 + pl;
+    const int row = pix / W, col = pix - row * W;
+    const int rows[3] = {max(row - 1, 0), row, min(row + 1, H - 1)};
+    const int cols[3] = {max(col - 1, 0), col, min(col + 1, W - 1)};
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cnt += lab[rows[i] * W + cols[j]];
+    mask[pix] = (cnt >= 5) ? 1 : 0;
+  }
+}
 
 // One workgroup's share of one frame: tile `tile` (0 .. a.G-1) of the
 // stream described by `a`.  Returns false when the gang aborted.
@@ -407,6 +437,11 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   __syncthreads();
 
   trace_point(a, tile, 0);
+  // ---- mask of the previous frame: 3x3 median of the labels now in memory
+  // (written by the previous launch; no workgroup rewrites labels before the
+  // last exchange of this frame, which every workgroup reaches after this) ----
+  median3x3_range(a.lab, a.mask, a.W, a.H, p0, npx);
+  __syncthreads();
   // ---- load the register tile: U rows, residual r = x - U y, weights ----
   const TS* __restrict__ Ug = (const TS*)a.U;
   const TS* __restrict__ xg = (const TS*)(a.xtab ? a.xtab[n % a.ring] : a.x);
@@ -524,7 +559,6 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     __syncthreads();
   }
   const bool bad = ks.flag[1] != 0;
-  int fg = 0;
 
   // ---- Step 2: eta pass (a = U^T eta, ||eta||^2, final cost) ----
   float acce[K + 2];
@@ -609,37 +643,9 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       uint8_t f = 0;
       for (int c = 0; c < a.C; ++c) f |= s_flag[c * npx + pl];
       a.lab[p0 + pl] = f;
-      fg += f;
     }
   }
-  // all label writes visible before the median reads its neighbours; the
-  // exchange also sums the foreground count
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  {
-    float accf[1] = {(float)fg};
-    if (!gang_reduce<1>(accf, a, tile, nbar, base, ebase, sm, ks.red, true)) return false;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  const double fg_total = ks.red[0];
-
-  if (!bad) {
-    // ---- 3x3 median of the labels (>= 5 of 9, edges replicated) ----
-    for (int pl = tid; pl < npx; pl += kBlock) {
-      const int pix = p0 + pl;
-      const int row = pix / a.W, col = pix - row * a.W;
-      const int r0 = max(row - 1, 0), r2 = min(row + 1, a.H - 1);
-      const int c0 = max(col - 1, 0), c2 = min(col + 1, a.W - 1);
-      int cnt = 0;
-      const int rows[3] = {r0, row, r2};
-      const int cols[3] = {c0, col, c2};
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) cnt += a.lab[rows[i] * a.W + cols[j]];
-      a.mask[pix] = (cnt >= 5) ? 1 : 0;
-    }
-  }
-
+  // the labels are read by the next frame's launch (median and weights)
   trace_point(a, tile, 63);
   if (lead && tid == 0) {
     a.stats->frame = n;
@@ -651,7 +657,6 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     } else {
       *a.nframe = n + 1;
     }
-    a.stats->fg_pixels = (long long)fg_total;
     if (a.sync_mode != 0)
       __hip_atomic_store(&a.sync[3], ebase + (unsigned)nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else

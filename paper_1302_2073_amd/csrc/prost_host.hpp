@@ -29,6 +29,7 @@ struct pros_handle {
   int G = 0, tpw = 0, NR = 0;
   int sync_mode = 1;       // 0: counter barrier, 1: tagged gather/broadcast, 2: two-level tagged
   long long* trace = nullptr;   // optional per-tile timestamps (diagnostics)
+  bool mask_stale = true;       // mask not yet computed from the latest labels
   long long timeout_ticks = 0;
   // host bookkeeping
   long long submitted = 0;
@@ -50,6 +51,9 @@ pros_status check_usable(pros_handle* h);
 pros_status sync_and_check(pros_handle* h);
 prost::FrameArgs make_args(pros_handle* h, const void* x);
 pros_status reset_exchange(pros_handle* h);
+// Compute the mask (and foreground count) of the latest labels if a frame
+// kernel has not done so yet.  Queued on the handle's stream.
+pros_status refresh_mask(pros_handle* h);
 
 uint16_t bf16_rne(float f);
 float bf16_to_f32(uint16_t b);

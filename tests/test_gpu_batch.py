@@ -68,7 +68,7 @@ def _load(bt, streams):
     for s, (sv, prm, st) in enumerate(streams):
         bt.set_state(s, st.U, st.y, st.labels, st.n)
         U0, y0, l0, n0 = bt.get_state(s)
-        starts.append(O.State(U0, y0, l0, l0.copy(), n0))
+        starts.append(O.State(U0, y0, l0, O.median3x3(l0, prm.height, prm.width), n0))
     return starts
 
 
@@ -94,9 +94,9 @@ def test_batch_step_matches_oracle_per_stream(cfg):
             nxt.append(_check_stream(bt, s, prm, starts[s], f32(sv.frame(4))))
         # second step reads ring slot 1, continuing from the GPU's own state
         starts2 = []
-        for s in range(len(streams)):
+        for s, (sv, prm, st) in enumerate(streams):
             U0, y0, l0, n0 = bt.get_state(s)
-            starts2.append(O.State(U0, y0, l0, l0.copy(), n0))
+            starts2.append(O.State(U0, y0, l0, O.median3x3(l0, prm.height, prm.width), n0))
         bt.step()
         for s, (sv, prm, st) in enumerate(streams):
             _check_stream(bt, s, prm, starts2[s], f32(sv.frame(5)))

@@ -182,11 +182,11 @@ def test_free_running_small_gray():
     assert worst <= 0.005
 
 
-@pytest.mark.parametrize("sync_mode", [0, 1, 2])
+@pytest.mark.parametrize("sync_mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("nr", [1, 4, 8])
 def test_launch_variants(nr, sync_mode):
     """Register rows per thread (gangs of 452 / 113 / 57 workgroups) and the
-    three gang exchanges give the same frame."""
+    four gang exchanges give the same frame."""
     wl, prm, sv, states = oracle_trajectory("qvga_rgb", 12)
     with _tracker(prm) as trk:
         trk.set_launch(nr, sync_mode)
