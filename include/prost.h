@@ -177,7 +177,7 @@ typedef struct pros_launch_info {
   int32_t rows_per_thread;   /* register-resident rows of U per thread */
   int32_t pixels_per_wg;     /* pixels of one workgroup tile */
   int32_t barriers_per_frame;/* gang-wide reductions per frame */
-  int32_t sync_mode;         /* 0: counter barrier, 1: tagged gather/broadcast */
+  int32_t sync_mode;         /* gang exchange, as in pros_set_launch */
 } pros_launch_info;
 PROS_API pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out);
 
@@ -269,13 +269,16 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
                             float* dX, float* dU, float* dY, float* dmu,
                             void* workspace, size_t workspace_bytes, void* hip_stream);
 
-/* Launch tuning of a single-stream handle: rows_per_thread (0 = automatic,
- * else 1, 2, 4, 8 or 16; the frame's pixels must fit the resident
- * workgroups) and the gang exchange used for the frame's reductions:
+/* Launch tuning of a single-stream handle: rows_per_thread (0 = automatic:
+ * the smallest tile whose gang fits one workgroup per compute unit; else
+ * 1, 2, 4, 8, 16 (k <= 8 for float32) or, for bfloat16 storage, whose tiles
+ * hold row pairs, 2, 4, 8, 16 or 32 (k <= 8); the frame's pixels must fit
+ * the resident workgroups) and the gang exchange used for the frame's
+ * reductions:
  * 0 = one arrival counter per gang and every workgroup reading all partial
  * sums, 1 = epoch-tagged partial sums gathered by the gang's first
- * workgroup and broadcast back (default), 2 = the same in two levels
- * (groups of tiles t = x mod 8; every workgroup reads the 8 group sums),
+ * workgroup and broadcast back, 2 = the same in two levels (groups of
+ * tiles t = x mod 8; every workgroup reads the 8 group sums; default),
  * 3 = every workgroup reads all tagged partials (one hop, G^2 reads).
  * Results agree to float64 rounding.
  * Synchronises. */

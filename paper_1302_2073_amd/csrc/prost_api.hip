@@ -173,8 +173,25 @@ void prost_host::free_handle(pros_handle* h) {
 // Pick the register rows per thread NR: the largest NR whose gang fits in
 // the resident workgroups, so that the gang (and with it the cost of every
 // gang-wide exchange) is as small as possible.
+int prost_host::tile_pixels(int storage, int NR, int channels, double scale) {
+  const int full = prost::kBlock * NR / channels;
+  int tpw = (int)std::floor(prost::kBlock * NR * scale / channels);
+  tpw = std::max(1, std::min(tpw, full));
+  if (storage == PROS_BF16 && tpw > 1) tpw &= ~1;
+  return tpw;
+}
+
+bool prost_host::pair_layout(const pros_handle* h) {
+  return h->prm.storage == PROS_BF16 && h->P % 2 == 0 && h->tpw % 2 == 0 && h->ldU % 2 == 0;
+}
+
+// Register rows per thread for a single stream.  A frame is latency-bound
+// (its gang-wide exchanges), so the fastest tile is the smallest one whose
+// gang still fits one workgroup per compute unit: more rows per thread only
+// add work per workgroup.  Frames too large for that take the largest tile
+// that is resident.  force_nr > 0 asks for one row count.
 static pros_status choose_launch(pros_handle* h, int force_nr) {
-  const int nrs[] = {16, 8, 4, 2, 1};
+  const int nrs[] = {1, 2, 4, 8, 16, 32};
   const void* best = nullptr;
   int bestNR = 0, bestG = 0, bestT = 0;
   for (int NR : nrs) {
@@ -182,15 +199,14 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
     const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR)
                                                   : prost::frame_kernel_f32(h->k, NR);
     if (!f) continue;
-    const int tpw = (prost::kBlock * NR) / h->C;
-    if (tpw < 1) continue;
+    if (prost::kBlock * NR < h->C) continue;
+    const int tpw = prost_host::tile_pixels(h->prm.storage, NR, h->C, 1.0);
     const long long G = (h->P + tpw - 1) / tpw;
     int occ = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0));
-    const long long cap = (long long)occ * h->num_cu;
-    if (G > cap) continue;
+    if (G > (long long)occ * h->num_cu) continue;   // not resident
     best = f; bestNR = NR; bestG = (int)G; bestT = tpw;
-    break;
+    if (G <= h->num_cu) break;                      // smallest tile at one workgroup per CU
   }
   if (!best)
     return fail(PROS_EUNSUPPORTED, "frame of %d pixels x %d channels at k=%d does not fit the device's resident workgroups",
@@ -449,6 +465,7 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.timeout = h->timeout_ticks;
   a.sync_mode = h->sync_mode;
   a.trace = h->trace;
+  a.pair_aligned = (pair_layout(h) && ((uintptr_t)x & 3u) == 0) ? 1 : 0;
   return a;
 }
 
@@ -569,8 +586,8 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   if (st != PROS_OK) return st;
   if (sync_mode < 0 || sync_mode > 3) return fail(PROS_EINVAL, "sync_mode must be 0..3");
   if (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 && rows_per_thread != 4 &&
-      rows_per_thread != 8 && rows_per_thread != 16)
-    return fail(PROS_EINVAL, "rows_per_thread must be 0 (automatic), 1, 2, 4, 8 or 16");
+      rows_per_thread != 8 && rows_per_thread != 16 && rows_per_thread != 32)
+    return fail(PROS_EINVAL, "rows_per_thread must be 0 (automatic), 1, 2, 4, 8, 16 or 32");
   HIP_TRY(hipStreamSynchronize(h->stream));
   const int oldG = h->G;
   st = choose_launch(h, rows_per_thread);

@@ -62,7 +62,7 @@ struct pros_batch {
   int nwg = 0;
   int rounds = 0;
   int strategy = 0;
-  int sync_mode = 1;
+  int sync_mode = 2;
   double tile_scale = 1.0;
   const void* kfn = nullptr;
   FrameArgs* d_descs = nullptr;
@@ -70,6 +70,7 @@ struct pros_batch {
   const void** d_xtab = nullptr;
   int ring = 1;
   bool frames_set = false;
+  std::vector<char> frames_aligned;   // per stream: every ring frame 4-byte aligned
   std::vector<FrameArgs> descs;
   std::vector<BatchItem> items;
   // graph
@@ -140,9 +141,8 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
   const int wpc = std::min(occ, wg_per_cu);
   const int nwg = wpc * b->num_cu;
   for (pros_handle* h : b->hs) {
-    const int NR = prost::batch_nr(budget, b->kclass);
-    int tpw = (int)std::floor(prost::kBlock * NR * tile_scale / h->C);
-    tpw = std::max(1, std::min(tpw, prost::kBlock * NR / h->C));
+    const int NR = prost::batch_rows(b->storage == PROS_BF16, budget, b->kclass);
+    const int tpw = prost_host::tile_pixels(b->storage, NR, h->C, tile_scale);
     const int G = (h->P + tpw - 1) / tpw;
     if (G > nwg) return fail(PROS_EUNSUPPORTED, "a %dx%dx%d stream at k=%d needs %d workgroups (> %d)",
                              h->prm.width, h->prm.height, h->C, h->k, G, nwg);
@@ -173,6 +173,7 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
     FrameArgs a = prost_host::make_args(b->hs[s], nullptr);
     a.xtab = b->d_xtab + (size_t)s * b->ring;
     a.ring = b->ring;
+    a.pair_aligned = (prost_host::pair_layout(b->hs[s]) && b->frames_aligned[s]) ? 1 : 0;
     b->descs[s] = a;
   }
   if (b->d_items) (void)hipFree(b->d_items);
@@ -234,6 +235,7 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
   pros_batch* b = new pros_batch();
   b->n = n;
   b->storage = storage;
+  b->frames_aligned.assign(n, 1);
   b->stream = (hipStream_t)hip_stream;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -252,8 +254,8 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
   }
   for (int s = 0; s < n; ++s) {
     pros_handle* h = nullptr;
-    const int NR = prost::batch_nr(128, b->kclass);
-    const int tpw = prost::kBlock * NR / per_stream[s].channels;
+    const int NR = prost::batch_rows(storage == PROS_BF16, 128, b->kclass);
+    const int tpw = prost_host::tile_pixels(storage, NR, per_stream[s].channels, 1.0);
     const int P = per_stream[s].width * per_stream[s].height;
     pros_status st = prost_host::create_handle(&per_stream[s], b->stream, NR, tpw, (P + tpw - 1) / tpw, &h);
     if (st != PROS_OK) {
@@ -268,7 +270,7 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
     free_batch(b);
     return fail(PROS_ENOMEM, "batch tables: %s", hipGetErrorString(e));
   }
-  pros_status st = configure(b, 128, 2, 1.0, 0, 1);
+  pros_status st = configure(b, 128, 2, 1.0, 0, 2);
   if (st != PROS_OK) {
     free_batch(b);
     return st;
@@ -304,6 +306,7 @@ pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int3
     if (!frames[i]) return fail(PROS_EINVAL, "frame pointer %d is NULL", i);
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
+  bool descs_changed = false;
   if (ring != b->ring) {
     (void)hipFree((void*)b->d_xtab);
     b->d_xtab = nullptr;
@@ -314,9 +317,22 @@ pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int3
       b->descs[s].xtab = b->d_xtab + (size_t)s * ring;
       b->descs[s].ring = ring;
     }
+    descs_changed = true;
+    drop_graph(b);
+  }
+  for (int s = 0; s < b->n; ++s) {
+    bool al = true;
+    for (int i = 0; i < ring; ++i) al = al && (((uintptr_t)frames[(size_t)s * ring + i] & 3u) == 0);
+    b->frames_aligned[s] = al ? 1 : 0;
+    const int pa = (prost_host::pair_layout(b->hs[s]) && al) ? 1 : 0;
+    if (b->descs[s].pair_aligned != pa) {
+      b->descs[s].pair_aligned = pa;
+      descs_changed = true;
+    }
+  }
+  if (descs_changed) {   // descriptors are read by the kernel at run time (also from a graph)
     e = hipMemcpy(b->d_descs, b->descs.data(), sizeof(FrameArgs) * b->n, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(PROS_EHIP, "descriptor upload: %s", hipGetErrorString(e));
-    drop_graph(b);
   }
   e = hipMemcpy((void*)b->d_xtab, frames, sizeof(void*) * (size_t)b->n * ring, hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(PROS_EHIP, "frame table upload: %s", hipGetErrorString(e));

@@ -24,12 +24,19 @@ struct BatchItem {
 };
 
 // Subspace-dimension classes with a batch kernel, and register rows per
-// thread for a budget of about `budget` floats of U per thread.
+// thread for a budget of about `budget` 32-bit registers of U per thread:
+// one float32 row entry or one bfloat16 row-pair entry per register.
 constexpr int kBatchClasses[] = {2, 4, 5, 8, 10, 12, 15, 16};
 constexpr int kNumBatchClasses = 8;
 
 __host__ __device__ constexpr int batch_nr(int budget, int K) {
   return (budget / K >= 16) ? 16 : (budget / K < 1 ? 1 : budget / K);
+}
+__host__ __device__ constexpr int batch_nr_bf16(int budget, int K) {
+  return 2 * batch_nr(budget, K);
+}
+__host__ __device__ constexpr int batch_rows(int storage_bf16, int budget, int K) {
+  return storage_bf16 ? batch_nr_bf16(budget, K) : batch_nr(budget, K);
 }
 
 __host__ __device__ constexpr int batch_class(int k) {
@@ -44,7 +51,7 @@ __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __res
     const BatchItem it = items[(size_t)r * gridDim.x + blockIdx.x];
     if (it.stream < 0) continue;
     const FrameArgs a = descs[it.stream];
-    if (!frame_tile<K, NR, TS>(a, it.tile, sm)) return;
+    if (!run_tile<K, NR, TS>(a, it.tile, sm)) return;
   }
 }
 

@@ -5,8 +5,8 @@
 namespace prost {
 const void* batch_kernel_k15(int storage_bf16, int budget) {
   if (storage_bf16)
-    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr(64, 15)>
-                        : (const void*)&batch_kernel<uint16_t, 15, batch_nr(128, 15)>;
+    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(64, 15)>
+                        : (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(128, 15)>;
   return budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15)>
                       : (const void*)&batch_kernel<float, 15, batch_nr(128, 15)>;
 }

@@ -5,8 +5,8 @@
 namespace prost {
 const void* batch_kernel_k2(int storage_bf16, int budget) {
   if (storage_bf16)
-    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 2, batch_nr(64, 2)>
-                        : (const void*)&batch_kernel<uint16_t, 2, batch_nr(128, 2)>;
+    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 2, batch_nr_bf16(64, 2)>
+                        : (const void*)&batch_kernel<uint16_t, 2, batch_nr_bf16(128, 2)>;
   return budget == 64 ? (const void*)&batch_kernel<float, 2, batch_nr(64, 2)>
                       : (const void*)&batch_kernel<float, 2, batch_nr(128, 2)>;
 }

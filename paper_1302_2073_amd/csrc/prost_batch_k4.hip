@@ -5,8 +5,8 @@
 namespace prost {
 const void* batch_kernel_k4(int storage_bf16, int budget) {
   if (storage_bf16)
-    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 4, batch_nr(64, 4)>
-                        : (const void*)&batch_kernel<uint16_t, 4, batch_nr(128, 4)>;
+    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 4, batch_nr_bf16(64, 4)>
+                        : (const void*)&batch_kernel<uint16_t, 4, batch_nr_bf16(128, 4)>;
   return budget == 64 ? (const void*)&batch_kernel<float, 4, batch_nr(64, 4)>
                       : (const void*)&batch_kernel<float, 4, batch_nr(128, 4)>;
 }

@@ -3,8 +3,9 @@
 //
 // One launch processes one frame.  The m x k subspace U is split into
 // workgroup tiles of `tpw` pixels (all colour entries of a pixel stay in one
-// tile); each thread keeps up to NR rows of U (K floats each) in registers for
-// the whole frame, so U is read from HBM once and written once per frame.
+// tile); each thread keeps NR rows of U in registers for the whole frame (K
+// floats per row, or K bfloat16 pairs per two rows with bfloat16 storage), so
+// U is read from HBM once and written once per frame.
 // The frame's sequence of dependent reductions runs as gang-wide reductions
 // between all workgroups of the launch (cooperative launch, so all of them
 // are resident):
@@ -46,6 +47,7 @@ struct FrameArgs {
   int weights_from_filtered;
   long long timeout;     // wall-clock ticks a barrier may wait
   long long* trace;      // optional per-tile timestamps (diagnostics), 64 per tile
+  int pair_aligned;      // bfloat16: row pairs are aligned 32-bit words (U planes and frame)
   int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
                          // 2: two-level tagged gather (groups of tiles with equal t % 8),
                          // 3: every workgroup reads all tagged partials
@@ -55,7 +57,7 @@ constexpr int kReplicas = 8;      // copies of a gathered result (spread the pol
 constexpr int kExtraSlots = 32;   // slots beyond 2 G: replicas / XCD-level slots
 
 // Shared k-space state of one workgroup (all float64 unless noted).
-constexpr int kMaxNR = 16;
+constexpr int kMaxNR = 32;   // register rows per thread (bfloat16 pairs at small k)
 template <int K>
 struct KSpace {
   double y[K];
@@ -408,26 +410,33 @@ __device__ __forceinline__ void median3x3_range(const uint8_t* __restrict__ lab,
   }
 }
 
-// One workgroup's share of one frame: tile `tile` (0 .. a.G-1) of the
-// stream described by `a`.  Returns false when the gang aborted.
-template <int K, int NR, typename TS>
-__device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
-  KSpace<kMaxK>& ks = sm.ks;
-  double (*s_red)[kSlot] = sm.red;
-  int* s_ctl = sm.ctl;
-  uint8_t* s_flag = sm.flag;
+// ---------------------------------------------------------------------------
+// Pieces shared by the two register layouts of a tile
+// ---------------------------------------------------------------------------
 
+// Per-tile constants.
+struct TileCtx {
+  int p0, npx, nq;        // first pixel, pixels, register rows (npx * C)
+  unsigned base, ebase;   // exchange counter / epoch bases of this launch
+  long long n;            // frame index
+  bool lead;              // tile 0 writes the stream's statistics and y
+};
+
+// Reads y and the frame index, then filters the previous frame's labels of
+// this tile into the mask (the labels were written by the previous launch; no
+// workgroup rewrites labels before the last exchange of this frame, which
+// every workgroup reaches only after this point).
+template <int K>
+__device__ __forceinline__ TileCtx tile_begin(const FrameArgs& a, const int tile, KSpace<kMaxK>& ks) {
+  TileCtx t;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int p0 = tile * a.tpw;
-  const int npx = min(a.tpw, a.P - p0);
-  const int nq = npx * a.C;
-  const unsigned base = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const unsigned ebase = __hip_atomic_load(&a.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  int nbar = 0;
-  const long long n = *a.nframe;
-  const bool lead = (tile == 0);
-
+  t.p0 = tile * a.tpw;
+  t.npx = min(a.tpw, a.P - t.p0);
+  t.nq = t.npx * a.C;
+  t.base = __hip_atomic_load(&a.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  t.ebase = __hip_atomic_load(&a.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  t.n = *a.nframe;
+  t.lead = (tile == 0);
   if (tid < K) {
     const double yv = (tid < a.k) ? a.y[tid] : 0.0;
     ks.y[tid] = yv;
@@ -435,19 +444,174 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   }
   if (tid < 4) ks.flag[tid] = 0;
   __syncthreads();
-
   trace_point(a, tile, 0);
-  // ---- mask of the previous frame: 3x3 median of the labels now in memory
-  // (written by the previous launch; no workgroup rewrites labels before the
-  // last exchange of this frame, which every workgroup reaches after this) ----
-  median3x3_range(a.lab, a.mask, a.W, a.H, p0, npx);
+  median3x3_range(a.lab, a.mask, a.W, a.H, t.p0, t.npx);
   __syncthreads();
+  trace_point(a, tile, 1);
+  return t;
+}
+
+// PR+ conjugate direction from the reduced gradient and cost in ks.red
+// (Sec. 3.3, Step 1): wave 0, lane j owns component j.  Sets ks.d / df / gp,
+// ks.gd and the stop flag ks.flag[0]; a non-finite first cost marks the frame
+// bad (ks.flag[1]).
+template <int K>
+__device__ __forceinline__ void cg_direction(const FrameArgs& a, KSpace<kMaxK>& ks, int it, bool lead,
+                                             int& restarts) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    const double g = (lane < K) ? -ks.red[lane] : 0.0;
+    const double f = ks.red[K];
+    const double gg = row16_sum(g * g);
+    int stop = 0;
+    if (it == 0 && !(isfinite(f) && isfinite(gg))) {
+      stop = 1;
+      if (lane == 0) ks.flag[1] = 1;
+    }
+    if (gg == 0.0) stop = 1;
+    if (lead && lane == 0) a.stats->f[it] = f;
+    double beta = 0.0, dj = -g;
+    if (!stop && it > 0) {
+      const double gp = (lane < K) ? ks.gp[lane] : 0.0;
+      const double num = row16_sum(g * (g - gp));
+      const double den = row16_sum(gp * gp);
+      beta = fmax(0.0, num / den);
+      const double dpv = (lane < K) ? ks.dp[lane] : 0.0;
+      dj = -g + beta * dpv;
+      const double gdv = row16_sum(g * dj);
+      if (gdv >= 0.0) {
+        dj = -g;
+        if (lane == 0) ++restarts;
+      }
+    }
+    const double gd = row16_sum(g * dj);
+    if (lane < K) {
+      ks.d[lane] = dj;
+      ks.df[lane] = (float)dj;
+      ks.gp[lane] = g;
+    }
+    if (lane == 0) {
+      ks.gd = gd;
+      ks.flag[0] = stop;
+      if (lead) a.stats->beta[it] = beta;
+    }
+  }
+  __syncthreads();
+}
+
+// Majoriser step along d: alpha = -g.d / d^T H d, y += alpha d.  Returns
+// alpha as float for the residual update.
+template <int K>
+__device__ __forceinline__ float cg_advance(const FrameArgs& a, KSpace<kMaxK>& ks, double dHd, int it, bool lead) {
+  const int tid = threadIdx.x;
+  const double alpha = -ks.gd / dHd;
+  __syncthreads();
+  if (tid < K) {
+    ks.y[tid] += alpha * ks.d[tid];
+    ks.dp[tid] = ks.d[tid];
+  }
+  if (lead && tid == 0) a.stats->alpha[it] = alpha;
+  return (float)alpha;
+}
+
+// Scalars of the rank-one geodesic step (Sec. 3.3, Step 2) from the reduced
+// a = U^T eta, ||eta||^2 and the final cost in ks.red: zeta = ||pi(eta)||,
+// nu = ||y||, sigma = zeta nu, theta = sigma t_n; row-pass coefficients in
+// ks.scal / vf / af.
+template <int K>
+__device__ __forceinline__ void geodesic_setup(const FrameArgs& a, KSpace<kMaxK>& ks, long long n, int steps,
+                                               bool lead) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    const double av = (lane < K) ? ks.red[lane] : 0.0;
+    const double yv = (lane < K) ? ks.y[lane] : 0.0;
+    const double aa = row16_sum(av * av);
+    const double yy = row16_sum(yv * yv);
+    const double ee = ks.red[K];
+    const double zeta = sqrt(fmax(ee - aa, 0.0));
+    const double nu = sqrt(yy);
+    const double sigma = zeta * nu;
+    const double t = fmax(exp(-a.tau * (double)n) * a.t_init, a.t_min);
+    const double theta = sigma * t;
+    const int upd = (zeta > 0.0 && nu > 0.0) ? 1 : 0;
+    if (lane < K) {
+      ks.af[lane] = (float)av;
+      ks.vf[lane] = upd ? (float)(yv / nu) : 0.f;
+      ks.yf[lane] = (float)yv;
+    }
+    if (lane == 0) {
+      const double sh = sin(0.5 * theta);
+      ks.scal[0] = upd ? (float)(-2.0 * sh * sh) : 0.f;          // cos(theta) - 1
+      ks.scal[1] = upd ? (float)(sin(theta) / zeta) : 0.f;       // sin(theta) / zeta
+      ks.scal[2] = (float)nu;
+      ks.flag[2] = upd;
+      if (lead) {
+        a.stats->f[steps] = ks.red[K + 1];
+        a.stats->t = t;
+        a.stats->sigma = sigma;
+        a.stats->theta = theta;
+        a.stats->zeta = zeta;
+        a.stats->nu = nu;
+        a.stats->updated = upd;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Pixel labels (Sec. 3.3, Step 3): foreground when any colour entry was
+// flagged in s_flag (entry q = c * npx + pixel).
+__device__ __forceinline__ void write_labels(const FrameArgs& a, const uint8_t* s_flag, int p0, int npx) {
+  __syncthreads();
+  for (int pl = threadIdx.x; pl < npx; pl += kBlock) {
+    uint8_t f = 0;
+    for (int c = 0; c < a.C; ++c) f |= s_flag[c * npx + pl];
+    a.lab[p0 + pl] = f;
+  }
+}
+
+// Statistics, frame counter, y and the exchange bases for the next launch.
+__device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSpace<kMaxK>& ks, const TileCtx& t,
+                                         int steps, int restarts, bool bad, int nbar) {
+  const int tid = threadIdx.x;
+  trace_point(a, tile, 63);
+  if (t.lead && tid == 0) {
+    a.stats->frame = t.n;
+    a.stats->cg_steps = steps;
+    a.stats->restarts = restarts;
+    a.stats->bad_frame = bad ? 1 : 0;
+    if (bad) {
+      __hip_atomic_fetch_or(&a.sync[2], kErrBadFrame, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      *a.nframe = t.n + 1;
+    }
+    if (a.sync_mode != 0)
+      __hip_atomic_store(&a.sync[3], t.ebase + (unsigned)nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_store(&a.sync[1], t.base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (t.lead && !bad && tid < a.k) a.y[tid] = ks.y[tid];
+  __syncthreads();   // shared scratch may be reused by the next tile
+}
+
+// ---------------------------------------------------------------------------
+// float32 storage: row q = tid + s * kBlock of the tile, K floats per row
+// ---------------------------------------------------------------------------
+template <int K, int NR>
+__device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
+  KSpace<kMaxK>& ks = sm.ks;
+  uint8_t* s_flag = sm.flag;
+  const int tid = threadIdx.x;
+  const TileCtx ctx = tile_begin<K>(a, tile, ks);
+  int nbar = 0;
+
   // ---- load the register tile: U rows, residual r = x - U y, weights ----
-  const TS* __restrict__ Ug = (const TS*)a.U;
-  const TS* __restrict__ xg = (const TS*)(a.xtab ? a.xtab[n % a.ring] : a.x);
+  const float* __restrict__ Ug = (const float*)a.U;
+  const float* __restrict__ xg = (const float*)(a.xtab ? a.xtab[ctx.n % a.ring] : a.x);
   const uint8_t* __restrict__ wsrc = a.weights_from_filtered ? a.mask : a.lab;
   float u[NR][K];
-  float r[NR], wt[NR], cw[NR], ud[NR];
+  float r[NR], wt[NR], cw[NR];
   int eix[NR];
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
@@ -457,16 +621,16 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     r[s] = 0.f;
 #pragma unroll
     for (int j = 0; j < K; ++j) u[s][j] = 0.f;
-    if (q < nq) {
-      const int c = q / npx;
-      const int pl = q - c * npx;
-      const int e = c * a.P + p0 + pl;
+    if (q < ctx.nq) {
+      const int c = q / ctx.npx;
+      const int pl = q - c * ctx.npx;
+      const int e = c * a.P + ctx.p0 + pl;
       eix[s] = e;
-      wt[s] = wsrc[p0 + pl] ? a.omega : 1.0f;
-      float acc = ld_elem(xg, e);
+      wt[s] = wsrc[ctx.p0 + pl] ? a.omega : 1.0f;
+      float acc = xg[e];
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        if (j < a.k) u[s][j] = ld_elem(Ug, (long long)j * a.ldU + e);   // columns >= k stay 0
+        if (j < a.k) u[s][j] = Ug[(long long)j * a.ldU + e];   // columns >= k stay 0
         acc = fmaf(-u[s][j], ks.yf[j], acc);
       }
       r[s] = acc;
@@ -491,80 +655,35 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, u[s][j], acc[j]);
     }
-    if (!gang_reduce<K + 1>(acc, a, tile, nbar, base, ebase, sm, ks.red)) return false;
-    // k-space: PR+ direction (wave 0, lane j owns component j)
-    if (tid < 64) {
-      const double g = (lane < K) ? -ks.red[lane] : 0.0;
-      const double f = ks.red[K];
-      const double gg = row16_sum(g * g);
-      int stop = 0;
-      if (it == 0 && !(isfinite(f) && isfinite(gg))) {
-        stop = 1;
-        if (lane == 0) ks.flag[1] = 1;
-      }
-      if (gg == 0.0) stop = 1;
-      if (lead && lane == 0) a.stats->f[it] = f;
-      double beta = 0.0, dj = -g;
-      if (!stop && it > 0) {
-        const double gp = (lane < K) ? ks.gp[lane] : 0.0;
-        const double num = row16_sum(g * (g - gp));
-        const double den = row16_sum(gp * gp);
-        beta = fmax(0.0, num / den);
-        const double dpv = (lane < K) ? ks.dp[lane] : 0.0;
-        dj = -g + beta * dpv;
-        const double gdv = row16_sum(g * dj);
-        if (gdv >= 0.0) {
-          dj = -g;
-          if (lane == 0) ++restarts;
-        }
-      }
-      const double gd = row16_sum(g * dj);
-      if (lane < K) {
-        ks.d[lane] = dj;
-        ks.df[lane] = (float)dj;
-        ks.gp[lane] = g;
-      }
-      if (lane == 0) {
-        ks.gd = gd;
-        ks.flag[0] = stop;
-        if (lead) a.stats->beta[it] = beta;
-      }
-    }
-    __syncthreads();
+    if (!gang_reduce<K + 1>(acc, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    cg_direction<K>(a, ks, it, ctx.lead, restarts);
     if (ks.flag[0]) break;
-    // phase B: curvature of the majoriser along d
+    // phase B: curvature of the majoriser along d; cw then holds u.d
     float accb[1] = {0.f};
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       float t = 0.f;
 #pragma unroll
       for (int j = 0; j < K; ++j) t = fmaf(u[s][j], ks.df[j], t);
-      ud[s] = t;
       accb[0] = fmaf(cw[s] * t, t, accb[0]);
+      cw[s] = t;
     }
-    if (!gang_reduce<1>(accb, a, tile, nbar, base, ebase, sm, ks.red)) return false;
+    if (!gang_reduce<1>(accb, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
     const double dHd = ks.red[0];
     if (!(dHd > 0.0)) break;   // same decision in every workgroup
-    const double alpha = -ks.gd / dHd;
-    __syncthreads();
-    if (tid < K) {
-      ks.y[tid] += alpha * ks.d[tid];
-      ks.dp[tid] = ks.d[tid];
-    }
-    if (lead && tid == 0) a.stats->alpha[it] = alpha;
-    const float af = (float)alpha;
+    const float af = cg_advance<K>(a, ks, dHd, it, ctx.lead);
 #pragma unroll
-    for (int s = 0; s < NR; ++s) r[s] = fmaf(-af, ud[s], r[s]);
+    for (int s = 0; s < NR; ++s) r[s] = fmaf(-af, cw[s], r[s]);
     ++steps;
     __syncthreads();
   }
   const bool bad = ks.flag[1] != 0;
 
-  // ---- Step 2: eta pass (a = U^T eta, ||eta||^2, final cost) ----
-  float acce[K + 2];
-#pragma unroll
-  for (int j = 0; j < K + 2; ++j) acce[j] = 0.f;
   if (!bad) {
+    // ---- Step 2: eta pass (a = U^T eta, ||eta||^2, final cost) ----
+    float acce[K + 2];
+#pragma unroll
+    for (int j = 0; j < K + 2; ++j) acce[j] = 0.f;
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       float phi, c;
@@ -576,45 +695,12 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, u[s][j], acce[j]);
     }
-    if (!gang_reduce<K + 2>(acce, a, tile, nbar, base, ebase, sm, ks.red)) return false;
-    if (tid < 64) {
-      const double av = (lane < K) ? ks.red[lane] : 0.0;
-      const double yv = (lane < K) ? ks.y[lane] : 0.0;
-      const double aa = row16_sum(av * av);
-      const double yy = row16_sum(yv * yv);
-      const double ee = ks.red[K];
-      const double zeta = sqrt(fmax(ee - aa, 0.0));
-      const double nu = sqrt(yy);
-      const double sigma = zeta * nu;
-      const double t = fmax(exp(-a.tau * (double)n) * a.t_init, a.t_min);
-      const double theta = sigma * t;
-      const int upd = (zeta > 0.0 && nu > 0.0) ? 1 : 0;
-      if (lane < K) {
-        ks.af[lane] = (float)av;
-        ks.vf[lane] = upd ? (float)(yv / nu) : 0.f;
-        ks.yf[lane] = (float)yv;
-      }
-      if (lane == 0) {
-        const double sh = sin(0.5 * theta);
-        ks.scal[0] = upd ? (float)(-2.0 * sh * sh) : 0.f;          // cos(theta) - 1
-        ks.scal[1] = upd ? (float)(sin(theta) / zeta) : 0.f;       // sin(theta) / zeta
-        ks.scal[2] = (float)nu;
-        ks.flag[2] = upd;
-        if (lead) {
-          a.stats->f[steps] = ks.red[K + 1];
-          a.stats->t = t;
-          a.stats->sigma = sigma;
-          a.stats->theta = theta;
-          a.stats->zeta = zeta;
-          a.stats->nu = nu;
-          a.stats->updated = upd;
-        }
-      }
-    }
-    __syncthreads();
+    if (!gang_reduce<K + 2>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    geodesic_setup<K>(a, ks, ctx.n, steps, ctx.lead);
+    trace_point(a, tile, 60);
 
     // ---- Step 2 update + Step 3 labels, one pass over the register tile ----
-    TS* __restrict__ Uw = (TS*)a.U;
+    float* __restrict__ Uw = (float*)a.U;
     const float cm1 = ks.scal[0], sz = ks.scal[1], nu_f = ks.scal[2];
     const bool upd = ks.flag[2] != 0;
 #pragma unroll
@@ -632,46 +718,257 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
           const float coef = fmaf(cm1, uv, -sz * (cw[s] - ua));
 #pragma unroll
           for (int j = 0; j < K; ++j)
-            if (j < a.k) st_elem((TS*)Uw, (long long)j * a.ldU + eix[s], fmaf(coef, ks.vf[j], u[s][j]));
+            if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = fmaf(coef, ks.vf[j], u[s][j]);
           if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
         }
         s_flag[q] = (fabsf(rl) >= a.delta) ? 1 : 0;
       }
     }
-    __syncthreads();
-    for (int pl = tid; pl < npx; pl += kBlock) {
-      uint8_t f = 0;
-      for (int c = 0; c < a.C; ++c) f |= s_flag[c * npx + pl];
-      a.lab[p0 + pl] = f;
-    }
+    trace_point(a, tile, 61);
+    write_labels(a, s_flag, ctx.p0, ctx.npx);
+    trace_point(a, tile, 62);
   }
-  // the labels are read by the next frame's launch (median and weights)
-  trace_point(a, tile, 63);
-  if (lead && tid == 0) {
-    a.stats->frame = n;
-    a.stats->cg_steps = steps;
-    a.stats->restarts = restarts;
-    a.stats->bad_frame = bad ? 1 : 0;
-    if (bad) {
-      __hip_atomic_fetch_or(&a.sync[2], kErrBadFrame, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      *a.nframe = n + 1;
-    }
-    if (a.sync_mode != 0)
-      __hip_atomic_store(&a.sync[3], ebase + (unsigned)nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-      __hip_atomic_store(&a.sync[1], base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-  }
-  if (lead && !bad && tid < a.k) a.y[tid] = ks.y[tid];
-  __syncthreads();   // shared scratch may be reused by the next tile
+  tile_end(a, tile, ks, ctx, steps, restarts, bad, nbar);
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// bfloat16 storage: the register tile keeps U in bfloat16, two rows per
+// 32-bit register (row 2i in the low half, row 2i + 1 in the high half), so a
+// tile holds twice the rows of the float32 layout in the same registers.
+// Values are widened to float32 (exact) where they are used; the update is
+// computed in float32 and rounded to nearest-even once, as it is stored.
+// Row pair s of thread tid covers rows q0 = 2 (tid + s kBlock) and q0 + 1.
+// When a.pair_aligned is set (even P, even tpw, 4-byte aligned frame) a pair
+// is one aligned 32-bit word in the U planes and in the frame; otherwise the
+// two halves are accessed separately and may lie in two colour planes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+__device__ __forceinline__ float bf_half(uint32_t w, int h) { return h ? bf_hi(w) : bf_lo(w); }
+
+// Two float32 values rounded to nearest-even bfloat16 and packed (lo, hi):
+// one v_cvt_pk_bf16_f32 on gfx950.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16_rne(float lo, float hi) {
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
+// Marks the packed tile as redefined at the start of every row pass, so the
+// compiler cannot hoist widened float32 copies of U out of the CG loop
+// (which would double the registers the tile needs).  No instructions.
+template <int NP, int K>
+__device__ __forceinline__ void pin_tile(uint32_t (&u)[NP][K]) {
+#pragma unroll
+  for (int s = 0; s < NP; ++s)
+#pragma unroll
+    for (int j = 0; j < K; ++j) asm volatile("" : "+v"(u[s][j]));
+}
+
+template <int K, int NP>
+__device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int tile, FrameSmem& sm) {
+  static_assert(2 * NP <= kMaxNR && NP <= 16, "row bit masks hold 32 rows");
+  KSpace<kMaxK>& ks = sm.ks;
+  uint8_t* s_flag = sm.flag;
+  const int tid = threadIdx.x;
+  const TileCtx ctx = tile_begin<K>(a, tile, ks);
+  int nbar = 0;
+  const bool al = a.pair_aligned != 0;
+
+  // ---- load the register tile ----
+  const uint16_t* __restrict__ Ug = (const uint16_t*)a.U;
+  const uint16_t* __restrict__ xg = (const uint16_t*)(a.xtab ? a.xtab[ctx.n % a.ring] : a.x);
+  const uint8_t* __restrict__ wsrc = a.weights_from_filtered ? a.mask : a.lab;
+  uint32_t u[NP][K];
+  float r[2 * NP], cw[2 * NP];
+  uint32_t vbits = 0;         // bit i: row i exists
+  uint32_t fbits = 0;         // bit i: row i's pixel was foreground (weight omega)
+  uint32_t sbits = 0;         // bit s: pair s continues in the next colour plane
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+    const int q0 = 2 * (tid + s * kBlock);
+    r[2 * s] = r[2 * s + 1] = 0.f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) u[s][j] = 0u;
+    if (q0 < ctx.nq) {
+      const int c = q0 / ctx.npx;
+      const int pl = q0 - c * ctx.npx;
+      const int e = c * a.P + ctx.p0 + pl;
+      const bool has1 = q0 + 1 < ctx.nq;
+      const bool split = (pl + 1 == ctx.npx);
+      const int e1 = split ? e + 1 + (a.P - ctx.npx) : e + 1;
+      vbits |= (has1 ? 3u : 1u) << (2 * s);
+      if (split) sbits |= 1u << s;
+      if (wsrc[ctx.p0 + pl]) fbits |= 1u << (2 * s);
+      if (has1 && wsrc[ctx.p0 + (split ? 0 : pl + 1)]) fbits |= 2u << (2 * s);
+      uint32_t xw;
+      if (al) xw = *(const uint32_t*)(xg + e);
+      else xw = (uint32_t)xg[e] | (has1 ? ((uint32_t)xg[e1] << 16) : 0u);
+      float acc0 = bf_lo(xw), acc1 = bf_hi(xw);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        if (j < a.k) {
+          const long long o = (long long)j * a.ldU;
+          u[s][j] = al ? *(const uint32_t*)(Ug + o + e)
+                       : ((uint32_t)Ug[o + e] | (has1 ? ((uint32_t)Ug[o + e1] << 16) : 0u));
+        }
+        acc0 = fmaf(-bf_lo(u[s][j]), ks.yf[j], acc0);
+        acc1 = fmaf(-bf_hi(u[s][j]), ks.yf[j], acc1);
+      }
+      r[2 * s] = acc0;
+      r[2 * s + 1] = has1 ? acc1 : 0.f;
+    }
+  }
+  const float om = a.omega;
+  auto weight = [&](int i) -> float {
+    return ((vbits >> i) & 1u) ? (((fbits >> i) & 1u) ? om : 1.0f) : 0.f;
+  };
+
+  // ---- Step 1: CG on y ----
+  int steps = 0, restarts = 0;
+  for (int it = 0; it < a.J; ++it) {
+    float acc[K + 1];
+#pragma unroll
+    for (int j = 0; j <= K; ++j) acc[j] = 0.f;
+    pin_tile(u);
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = 2 * s + h;
+        const float wt = weight(i);
+        float phi, c;
+        cost_eval(r[i], a.cp, phi, c);
+        const float wc = wt * c;
+        cw[i] = wc;
+        const float wd = wc * r[i];
+        acc[K] = fmaf(wt, phi, acc[K]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, bf_half(u[s][j], h), acc[j]);
+      }
+    if (!gang_reduce<K + 1>(acc, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    cg_direction<K>(a, ks, it, ctx.lead, restarts);
+    if (ks.flag[0]) break;
+    float accb[1] = {0.f};
+    pin_tile(u);
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = 2 * s + h;
+        float t = 0.f;
+#pragma unroll
+        for (int j = 0; j < K; ++j) t = fmaf(bf_half(u[s][j], h), ks.df[j], t);
+        accb[0] = fmaf(cw[i] * t, t, accb[0]);
+        cw[i] = t;
+      }
+    if (!gang_reduce<1>(accb, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    const double dHd = ks.red[0];
+    if (!(dHd > 0.0)) break;
+    const float af = cg_advance<K>(a, ks, dHd, it, ctx.lead);
+#pragma unroll
+    for (int i = 0; i < 2 * NP; ++i) r[i] = fmaf(-af, cw[i], r[i]);
+    ++steps;
+    __syncthreads();
+  }
+  const bool bad = ks.flag[1] != 0;
+
+  if (!bad) {
+    float acce[K + 2];
+#pragma unroll
+    for (int j = 0; j < K + 2; ++j) acce[j] = 0.f;
+    pin_tile(u);
+#pragma unroll
+    for (int s = 0; s < NP; ++s)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = 2 * s + h;
+        const float wt = weight(i);
+        float phi, c;
+        cost_eval(r[i], a.cp, phi, c);
+        const float eta = -wt * c * r[i];
+        cw[i] = eta;
+        acce[K] = fmaf(eta, eta, acce[K]);
+        acce[K + 1] = fmaf(wt, phi, acce[K + 1]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, bf_half(u[s][j], h), acce[j]);
+      }
+    if (!gang_reduce<K + 2>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    geodesic_setup<K>(a, ks, ctx.n, steps, ctx.lead);
+    trace_point(a, tile, 60);
+
+    uint16_t* __restrict__ Uw = (uint16_t*)a.U;
+    const float cm1 = ks.scal[0], sz = ks.scal[1], nu_f = ks.scal[2];
+    const bool upd = ks.flag[2] != 0;
+    pin_tile(u);
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int q0 = 2 * (tid + s * kBlock);
+      if (q0 >= ctx.nq) continue;
+      const bool has1 = (vbits >> (2 * s + 1)) & 1u;
+      const int c = q0 / ctx.npx;
+      const int e = c * a.P + ctx.p0 + (q0 - c * ctx.npx);
+      const int e1 = ((sbits >> s) & 1u) ? e + 1 + (a.P - ctx.npx) : e + 1;
+      float rl0 = r[2 * s], rl1 = r[2 * s + 1];
+      if (upd) {
+        float uv0 = 0.f, ua0 = 0.f, uv1 = 0.f, ua1 = 0.f;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float a0 = bf_lo(u[s][j]), a1 = bf_hi(u[s][j]);
+          uv0 = fmaf(a0, ks.vf[j], uv0);
+          ua0 = fmaf(a0, ks.af[j], ua0);
+          uv1 = fmaf(a1, ks.vf[j], uv1);
+          ua1 = fmaf(a1, ks.af[j], ua1);
+        }
+        const float coef0 = fmaf(cm1, uv0, -sz * (cw[2 * s] - ua0));
+        const float coef1 = fmaf(cm1, uv1, -sz * (cw[2 * s + 1] - ua1));
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+          if (j < a.k) {
+            const uint32_t nw = pack_bf16_rne(fmaf(coef0, ks.vf[j], bf_lo(u[s][j])),
+                                              fmaf(coef1, ks.vf[j], bf_hi(u[s][j])));
+            const long long o = (long long)j * a.ldU;
+            if (al) {
+              *(uint32_t*)(Uw + o + e) = nw;
+            } else {
+              Uw[o + e] = (uint16_t)(nw & 0xFFFFu);
+              if (has1) Uw[o + e1] = (uint16_t)(nw >> 16);
+            }
+          }
+        if (a.labels_after_update) {
+          rl0 = fmaf(-coef0, nu_f, rl0);
+          rl1 = fmaf(-coef1, nu_f, rl1);
+        }
+      }
+      s_flag[q0] = (fabsf(rl0) >= a.delta) ? 1 : 0;
+      if (has1) s_flag[q0 + 1] = (fabsf(rl1) >= a.delta) ? 1 : 0;
+    }
+    trace_point(a, tile, 61);
+    write_labels(a, s_flag, ctx.p0, ctx.npx);
+    trace_point(a, tile, 62);
+  }
+  tile_end(a, tile, ks, ctx, steps, restarts, bad, nbar);
+  return true;
+}
+
+// One workgroup's share of one frame in the storage type's register layout.
+// Returns false when the gang aborted.
+template <int K, int NR, typename TS>
+__device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
+  if constexpr (sizeof(TS) == 2) {
+    static_assert(NR % 2 == 0, "bfloat16 tiles hold row pairs");
+    return frame_tile_packed<K, NR / 2>(a, tile, sm);
+  } else {
+    return frame_tile<K, NR>(a, tile, sm);
+  }
 }
 
 template <int K, int NR, typename TS>
 __global__ __launch_bounds__(kBlock, 2) void frame_kernel(FrameArgs a) {
   __shared__ FrameSmem sm;
-  frame_tile<K, NR, TS>(a, blockIdx.x, sm);
+  run_tile<K, NR, TS>(a, blockIdx.x, sm);
 }
 
 }  // namespace prost

@@ -27,7 +27,7 @@ struct pros_handle {
   // launch configuration
   const void* kfn = nullptr;
   int G = 0, tpw = 0, NR = 0;
-  int sync_mode = 1;       // 0: counter barrier, 1: tagged gather/broadcast, 2: two-level tagged
+  int sync_mode = 2;       // 0: counter barrier, 1: tagged gather/broadcast, 2: two-level tagged, 3: tagged all-read
   long long* trace = nullptr;   // optional per-tile timestamps (diagnostics)
   bool mask_stale = true;       // mask not yet computed from the latest labels
   long long timeout_ticks = 0;
@@ -54,6 +54,13 @@ pros_status reset_exchange(pros_handle* h);
 // Compute the mask (and foreground count) of the latest labels if a frame
 // kernel has not done so yet.  Queued on the handle's stream.
 pros_status refresh_mask(pros_handle* h);
+// Pixels per workgroup tile for NR register rows per thread (a fraction
+// `scale` of the full tile); even for bfloat16 storage so that row pairs
+// stay inside one colour plane.
+int tile_pixels(int storage, int NR, int channels, double scale);
+// bfloat16 row pairs can be accessed as aligned 32-bit words in U (frame
+// alignment is checked separately).
+bool pair_layout(const pros_handle* h);
 
 uint16_t bf16_rne(float f);
 float bf16_to_f32(uint16_t b);

@@ -154,7 +154,7 @@ class Tracker:
                     pixels_per_wg=li.pixels_per_wg, barriers_per_frame=li.barriers_per_frame,
                     sync_mode=li.sync_mode)
 
-    def set_launch(self, rows_per_thread=0, sync_mode=1):
+    def set_launch(self, rows_per_thread=0, sync_mode=2):
         L.check(L.lib().pros_set_launch(self._h, int(rows_per_thread), int(sync_mode)))
 
 
@@ -274,7 +274,7 @@ class BatchTracker:
                     tile_scale=c.tile_scale, strategy=c.strategy, sync_mode=c.sync_mode,
                     workgroups=c.workgroups, rounds=c.rounds)
 
-    def configure(self, register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0, sync_mode=1):
+    def configure(self, register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0, sync_mode=2):
         c = L.pros_batch_config(register_budget, workgroups_per_cu, tile_scale, strategy, sync_mode, 0, 0)
         L.check(L.lib().pros_batch_configure(self._b, C.byref(c)))
 

@@ -108,11 +108,15 @@ def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U):
     assert rep["f_rel"] <= TOL_F
 
 
-def update_rounding_bound(start, x64, prm, y_final):
-    """Per-entry bound of the float32 rounding error of the geodesic update
+def update_rounding_bound(start, x64, prm, y_final, y_dev=None):
+    """Per-entry bound of the float32 error of the geodesic update
     u' = u + [(cos(theta)-1) (u.v) - (sin(theta)/zeta) (eta - u.a)] v, from the
-    oracle's float64 intermediates: 2^-20 times the magnitudes of the terms
-    (a float32 error of a few units in the last place of each of them)."""
+    oracle's float64 intermediates:
+    * 2^-20 times the magnitudes of the terms (a float32 error of a few units
+      in the last place of each of them);
+    * the residual's own float32 error and the device's y (y_dev, which the
+      parity bar allows to differ from the oracle's), carried into eta by
+      the cost's second derivative (largest at r = 0) and into v = y/||y||."""
     import math
     U = start.U
     w = O.pixel_weights(start.mask if prm.weights_from_filtered else start.labels, prm.omega, prm.channels)
@@ -123,4 +127,14 @@ def update_rounding_bound(start, x64, prm, y_final):
     theta = sigma * O.step_size(start.n, prm.t_init, prm.t_min, prm.i_init)
     a = U.T @ eta
     term = (abs(math.cos(theta) - 1.0) * np.abs(U @ v) + abs(math.sin(theta) / zeta) * (np.abs(eta) + np.abs(U @ a)))
-    return 2.0 ** -20 * (np.abs(U) + np.abs(term)[:, None] * np.abs(v)[None, :])
+    bound = 2.0 ** -20 * (np.abs(U) + np.abs(term)[:, None] * np.abs(v)[None, :])
+    dy = 0.0 if y_dev is None else float(np.linalg.norm(np.asarray(y_dev) - y_final))
+    dr = 2.0 ** -20 * (np.abs(x64) + np.abs(U) @ np.abs(y_final)) + np.linalg.norm(U, axis=1) * dy
+    if prm.cost == "log":
+        phi2 = 2.0 / prm.mu
+    else:
+        phi2 = prm.p * prm.mu ** (prm.p / 2.0 - 1.0)
+    deta = w * phi2 * dr
+    bound += abs(math.sin(theta) / zeta) * deta[:, None] * np.abs(v)[None, :]
+    bound += np.abs(term)[:, None] * (dy / nu)
+    return bound

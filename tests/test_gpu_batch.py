@@ -160,10 +160,61 @@ def test_batch_bf16_matches_oracle():
             y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
             e = rne(exp.U)
             ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(e), 1e-38))) - 7)
-            ulp = ulp + update_rounding_bound(starts[s], x, prm, exp.y)
+            ulp = ulp + update_rounding_bound(starts[s], x, prm, exp.y, y1)
             over = int(np.sum(np.abs(U1 - e) > ulp * 1.0000001 + 1e-45))
             say(f"  bf16 stream {s}: y {y_rel:.1e}, U entries beyond 1 ulp: {over}")
             assert y_rel <= 1e-4 and over == 0
+
+
+def test_batch_bf16_two_vga_streams_share_a_round():
+    """Two 640x480x3 k=15 streams in bfloat16 (the benchmark's streams): the
+    row-pair tiles halve each gang, so both frames run side by side in one
+    round; each stream matches its own oracle step."""
+    from paper_1302_2073_amd.tracker import BatchTracker, bf16_bits
+    import torch
+
+    def rne(a):
+        f = np.asarray(a, np.float32)
+        u = f.view(np.uint32).astype(np.uint64)
+        return ((((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)).view(np.float32).astype(np.float64)
+
+    wls = [V.vga_rgb(stream=s) for s in range(2)]
+    svs = [V.SyntheticVideo(w.video) for w in wls]
+    specs = [dict(width=640, height=480, channels=3, k=15, mu=w.mu) for w in wls]
+    with BatchTracker(specs, storage="bf16") as bt:
+        cfg = bt.config()
+        say("  config", cfg)
+        assert cfg["rounds"] == 1
+        frames = [[torch.from_numpy(bf16_bits(sv.frame(0)).view(np.int16)).cuda().view(torch.bfloat16)]
+                  for sv in svs]
+        for s in range(2):
+            bt.set_state(s, V.initial_subspace(640 * 480 * 3, 15, 3, s))
+        bt.set_frames(frames)
+        starts = []
+        for s, w in enumerate(wls):
+            U0, y0, l0, n0 = bt.get_state(s)
+            starts.append(O.State(U0, y0, l0, O.median3x3(l0, 480, 640), n0))
+        bt.step()
+        assert bt.sync() == 0
+        for s, w in enumerate(wls):
+            prm = O.Params(640, 480, 3, k=15, mu=w.mu)
+            x = rne(svs[s].frame(0))
+            exp, _ = O.track_frame(starts[s], x, prm)
+            U1, y1, l1, n1 = bt.get_state(s)
+            y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
+            e = rne(exp.U)
+            ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(e), 1e-38))) - 7)
+            ulp = ulp + update_rounding_bound(starts[s], x, prm, exp.y, y1)
+            over = int(np.sum(np.abs(U1 - e) > ulp * 1.0000001 + 1e-45))
+            if over:
+                r = (np.abs(U1 - e) / ulp).ravel()
+                worst = np.argsort(r)[-5:]
+                say("  worst entries (value, oracle, |diff|/bound):",
+                    [(float(U1.ravel()[i]), float(e.ravel()[i]), float(r[i])) for i in worst])
+            band = O.band_pixels(exp.U, x, exp.y, prm.thr, 3, GUARD)
+            mism = int(np.sum((l1 != exp.labels) & ~band))
+            say(f"  vga bf16 stream {s}: y {y_rel:.1e}, U entries beyond 1 ulp: {over}, labels outside band {mism}")
+            assert n1 == exp.n and y_rel <= 1e-4 and over == 0 and mism == 0
 
 
 def test_mixed_streams_workload_parity_sample():
