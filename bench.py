@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--forms", default="plain_f32,plain_bf16,batched_bf16",
                     help="comma list of forms to time (the headline is batched_bf16)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched form: keep the default launch configuration (profiling runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -218,7 +220,7 @@ def main():
         plain_bf16 = run_plain("bf16", args.steps * 4, args.warmup, args.pool)
         record("plain_bf16", plain_bf16, 2, 2)
     if "batched_bf16" in want:
-        batched = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool)
+        batched = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune)
         achieved = record("batched_bf16", batched, 2, 2, args.streams)
         if plain:
             forms["batched_bf16"]["vs_plain_f32"] = round(batched["fps"] / plain["fps"], 3)

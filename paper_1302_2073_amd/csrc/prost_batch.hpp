@@ -43,6 +43,20 @@ __host__ __device__ constexpr int batch_class(int k) {
   return k <= 2 ? 2 : k <= 4 ? 4 : k <= 5 ? 5 : k <= 8 ? 8 : k <= 10 ? 10 : k <= 12 ? 12 : k <= 15 ? 15 : 16;
 }
 
+// A stream descriptor copied into scalar registers (its words are uniform
+// across the workgroup), as kernel arguments are: held in vector registers
+// the fields would take room from the register tile.
+__device__ __forceinline__ FrameArgs load_uniform(const FrameArgs* __restrict__ p) {
+  static_assert(sizeof(FrameArgs) % 4 == 0, "descriptor of 32-bit words");
+  FrameArgs a;
+  const int* src = (const int*)p;
+  int w[sizeof(FrameArgs) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(FrameArgs) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  __builtin_memcpy(&a, w, sizeof(FrameArgs));
+  return a;
+}
+
 template <typename TS, int K, int NR>
 __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __restrict__ descs,
                                                        const BatchItem* __restrict__ items, int rounds) {
@@ -50,7 +64,7 @@ __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __res
   for (int r = 0; r < rounds; ++r) {
     const BatchItem it = items[(size_t)r * gridDim.x + blockIdx.x];
     if (it.stream < 0) continue;
-    const FrameArgs a = descs[it.stream];
+    const FrameArgs a = load_uniform(descs + it.stream);
     if (!run_tile<K, NR, TS>(a, it.tile, sm)) return;
   }
 }

@@ -22,6 +22,16 @@ constexpr int kSlot = 32;              // doubles per workgroup partial slot
 constexpr unsigned kErrTimeout = 1u;
 constexpr unsigned kErrBadFrame = 2u;
 
+// Thread index through an opaque move.  In a persistent loop over tiles the
+// compiler would otherwise hoist all index arithmetic derived from it out of
+// the loop and keep the results live across whole frames, taking registers
+// from the register-resident tile.
+__device__ __forceinline__ int thread_index() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // storage
 // ---------------------------------------------------------------------------
@@ -99,7 +109,7 @@ template <int L, typename T>
 __device__ __forceinline__ T wave_reduce_scatter(T (&a)[L], int& comp) {
   constexpr int P = pow2_at_least(L);
   constexpr int S = ilog2(P);
-  const int lane = threadIdx.x & 63;
+  const int lane = thread_index() & 63;
   int base = 0;
 #pragma unroll
   for (int st = 0; st < S; ++st) {
@@ -153,7 +163,7 @@ __device__ __forceinline__ void st_tagged(double* p, double v) {
 __device__ __forceinline__ bool gang_barrier(unsigned* sync, unsigned target, long long timeout,
                                              int* s_ctl) {
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (thread_index() == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long t0 = now_ticks();

@@ -98,7 +98,7 @@ template <int L>
 __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const FrameArgs& a, const int tile,
                                                    int& nbar, unsigned ebase, double* s_big,
                                                    double* s_out, int* s_ctl, bool fenced) {
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const int lane = tid & 63;
   const int wv = tid >> 6;
   ++nbar;
@@ -183,7 +183,7 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
 template <int L>
 __device__ __forceinline__ bool poll_sum_slots(const double* slots, int nslots, unsigned ep, const FrameArgs& a,
                                                double* s_big, double* out) {
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   constexpr int kRows = kBlock / 32;
   const int comp = tid & 31, row0 = tid >> 5;
   const long long t0 = now_ticks();
@@ -226,7 +226,7 @@ template <int L>
 __device__ __forceinline__ bool gang_reduce_2level(const double* wg_sum, const FrameArgs& a, const int tile,
                                                    int& nbar, unsigned ebase, double* s_big,
                                                    double* s_out, int* s_ctl, bool fenced) {
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   ++nbar;
   const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
   const int x = tile & 7;
@@ -278,7 +278,7 @@ template <int L>
 __device__ __forceinline__ bool gang_reduce_allread(const double* wg_sum, const FrameArgs& a, const int tile,
                                                     int& nbar, unsigned ebase, double* s_big,
                                                     double* s_out, bool fenced) {
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   ++nbar;
   const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
   double* slots = a.part + (size_t)(nbar & 1) * a.G * kSlot;      // double-buffered
@@ -293,18 +293,18 @@ __device__ __forceinline__ bool gang_reduce_allread(const double* wg_sum, const 
 // result in wg_sum[0..L) (shared).
 template <int L>
 __device__ __forceinline__ void wg_reduce(float (&acc)[L], double (*s_red)[kSlot], double* wg_sum) {
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int lane = thread_index() & 63;
+  const int wv = thread_index() >> 6;
   int comp;
   const float v = wave_reduce_scatter<L>(acc, comp);
   constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
   if ((lane & kLowMask) == 0 && comp < L) s_red[wv][comp] = (double)v;
   __syncthreads();
-  if (threadIdx.x < L) {
+  if (thread_index() < L) {
     double v = 0.0;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) v += s_red[q][threadIdx.x];
-    wg_sum[threadIdx.x] = v;
+    for (int q = 0; q < kWaves; ++q) v += s_red[q][thread_index()];
+    wg_sum[thread_index()] = v;
   }
   __syncthreads();
 }
@@ -313,8 +313,8 @@ template <int L>
 __device__ __forceinline__ bool gang_reduce_counter(float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
                                                     unsigned base, double (*s_red)[kSlot], double* s_big,
                                                     double* s_out, int* s_ctl) {
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int lane = thread_index() & 63;
+  const int wv = thread_index() >> 6;
   constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
   // 1. per wave
   {
@@ -324,11 +324,11 @@ __device__ __forceinline__ bool gang_reduce_counter(float (&acc)[L], const Frame
   }
   __syncthreads();
   double* slot = a.part + ((size_t)(nbar & 1) * a.G + tile) * kSlot;
-  if (threadIdx.x < L) {
+  if (thread_index() < L) {
     double v = 0.0;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) v += s_red[q][threadIdx.x];
-    __hip_atomic_store(&slot[threadIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int q = 0; q < kWaves; ++q) v += s_red[q][thread_index()];
+    __hip_atomic_store(&slot[thread_index()], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // 2. gang barrier
   ++nbar;
@@ -340,17 +340,17 @@ __device__ __forceinline__ bool gang_reduce_counter(float (&acc)[L], const Frame
   // so the first workgroup of each XCD pulls the partials into its L2.
   const double* buf = a.part + (size_t)((nbar - 1) & 1) * a.G * kSlot;
   constexpr int kRows = kBlock / 32;
-  const int comp = threadIdx.x & 31, row0 = threadIdx.x >> 5;
+  const int comp = thread_index() & 31, row0 = thread_index() >> 5;
   double v = 0.0;
   if (comp < L)
     for (int w = row0; w < a.G; w += kRows) v += buf[(size_t)w * kSlot + comp];
-  s_big[threadIdx.x] = v;
+  s_big[thread_index()] = v;
   __syncthreads();
-  if (threadIdx.x < L) {
+  if (thread_index() < L) {
     double tot = 0.0;
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) tot += s_big[r * 32 + threadIdx.x];
-    s_out[threadIdx.x] = tot;
+    for (int r = 0; r < kRows; ++r) tot += s_big[r * 32 + thread_index()];
+    s_out[thread_index()] = tot;
   }
   __syncthreads();
   return true;
@@ -378,7 +378,7 @@ __device__ __forceinline__ bool gang_reduce_impl(float (&acc)[L], const FrameArg
 }
 
 __device__ __forceinline__ void trace_point(const FrameArgs& a, int tile, int idx) {
-  if (a.trace && threadIdx.x == 0 && idx < 64) a.trace[(size_t)tile * 64 + idx] = wall_clock64();
+  if (a.trace && thread_index() == 0 && idx < 64) a.trace[(size_t)tile * 64 + idx] = wall_clock64();
 }
 
 template <int L>
@@ -396,7 +396,7 @@ __device__ __forceinline__ bool gang_reduce(float (&acc)[L], const FrameArgs& a,
 // Sec. 3.4) for pixels [p0, p0 + npx) of a W x H image.
 __device__ __forceinline__ void median3x3_range(const uint8_t* __restrict__ lab, uint8_t* __restrict__ mask, int W,
                                                 int H, int p0, int npx) {
-  for (int pl = threadIdx.x; pl < npx; pl += blockDim.x) {
+  for (int pl = thread_index(); pl < npx; pl += blockDim.x) {
     const int pix = p0 + pl;
     const int row = pix / W, col = pix - row * W;
     const int rows[3] = {max(row - 1, 0), row, min(row + 1, H - 1)};
@@ -429,7 +429,7 @@ struct TileCtx {
 template <int K>
 __device__ __forceinline__ TileCtx tile_begin(const FrameArgs& a, const int tile, KSpace<kMaxK>& ks) {
   TileCtx t;
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   t.p0 = tile * a.tpw;
   t.npx = min(a.tpw, a.P - t.p0);
   t.nq = t.npx * a.C;
@@ -458,7 +458,7 @@ __device__ __forceinline__ TileCtx tile_begin(const FrameArgs& a, const int tile
 template <int K>
 __device__ __forceinline__ void cg_direction(const FrameArgs& a, KSpace<kMaxK>& ks, int it, bool lead,
                                              int& restarts) {
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = thread_index(), lane = tid & 63;
   if (tid < 64) {
     const double g = (lane < K) ? -ks.red[lane] : 0.0;
     const double f = ks.red[K];
@@ -503,7 +503,7 @@ __device__ __forceinline__ void cg_direction(const FrameArgs& a, KSpace<kMaxK>& 
 // alpha as float for the residual update.
 template <int K>
 __device__ __forceinline__ float cg_advance(const FrameArgs& a, KSpace<kMaxK>& ks, double dHd, int it, bool lead) {
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const double alpha = -ks.gd / dHd;
   __syncthreads();
   if (tid < K) {
@@ -521,7 +521,7 @@ __device__ __forceinline__ float cg_advance(const FrameArgs& a, KSpace<kMaxK>& k
 template <int K>
 __device__ __forceinline__ void geodesic_setup(const FrameArgs& a, KSpace<kMaxK>& ks, long long n, int steps,
                                                bool lead) {
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = thread_index(), lane = tid & 63;
   if (tid < 64) {
     const double av = (lane < K) ? ks.red[lane] : 0.0;
     const double yv = (lane < K) ? ks.y[lane] : 0.0;
@@ -563,7 +563,7 @@ __device__ __forceinline__ void geodesic_setup(const FrameArgs& a, KSpace<kMaxK>
 // flagged in s_flag (entry q = c * npx + pixel).
 __device__ __forceinline__ void write_labels(const FrameArgs& a, const uint8_t* s_flag, int p0, int npx) {
   __syncthreads();
-  for (int pl = threadIdx.x; pl < npx; pl += kBlock) {
+  for (int pl = thread_index(); pl < npx; pl += kBlock) {
     uint8_t f = 0;
     for (int c = 0; c < a.C; ++c) f |= s_flag[c * npx + pl];
     a.lab[p0 + pl] = f;
@@ -573,7 +573,7 @@ __device__ __forceinline__ void write_labels(const FrameArgs& a, const uint8_t* 
 // Statistics, frame counter, y and the exchange bases for the next launch.
 __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSpace<kMaxK>& ks, const TileCtx& t,
                                          int steps, int restarts, bool bad, int nbar) {
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   trace_point(a, tile, 63);
   if (t.lead && tid == 0) {
     a.stats->frame = t.n;
@@ -602,7 +602,7 @@ template <int K, int NR>
 __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const TileCtx ctx = tile_begin<K>(a, tile, ks);
   int nbar = 0;
 
@@ -772,7 +772,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   static_assert(2 * NP <= kMaxNR && NP <= 16, "row bit masks hold 32 rows");
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
-  const int tid = threadIdx.x;
+  const int tid = thread_index();
   const TileCtx ctx = tile_begin<K>(a, tile, ks);
   int nbar = 0;
   const bool al = a.pair_aligned != 0;
