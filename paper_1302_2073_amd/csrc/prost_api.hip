@@ -454,6 +454,8 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.cp.half_p = (float)(0.5 * p.p);
   a.cp.mu = (float)p.mu;
   a.cp.inv_mu = (float)(1.0 / p.mu);
+  a.cp.half_p_m1 = (float)(0.5 * p.p - 1.0);
+  a.cp.inv_p = (float)(1.0 / p.p);
   a.delta = (float)effective_delta(p);
   a.omega = (float)p.omega;
   a.t_init = p.t_init;

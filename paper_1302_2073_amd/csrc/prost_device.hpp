@@ -56,21 +56,22 @@ struct CostParams {
   float half_p;   // p / 2
   float mu;       // smoothing
   float inv_mu;   // 1 / mu
+  float half_p_m1;  // p / 2 - 1
+  float inv_p;    // 1 / p
   int form;       // 0: (r^2+mu)^(p/2), 1: log(1 + r^2/mu)
 };
 
-// phi(r) and c(r) = phi'(r)/r.  lp: phi = s^(p/2), c = p s^(p/2-1) with
-// s = r^2 + mu.  log: phi = log(1 + r^2/mu), c = 2/s.
+// phi(r) and c(r) = phi'(r)/r.  lp: c = p s^(p/2-1) with s = r^2 + mu and
+// phi = s^(p/2) = c s / p (two transcendental instructions: log2, exp2).
+// log: phi = log(1 + r^2/mu), c = 2/s.
 __device__ __forceinline__ void cost_eval(float r, const CostParams& cp, float& phi, float& c) {
   const float s = fmaf(r, r, cp.mu);
-  const float inv_s = __builtin_amdgcn_rcpf(s);
   if (cp.form == 0) {
-    const float ph = __builtin_amdgcn_exp2f(cp.half_p * __builtin_amdgcn_logf(s));
-    phi = ph;
-    c = cp.p * ph * inv_s;
+    c = cp.p * __builtin_amdgcn_exp2f(cp.half_p_m1 * __builtin_amdgcn_logf(s));
+    phi = c * s * cp.inv_p;
   } else {
     phi = 0.69314718055994531f * __builtin_amdgcn_logf(fmaf(r * r, cp.inv_mu, 1.0f));
-    c = 2.0f * inv_s;
+    c = 2.0f * __builtin_amdgcn_rcpf(s);
   }
 }
 

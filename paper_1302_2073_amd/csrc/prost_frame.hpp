@@ -86,6 +86,11 @@ struct FrameSmem {
 };
 
 
+// Diagnostics: wall-clock timestamp `idx` (< 64) of a tile, by thread 0.
+__device__ __forceinline__ void trace_point(const FrameArgs& a, int tile, int idx) {
+  if (a.trace && thread_index() == 0 && idx < 64) a.trace[(size_t)tile * 64 + idx] = wall_clock64();
+}
+
 // Workgroup + gang reduction of L float partials held by every thread.
 // Result (float64, identical in every workgroup) lands in s_out[0..L).
 // Tagged gather/broadcast: every workgroup publishes its tagged partial
@@ -265,6 +270,7 @@ __device__ __forceinline__ bool gang_reduce_2level(const double* wg_sum, const F
       for (int r = 0; r < kRows; ++r) g += s_big[r * 32 + tid];
       st_tagged(&gs[(size_t)x * kSlot + tid], tag_value(g, ep));
     }
+    trace_point(a, tile, 25 + 3 * (nbar - 1));
     __syncthreads();
   }
   if (!poll_sum_slots<L>(gs, ngrp, ep, a, s_big, s_out)) return false;
@@ -368,6 +374,7 @@ __device__ __forceinline__ bool gang_reduce_impl(float (&acc)[L], const FrameArg
   }
   if (a.sync_mode == 2) {
     wg_reduce<L>(acc, sm.red, sm.wg);
+    trace_point(a, tile, 24 + 3 * nbar);
     return gang_reduce_2level<L>(sm.wg, a, tile, nbar, ebase, sm.big, s_out, sm.ctl, fenced);
   }
   if (a.sync_mode == 3) {
@@ -377,9 +384,6 @@ __device__ __forceinline__ bool gang_reduce_impl(float (&acc)[L], const FrameArg
   return gang_reduce_counter<L>(acc, a, tile, nbar, base, sm.red, sm.big, s_out, sm.ctl);
 }
 
-__device__ __forceinline__ void trace_point(const FrameArgs& a, int tile, int idx) {
-  if (a.trace && thread_index() == 0 && idx < 64) a.trace[(size_t)tile * 64 + idx] = wall_clock64();
-}
 
 template <int L>
 __device__ __forceinline__ bool gang_reduce(float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,

@@ -34,6 +34,8 @@ __device__ __forceinline__ CostParams make_cp(int form, float p, float mu) {
   cp.half_p = 0.5f * p;
   cp.mu = mu;
   cp.inv_mu = 1.0f / mu;
+  cp.half_p_m1 = 0.5f * p - 1.0f;
+  cp.inv_p = 1.0f / p;
   return cp;
 }
 
