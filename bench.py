@@ -75,6 +75,26 @@ def make_frames(pool, dtype):
     return wl, sv, t.contiguous()
 
 
+REPEATS = 5   # timed repeats per form; the median is reported
+
+
+def timed_median(fn, steps, stream):
+    """Median over REPEATS of the HIP-event time (ms) of `steps` calls of fn
+    on `stream`, plus the spread."""
+    import torch
+    ts = []
+    for _ in range(REPEATS):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            fn(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2], ts[0], ts[-1]
+
+
 def run_plain(storage, steps, warmup, pool):
     import torch
     from paper_1302_2073_amd import Tracker
@@ -83,24 +103,45 @@ def run_plain(storage, steps, warmup, pool):
     trk = Tracker(WIDTH, HEIGHT, CH, K, mu=wl.mu, storage=storage)
     trk.set_state(V.initial_subspace(trk.m, K, wl.video.seed))
     stream = torch.cuda.current_stream()   # the tracker was created on this stream
-    for i in range(warmup):
+    for i in range(max(warmup, 50)):
         trk.track(frames[i % pool])
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(steps):
-        trk.track(frames[(warmup + i) % pool])
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms, lo, hi = timed_median(lambda i: trk.track(frames[i % pool]), steps, stream)
     st = trk.sync()
     if st != 0:
         raise RuntimeError(f"tracker error {st}")
-    ms = e0.elapsed_time(e1)
     info = trk.launch_info()
     stats = trk.stats()
     trk.close()
     return dict(ms_total=ms, ms_per_frame=ms / steps, fps=steps / (ms / 1e3), launch=info,
-                fg=None, cg_steps=stats["cg_steps"])
+                cg_steps=stats["cg_steps"], spread_ms=[round(lo, 3), round(hi, 3)])
+
+
+def run_plain_host(steps, warmup, pool):
+    """One float32 stream fed from host memory: every frame crosses PCIe
+    (pageable copy into the handle's staging buffer) before its launch.
+    Wall-clock rate of the whole loop."""
+    import torch
+    from paper_1302_2073_amd import Tracker
+    from synth import video as V
+    wl = V.vga_rgb()
+    sv = V.SyntheticVideo(wl.video)
+    frames = [np.ascontiguousarray(sv.frame(n).astype(np.float32)) for n in range(pool)]
+    trk = Tracker(WIDTH, HEIGHT, CH, K, mu=wl.mu, storage="f32")
+    trk.set_state(V.initial_subspace(trk.m, K, wl.video.seed))
+    for i in range(max(warmup, 50)):
+        trk.track(frames[i % pool])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        trk.track(frames[(warmup + i) % pool])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = trk.sync()
+    trk.close()
+    if st != 0:
+        raise RuntimeError(f"tracker error {st}")
+    return dict(ms_total=el * 1e3, ms_per_frame=el * 1e3 / steps, fps=steps / el)
 
 
 def run_batched(storage, nstreams, steps, warmup, pool, tune=True):
@@ -132,19 +173,95 @@ def run_batched(storage, nstreams, steps, warmup, pool, tune=True):
     for _ in range(warmup):
         bt.step()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        bt.step()
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms, lo, hi = timed_median(lambda i: bt.step(), steps, stream)
     st = bt.sync()
     if st != 0:
         raise RuntimeError(f"batch error {st}")
-    ms = e0.elapsed_time(e1)
     cfg = bt.config()
     bt.close()
-    return dict(ms_total=ms, ms_per_step=ms / steps, fps=steps * nstreams / (ms / 1e3), config=cfg, tuned=tuned)
+    return dict(ms_total=ms, ms_per_step=ms / steps, fps=steps * nstreams / (ms / 1e3), config=cfg, tuned=tuned,
+                spread_ms=[round(lo, 3), round(hi, 3)])
+
+
+def run_batched_mixed(nstreams, steps, warmup, pool):
+    """The mixed workload: nstreams bfloat16 streams of uneven size and k
+    (160x120 / 320x240 / 640x480 RGB, k in {5, 10, 15}), one persistent
+    launch per step (hipGraph), tuned.  Returns stream-frames/s and the
+    same work in 640x480x3, k=15 frame equivalents (by m k)."""
+    import torch
+    from paper_1302_2073_amd.tracker import BatchTracker, bf16_bits
+    from synth import video as V
+    wls = V.mixed_streams(nstreams)
+    specs, frames, mk, alg = [], [], 0, 0
+    for s, wl in enumerate(wls):
+        v = wl.video
+        specs.append(dict(width=v.width, height=v.height, channels=3, k=wl.k, mu=wl.mu))
+        sv = V.SyntheticVideo(v)
+        frames.append([torch.from_numpy(bf16_bits(sv.frame(n)).view(np.int16)).cuda().view(torch.bfloat16)
+                       for n in range(pool)])
+        mk += v.m * wl.k
+        alg += alg_bytes(v.m, wl.k, v.width * v.height, 2, 2)
+    bt = BatchTracker(specs, storage="bf16")
+    for s, wl in enumerate(wls):
+        bt.set_state(s, V.initial_subspace(wl.video.m, wl.k, 4, s))
+    bt.set_frames(frames)
+    tuned = bt.tune(steps=3)
+    bt.use_graph(True)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        bt.step()
+    torch.cuda.synchronize()
+    ms, lo, hi = timed_median(lambda i: bt.step(), steps, stream)
+    st = bt.sync()
+    cfg = bt.config()
+    bt.close()
+    if st != 0:
+        raise RuntimeError(f"batch error {st}")
+    per = ms / steps
+    return dict(ms_total=ms, ms_per_step=per, fps=nstreams / (per * 1e-3),
+                vga_k15_equiv_fps=(mk / (WIDTH * HEIGHT * CH * K)) / (per * 1e-3),
+                alg_bytes_per_step=alg, config=cfg, tuned=tuned, spread_ms=[round(lo, 3), round(hi, 3)])
+
+
+def run_lpcost(steps, warmup):
+    """Differentiation form: forward + backward of the weighted smoothed cost
+    over B = 32 frames of m = 230400 entries, k = 10 (float32)."""
+    import ctypes as C
+    import torch
+    from paper_1302_2073_amd import _lib as L
+    from synth import video as V
+    U, Y, X, w = V.lpcost_batch()
+    m, k = U.shape
+    B = Y.shape[1]
+    dev = "cuda"
+    Ut = torch.tensor(U, dtype=torch.float32, device=dev).contiguous()
+    Yt = torch.tensor(Y.T, dtype=torch.float32, device=dev).contiguous()
+    Xt = torch.tensor(X.T, dtype=torch.float32, device=dev).contiguous()
+    mu = torch.tensor([1e-3], dtype=torch.float32, device=dev)
+    f = torch.empty(B, dtype=torch.float32, device=dev)
+    g = torch.ones(B, dtype=torch.float32, device=dev)
+    dX, dU, dY = torch.empty_like(Xt), torch.empty_like(Ut), torch.empty_like(Yt)
+    dmu = torch.empty(1, dtype=torch.float32, device=dev)
+    lib = L.lib()
+    nws = lib.pros_lpcost_workspace_size(m, k, B)
+    ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+
+    def step(i):
+        L.check(lib.pros_lpcost_fwd(ptr(Ut), ptr(Yt), ptr(Xt), None, ptr(mu), m, k, B, L.PROS_COST_LP, 0.25,
+                                    ptr(f), ptr(ws), nws, sp))
+        L.check(lib.pros_lpcost_bwd(ptr(Ut), ptr(Yt), ptr(Xt), None, ptr(mu), m, k, B, L.PROS_COST_LP, 0.25,
+                                    ptr(g), ptr(dX), ptr(dU), ptr(dY), ptr(dmu), ptr(ws), nws, sp))
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ms, lo, hi = timed_median(step, steps, stream)
+    per = ms / steps
+    alg = (m * k * 4 + B * m * 4) + 2 * (m * k * 4 + B * m * 4)   # forward + backward compulsory bytes
+    return dict(ms_total=ms, ms_per_step=per, fps=B / (per * 1e-3), alg_bytes_per_step=alg,
+                spread_ms=[round(lo, 3), round(hi, 3)])
 
 
 def cpu_baseline(seconds=15.0):
@@ -182,7 +299,7 @@ def main():
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--streams", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--forms", default="plain_f32,plain_bf16,batched_bf16",
+    ap.add_argument("--forms", default="plain_f32,plain_bf16,plain_f32_host,batched_bf16,batched_mixed_bf16,lpcost",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -219,11 +336,30 @@ def main():
     if "plain_bf16" in want:
         plain_bf16 = run_plain("bf16", args.steps * 4, args.warmup, args.pool)
         record("plain_bf16", plain_bf16, 2, 2)
+    if "plain_f32_host" in want:
+        host = run_plain_host(args.steps, args.warmup, args.pool)
+        record("plain_f32_host", host, 4, 4)
+        forms["plain_f32_host"]["note"] = "frames from host memory (PCIe copy per frame), wall clock"
     if "batched_bf16" in want:
         batched = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune)
         achieved = record("batched_bf16", batched, 2, 2, args.streams)
         if plain:
             forms["batched_bf16"]["vs_plain_f32"] = round(batched["fps"] / plain["fps"], 3)
+    if "batched_mixed_bf16" in want:
+        mixed = run_batched_mixed(64, max(args.steps // 4, 10), args.warmup, args.pool)
+        per = mixed["ms_per_step"]
+        forms["batched_mixed_bf16"] = {
+            "stream_fps": round(mixed["fps"], 1), "vga_k15_equiv_fps": round(mixed["vga_k15_equiv_fps"], 1),
+            "ms_per_step": round(per, 5), "alg_GBps": round(mixed["alg_bytes_per_step"] / (per * 1e-3) / 1e9, 1),
+            "streams": 64, "config": mixed["config"], "spread_ms": mixed["spread_ms"]}
+    if "lpcost" in want:
+        lp = run_lpcost(args.steps, args.warmup)
+        per = lp["ms_per_step"]
+        gbps = lp["alg_bytes_per_step"] / (per * 1e-3) / 1e9
+        forms["lpcost"] = {"frames_per_s": round(lp["fps"], 1), "ms_per_fwd_bwd": round(per, 5),
+                           "alg_GBps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / PEAK_HBM_GBS, 4),
+                           "workload": "forward + backward, m = 230400, k = 10, B = 32, float32",
+                           "spread_ms": lp["spread_ms"]}
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
