@@ -20,12 +20,11 @@
 
 namespace prost {
 
-constexpr int kLpChunk = 32;   // frames of Y staged in LDS at a time
-
-template <int K>
-struct LpRows {
-  static constexpr int R = (K <= 8) ? 8 : 4;   // rows per thread
-};
+constexpr int kLpBlock = 256;        // rows of U per workgroup, one per thread
+constexpr int kLpWaves = kLpBlock / 64;
+constexpr int kLpChunkF = 32;        // frames per pass, forward
+constexpr int kLpChunkB = 16;        // frames per pass, backward (LDS for s)
+constexpr int kLpPad = kLpBlock + 4; // LDS row stride (16-byte aligned, spreads banks)
 
 __device__ __forceinline__ CostParams make_cp(int form, float p, float mu) {
   CostParams cp;
@@ -44,185 +43,202 @@ __device__ __forceinline__ float dphi_dmu(float r, float c, const CostParams& cp
   return (cp.form == 0) ? 0.5f * c : -r * r * c * 0.5f * cp.inv_mu;
 }
 
+// Stage the workgroup's rows of U (row-major, K per row) transposed into
+// LDS with coalesced reads; rows past the end are zero.
 template <int K>
-__global__ __launch_bounds__(kBlock) void lpcost_fwd_kernel(const float* __restrict__ U, const float* __restrict__ Y,
-                                                            const float* __restrict__ X, const float* __restrict__ w,
-                                                            int m, int B, int form, float p, const float* __restrict__ mu_p,
-                                                            double* __restrict__ part) {
-  constexpr int R = LpRows<K>::R;
-  __shared__ float ys[kLpChunk][K];
-  __shared__ double red[kWaves][kLpChunk];
-  const CostParams cp = make_cp(form, p, *mu_p);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const long long row0 = (long long)blockIdx.x * kBlock * R;
-  float u[R][K], wt[R];
-  long long ex[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const long long e = row0 + s * kBlock + tid;
-    ex[s] = e;
-    wt[s] = 0.f;
-#pragma unroll
-    for (int j = 0; j < K; ++j) u[s][j] = 0.f;
-    if (e < m) {
-      wt[s] = w ? w[e] : 1.0f;
-#pragma unroll
-      for (int j = 0; j < K; ++j) u[s][j] = U[e * K + j];
-    }
+__device__ __forceinline__ void stage_rows(const float* __restrict__ U, long long e0, int nrow, float (*uT)[kLpPad]) {
+  for (int q = thread_index(); q < kLpBlock * K; q += kLpBlock) {
+    const int row = q / K, j = q - row * K;
+    uT[j][row] = (row < nrow) ? U[e0 * K + q] : 0.f;
   }
-  for (int b0 = 0; b0 < B; b0 += kLpChunk) {
-    const int nb = min(kLpChunk, B - b0);
-    __syncthreads();
-    for (int q = tid; q < nb * K; q += kBlock) ys[q / K][q % K] = Y[(long long)(b0 + q / K) * K + q % K];
-    __syncthreads();
-    for (int bl = 0; bl < nb; ++bl) {
-      const float* xb = X + (long long)(b0 + bl) * m;
-      float acc = 0.f;
+}
+
+// Frames [b0, b0 + nb) of Y into LDS.
+template <int K, int CH>
+__device__ __forceinline__ void stage_frames(const float* __restrict__ Y, int b0, int nb, float (*ys)[K]) {
+  for (int q = thread_index(); q < nb * K; q += kLpBlock) ys[q / K][q % K] = Y[(long long)b0 * K + q];
+}
+
+// Forward: each thread owns one row e (u_e in registers) and walks the
+// frames; the chunk's frame entries are requested before U and Y are staged,
+// so their latency overlaps.  Per frame the workgroup's sum of w phi(r) is
+// formed with one in-place reduce-scatter per chunk and float64 across
+// wavefronts.
+template <int K>
+__global__ __launch_bounds__(kLpBlock) void lpcost_fwd_kernel(const float* __restrict__ U, const float* __restrict__ Y,
+                                                              const float* __restrict__ X, const float* __restrict__ w,
+                                                              int m, int B, int form, float p, const float* __restrict__ mu_p,
+                                                              double* __restrict__ part) {
+  constexpr int CH = kLpChunkF;
+  __shared__ __align__(16) float uT[K][kLpPad];
+  __shared__ float ys[CH][K];
+  __shared__ double red[kLpWaves][CH];
+  const CostParams cp = make_cp(form, p, *mu_p);
+  const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
+  const long long e0 = (long long)blockIdx.x * kLpBlock;
+  const int nrow = (int)((long long)m - e0 < kLpBlock ? (long long)m - e0 : kLpBlock);
+  const bool valid = tid < nrow;
+  const long long e = e0 + tid;
+  const float wt = valid ? (w ? w[e] : 1.0f) : 0.f;
+  float u[K];
+  for (int b0 = 0; b0 < B; b0 += CH) {
+    const int nb = min(CH, B - b0);
+    float xv[CH];
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        if (ex[s] < m) {
-          float r = xb[ex[s]];
+    for (int bl = 0; bl < CH; ++bl) xv[bl] = (bl < nb && valid) ? X[(long long)(b0 + bl) * m + e] : 0.f;
+    __syncthreads();
+    if (b0 == 0) stage_rows<K>(U, e0, nrow, uT);
+    stage_frames<K, CH>(Y, b0, nb, ys);
+    __syncthreads();
+    if (b0 == 0) {
 #pragma unroll
-          for (int j = 0; j < K; ++j) r = fmaf(-u[s][j], ys[bl][j], r);
-          float phi, c;
-          cost_eval(r, cp, phi, c);
-          acc = fmaf(wt[s], phi, acc);
-        }
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) red[wv][bl] = (double)acc;
+      for (int j = 0; j < K; ++j) u[j] = uT[j][tid];
     }
+    float acc[CH];
+#pragma unroll
+    for (int bl = 0; bl < CH; ++bl) {
+      float r = xv[bl];
+#pragma unroll
+      for (int j = 0; j < K; ++j) r = fmaf(-u[j], ys[bl][j], r);
+      float phi, c;
+      cost_eval(r, cp, phi, c);
+      acc[bl] = (bl < nb) ? wt * phi : 0.f;
+    }
+    int comp;
+    const float v = wave_reduce_scatter<CH>(acc, comp);
+    if ((lane & 1) == 0) red[wv][comp] = (double)v;   // each component once per wavefront
     __syncthreads();
     if (tid < nb) {
-      double v = 0.0;
+      double sum = 0.0;
 #pragma unroll
-      for (int q = 0; q < kWaves; ++q) v += red[q][tid];
-      part[(size_t)blockIdx.x * B + b0 + tid] = v;
+      for (int q = 0; q < kLpWaves; ++q) sum += red[q][tid];
+      part[(size_t)blockIdx.x * B + b0 + tid] = sum;
     }
   }
 }
 
-__global__ void lpcost_fwd_finish(const double* __restrict__ part, int nblk, int B, float* __restrict__ f) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  double s = 0.0;
-  for (int q = 0; q < nblk; ++q) s += part[(size_t)q * B + b];
-  f[b] = (float)s;
-}
-
+// Backward: per frame each thread forms s = g w phi'(r) for its row, writes
+// dX, accumulates its dU row and dmu in registers, and leaves s in LDS; after
+// each chunk the workgroup's share of dY (chunk x K) is formed from LDS, one
+// output per thread, rows in order.  Partials: nb x K of dY per chunk, then
+// dmu last (n = B K + 1 per workgroup).
 template <int K>
-__global__ __launch_bounds__(kBlock) void lpcost_bwd_kernel(const float* __restrict__ U, const float* __restrict__ Y,
-                                                            const float* __restrict__ X, const float* __restrict__ w,
-                                                            int m, int B, int form, float p, const float* __restrict__ mu_p,
-                                                            const float* __restrict__ gout, float* __restrict__ dX,
-                                                            float* __restrict__ dU, double* __restrict__ part_dy,
-                                                            double* __restrict__ part_dmu) {
-  constexpr int R = LpRows<K>::R;
-  __shared__ float ys[kLpChunk][K];
-  __shared__ float gs[kLpChunk];
-  __shared__ double red[kWaves][kLpChunk * K];
-  __shared__ double redm[kWaves];
+__global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __restrict__ U, const float* __restrict__ Y,
+                                                              const float* __restrict__ X, const float* __restrict__ w,
+                                                              int m, int B, int form, float p, const float* __restrict__ mu_p,
+                                                              const float* __restrict__ gout, float* __restrict__ dX,
+                                                              float* __restrict__ dU, double* __restrict__ part) {
+  constexpr int CH = kLpChunkB;
+  __shared__ __align__(16) float uT[K][kLpPad];
+  __shared__ __align__(16) float sdl[CH][kLpPad];
+  __shared__ float ys[CH][K];
+  __shared__ float gs[CH];
+  __shared__ double redm[kLpWaves];
   const CostParams cp = make_cp(form, p, *mu_p);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const long long row0 = (long long)blockIdx.x * kBlock * R;
-  float u[R][K], du[R][K], wt[R];
-  long long ex[R];
+  const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
+  const long long e0 = (long long)blockIdx.x * kLpBlock;
+  const int nrow = (int)((long long)m - e0 < kLpBlock ? (long long)m - e0 : kLpBlock);
+  const bool valid = tid < nrow;
+  const long long e = e0 + tid;
+  const float wt = valid ? (w ? w[e] : 1.0f) : 0.f;
+  const size_t np = (size_t)B * K + 1;
+  float u[K], du[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) du[j] = 0.f;
   float dmu = 0.f;
+  for (int b0 = 0; b0 < B; b0 += CH) {
+    const int nb = min(CH, B - b0);
+    float xv[CH];
 #pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const long long e = row0 + s * kBlock + tid;
-    ex[s] = e;
-    wt[s] = 0.f;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      u[s][j] = 0.f;
-      du[s][j] = 0.f;
-    }
-    if (e < m) {
-      wt[s] = w ? w[e] : 1.0f;
-#pragma unroll
-      for (int j = 0; j < K; ++j) u[s][j] = U[e * K + j];
-    }
-  }
-  for (int b0 = 0; b0 < B; b0 += kLpChunk) {
-    const int nb = min(kLpChunk, B - b0);
+    for (int bl = 0; bl < CH; ++bl) xv[bl] = (bl < nb && valid) ? X[(long long)(b0 + bl) * m + e] : 0.f;
     __syncthreads();
-    for (int q = tid; q < nb * K; q += kBlock) ys[q / K][q % K] = Y[(long long)(b0 + q / K) * K + q % K];
+    if (b0 == 0) stage_rows<K>(U, e0, nrow, uT);
+    stage_frames<K, CH>(Y, b0, nb, ys);
     if (tid < nb) gs[tid] = gout[b0 + tid];
     __syncthreads();
-    for (int bl = 0; bl < nb; ++bl) {
-      const long long boff = (long long)(b0 + bl) * m;
-      const float g = gs[bl];
-      float dy[K];
+    if (b0 == 0) {
 #pragma unroll
-      for (int j = 0; j < K; ++j) dy[j] = 0.f;
+      for (int j = 0; j < K; ++j) u[j] = uT[j][tid];
+    }
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        if (ex[s] < m) {
-          float r = X[boff + ex[s]];
+    for (int bl = 0; bl < CH; ++bl) {
+      float sd = 0.f;
+      if (bl < nb && valid) {
+        float r = xv[bl];
 #pragma unroll
-          for (int j = 0; j < K; ++j) r = fmaf(-u[s][j], ys[bl][j], r);
-          float phi, c;
-          cost_eval(r, cp, phi, c);
-          const float sd = g * wt[s] * c * r;          // g w phi'(r)
-          if (dX) dX[boff + ex[s]] = sd;
-          dmu = fmaf(g * wt[s], dphi_dmu(r, c, cp), dmu);
+        for (int j = 0; j < K; ++j) r = fmaf(-u[j], ys[bl][j], r);
+        float phi, c;
+        cost_eval(r, cp, phi, c);
+        const float gw = gs[bl] * wt;
+        sd = gw * c * r;                         // g w phi'(r)
+        if (dX) dX[(long long)(b0 + bl) * m + e] = sd;
+        dmu = fmaf(gw, dphi_dmu(r, c, cp), dmu);
 #pragma unroll
-          for (int j = 0; j < K; ++j) {
-            du[s][j] = fmaf(-sd, ys[bl][j], du[s][j]);
-            dy[j] = fmaf(-sd, u[s][j], dy[j]);
-          }
-        }
+        for (int j = 0; j < K; ++j) du[j] = fmaf(-sd, ys[bl][j], du[j]);
       }
-#pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const float v = wave_sum(dy[j]);
-        if (lane == 0) red[wv][bl * K + j] = (double)v;
-      }
+      if (bl < nb) sdl[bl][tid] = sd;
     }
     __syncthreads();
-    for (int q = tid; q < nb * K; q += kBlock) {
-      double v = 0.0;
-#pragma unroll
-      for (int wq = 0; wq < kWaves; ++wq) v += red[wq][q];
-      part_dy[(size_t)blockIdx.x * B * K + (size_t)b0 * K + q] = v;
+    // dY share of this workgroup: -sum_rows s[b][row] u[row][j], rows in order
+    // (four interleaved float32 partial sums, combined in float64)
+    for (int q = tid; q < nb * K; q += kLpBlock) {
+      const int bl = q / K, j = q - bl * K;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll 4
+      for (int row = 0; row < kLpBlock; row += 4) {
+        const float4 sv = *(const float4*)&sdl[bl][row];
+        const float4 uv = *(const float4*)&uT[j][row];
+        a0 = fmaf(sv.x, uv.x, a0);
+        a1 = fmaf(sv.y, uv.y, a1);
+        a2 = fmaf(sv.z, uv.z, a2);
+        a3 = fmaf(sv.w, uv.w, a3);
+      }
+      part[(size_t)blockIdx.x * np + (size_t)b0 * K + q] = -(((double)a0 + (double)a1) + ((double)a2 + (double)a3));
     }
   }
-  if (dU) {
+  if (dU) {   // coalesced store of the workgroup's dU rows through LDS
+    static_assert(CH * kLpPad >= kLpBlock * K, "dU staging fits the s buffer");
+    __syncthreads();
+    float* buf = &sdl[0][0];
 #pragma unroll
-    for (int s = 0; s < R; ++s)
-      if (ex[s] < m)
-#pragma unroll
-        for (int j = 0; j < K; ++j) dU[ex[s] * K + j] = du[s][j];
+    for (int j = 0; j < K; ++j) buf[tid * K + j] = du[j];
+    __syncthreads();
+    for (int q = tid; q < nrow * K; q += kLpBlock) dU[e0 * K + q] = buf[q];
   }
   const float dm = wave_sum(dmu);
   if (lane == 0) redm[wv] = (double)dm;
   __syncthreads();
   if (tid == 0) {
     double v = 0.0;
-    for (int q = 0; q < kWaves; ++q) v += redm[q];
-    part_dmu[blockIdx.x] = v;
+    for (int q = 0; q < kLpWaves; ++q) v += redm[q];
+    part[(size_t)blockIdx.x * np + (size_t)B * K] = v;
   }
 }
 
-__global__ void lpcost_bwd_finish(const double* __restrict__ part_dy, const double* __restrict__ part_dmu, int nblk,
-                                  int BK, float* __restrict__ dY, float* __restrict__ dmu) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < BK && dY) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part_dy[(size_t)b * BK + q];
-    dY[q] = (float)s;
-  }
-  if (q == 0 && dmu) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part_dmu[b];
-    *dmu = (float)s;
+// out[q] = sum over workgroups b of part[b * n + q] (q < n0 to out0, the
+// rest to out1), one workgroup per output: thread t adds partials t, t + 256,
+// ... in order, then fixed-order wavefront and workgroup sums.
+__global__ __launch_bounds__(256) void lpcost_finish(const double* __restrict__ part, int nblk, int n, int n0,
+                                                     float* __restrict__ out0, float* __restrict__ out1) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int b = t; b < nblk; b += 256) s += part[(size_t)b * n + q];
+  s = wave_sum(s);
+  if ((t & 63) == 0) red[t >> 6] = s;
+  __syncthreads();
+  if (t == 0) {
+    const double v = (red[0] + red[1]) + (red[2] + red[3]);
+    if (q < n0) {
+      if (out0) out0[q] = (float)v;
+    } else if (out1) {
+      out1[q - n0] = (float)v;
+    }
   }
 }
 
-static int lp_blocks_k(int k, int m) {
-  return (k <= 8) ? (int)((m + kBlock * 8LL - 1) / (kBlock * 8LL)) : (int)((m + kBlock * 4LL - 1) / (kBlock * 4LL));
-}
+static int lp_blocks(int m) { return (m + kLpBlock - 1) / kLpBlock; }
 
 }  // namespace prost
 
@@ -245,8 +261,8 @@ extern "C" {
 
 size_t pros_lpcost_workspace_size(int32_t m, int32_t k, int32_t B) {
   if (m <= 0 || k < 1 || k > PROS_MAX_K || B <= 0) return 0;
-  const size_t nblk = (size_t)lp_blocks_k(k, m);
-  return sizeof(double) * (nblk * (size_t)B * k + nblk * (size_t)B + nblk) + 256;
+  const size_t nblk = (size_t)lp_blocks(m);
+  return sizeof(double) * (nblk * ((size_t)B * k + 1) + nblk * (size_t)B) + 256;
 }
 
 static pros_status lp_check(const float* U, const float* Y, const float* X, const float* mu, int32_t m, int32_t k,
@@ -267,11 +283,11 @@ pros_status pros_lpcost_fwd(const float* U, const float* Y, const float* X, cons
   if (!f) return prost_host::set_error(PROS_EINVAL, "f is NULL");
   hipStream_t s = (hipStream_t)hip_stream;
   double* part = (double*)workspace;
-  const int nblk = lp_blocks_k(k, m);
+  const int nblk = lp_blocks(m);
   const int form = (cost == PROS_COST_LOG) ? 1 : 0;
-  PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_fwd_kernel<KK>), dim3(nblk), dim3(kBlock), 0, s, U, Y, X, w, m, B,
+  PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_fwd_kernel<KK>), dim3(nblk), dim3(kLpBlock), 0, s, U, Y, X, w, m, B,
                                        form, p, mu, part));
-  hipLaunchKernelGGL(lpcost_fwd_finish, dim3((B + 255) / 256), dim3(256), 0, s, (const double*)part, nblk, B, f);
+  hipLaunchKernelGGL(lpcost_finish, dim3(B), dim3(256), 0, s, (const double*)part, nblk, B, B, f, (float*)nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return prost_host::set_error(PROS_EHIP, "lpcost forward launch: %s", hipGetErrorString(e));
   return PROS_OK;
@@ -285,15 +301,15 @@ pros_status pros_lpcost_bwd(const float* U, const float* Y, const float* X, cons
   if (st != PROS_OK) return st;
   if (!gout) return prost_host::set_error(PROS_EINVAL, "gout is NULL");
   hipStream_t s = (hipStream_t)hip_stream;
-  const int nblk = lp_blocks_k(k, m);
-  double* part_dy = (double*)workspace;
-  double* part_dmu = part_dy + (size_t)nblk * B * k;
+  const int nblk = lp_blocks(m);
+  double* part = (double*)workspace;
   const int form = (cost == PROS_COST_LOG) ? 1 : 0;
-  PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_bwd_kernel<KK>), dim3(nblk), dim3(kBlock), 0, s, U, Y, X, w, m, B,
-                                       form, p, mu, gout, dX, dU, part_dy, part_dmu));
-  const int BK = B * k;
-  hipLaunchKernelGGL(lpcost_bwd_finish, dim3((BK + 255) / 256), dim3(256), 0, s, (const double*)part_dy,
-                     (const double*)part_dmu, nblk, BK, dY, dmu);
+  PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_bwd_kernel<KK>), dim3(nblk), dim3(kLpBlock), 0, s, U, Y, X, w, m, B,
+                                       form, p, mu, gout, dX, dU, part));
+  if (dY || dmu) {
+    const int n = B * k + 1;
+    hipLaunchKernelGGL(lpcost_finish, dim3(n), dim3(256), 0, s, (const double*)part, nblk, n, B * k, dY, dmu);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return prost_host::set_error(PROS_EHIP, "lpcost backward launch: %s", hipGetErrorString(e));
   return PROS_OK;
