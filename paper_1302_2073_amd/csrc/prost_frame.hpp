@@ -771,6 +771,20 @@ __device__ __forceinline__ void pin_tile(uint32_t (&u)[NP][K]) {
     for (int j = 0; j < K; ++j) asm volatile("" : "+v"(u[s][j]));
 }
 
+// 32- and 16-bit accesses at a byte offset (32-bit) from a base pointer.
+__device__ __forceinline__ uint32_t ld_u32(const uint16_t* base, unsigned boff) {
+  return *(const uint32_t*)((const char*)base + boff);
+}
+__device__ __forceinline__ uint32_t ld_u16(const uint16_t* base, unsigned boff) {
+  return *(const uint16_t*)((const char*)base + boff);
+}
+__device__ __forceinline__ void st_u32(uint16_t* base, unsigned boff, uint32_t v) {
+  *(uint32_t*)((char*)base + boff) = v;
+}
+__device__ __forceinline__ void st_u16(uint16_t* base, unsigned boff, uint16_t v) {
+  *(uint16_t*)((char*)base + boff) = v;
+}
+
 template <int K, int NP>
 __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int tile, FrameSmem& sm) {
   static_assert(2 * NP <= kMaxNR && NP <= 16, "row bit masks hold 32 rows");
@@ -807,16 +821,18 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
       if (split) sbits |= 1u << s;
       if (wsrc[ctx.p0 + pl]) fbits |= 1u << (2 * s);
       if (has1 && wsrc[ctx.p0 + (split ? 0 : pl + 1)]) fbits |= 2u << (2 * s);
+      // byte offsets in 32 bits from uniform plane bases: the addresses are a
+      // scalar base plus one vector offset, not 64-bit vector arithmetic
+      const unsigned b0 = 2u * (unsigned)e, b1 = 2u * (unsigned)e1;
       uint32_t xw;
-      if (al) xw = *(const uint32_t*)(xg + e);
-      else xw = (uint32_t)xg[e] | (has1 ? ((uint32_t)xg[e1] << 16) : 0u);
+      if (al) xw = ld_u32(xg, b0);
+      else xw = ld_u16(xg, b0) | (has1 ? (ld_u16(xg, b1) << 16) : 0u);
       float acc0 = bf_lo(xw), acc1 = bf_hi(xw);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         if (j < a.k) {
-          const long long o = (long long)j * a.ldU;
-          u[s][j] = al ? *(const uint32_t*)(Ug + o + e)
-                       : ((uint32_t)Ug[o + e] | (has1 ? ((uint32_t)Ug[o + e1] << 16) : 0u));
+          const uint16_t* col = Ug + (long long)j * a.ldU;
+          u[s][j] = al ? ld_u32(col, b0) : (ld_u16(col, b0) | (has1 ? (ld_u16(col, b1) << 16) : 0u));
         }
         acc0 = fmaf(-bf_lo(u[s][j]), ks.yf[j], acc0);
         acc1 = fmaf(-bf_hi(u[s][j]), ks.yf[j], acc1);
@@ -933,12 +949,12 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
           if (j < a.k) {
             const uint32_t nw = pack_bf16_rne(fmaf(coef0, ks.vf[j], bf_lo(u[s][j])),
                                               fmaf(coef1, ks.vf[j], bf_hi(u[s][j])));
-            const long long o = (long long)j * a.ldU;
+            uint16_t* col = Uw + (long long)j * a.ldU;
             if (al) {
-              *(uint32_t*)(Uw + o + e) = nw;
+              st_u32(col, 2u * (unsigned)e, nw);
             } else {
-              Uw[o + e] = (uint16_t)(nw & 0xFFFFu);
-              if (has1) Uw[o + e1] = (uint16_t)(nw >> 16);
+              st_u16(col, 2u * (unsigned)e, (uint16_t)(nw & 0xFFFFu));
+              if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(nw >> 16));
             }
           }
         if (a.labels_after_update) {
