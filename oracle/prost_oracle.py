@@ -119,6 +119,7 @@ class Params:
     i_init: int = 100
     labels_after_update: bool = True   # READING: step 3 uses U^(i+1)
     weights_from_filtered: bool = False  # READING: raw labels feed the weights
+    preprocess: bool = False     # Sec. 3.4 pre-processing (mean subtraction, scaling)
 
     @property
     def P(self):
@@ -134,15 +135,72 @@ class Params:
 
 
 @dataclasses.dataclass
+class Preproc:
+    """Statistics of the pre-processing of Sec. 3.4 (Pre- and
+    post-processing) over the frames of the initialization phase seen so
+    far: per-entry sums of x and x^2 (float64) and the frame count."""
+    s1: np.ndarray       # m, sum of x
+    s2: np.ndarray       # m, sum of x^2
+    count: int = 0
+
+    def copy(self):
+        return Preproc(self.s1.copy(), self.s2.copy(), self.count)
+
+    @property
+    def mean(self):
+        return self.s1 / self.count if self.count else np.zeros_like(self.s1)
+
+    @property
+    def m2(self):
+        """Per-entry sum of squared deviations from the per-entry mean."""
+        if not self.count:
+            return np.zeros_like(self.s1)
+        return self.s2 - self.s1 * self.s1 / self.count
+
+
+def preproc_init(m):
+    return Preproc(np.zeros(m), np.zeros(m), 0)
+
+
+def preproc_scale(pp: Preproc):
+    """Sample standard deviation over all entries of the initialization
+    frames seen so far, of the mean-subtracted values (READING: pooled
+    within-entry variance, sum of squared deviations / (m (N - 1)));
+    1 while fewer than two frames are in (or the variance is 0)."""
+    if pp.count < 2:
+        return 1.0
+    var = float(pp.m2.sum()) / (pp.s1.size * (pp.count - 1))
+    return math.sqrt(var) if var > 0.0 else 1.0
+
+
+def preprocess(pp: Preproc, x, n, i_init):
+    """Sec. 3.4 pre-processing of frame n: while n < i_init (the
+    initialization phase of the step-size rule) the frame joins the running
+    average; the frame minus the running average (this frame included) is
+    divided by the standard deviation of the initialization frames before
+    this one (READING: the pooled deviation is a reduction over the whole
+    frame, so the current frame's contribution counts from the next frame
+    on).  After the initialization phase both are frozen.  Returns
+    (x_tilde, new statistics)."""
+    x = np.asarray(x, dtype=np.float64)
+    s = preproc_scale(pp)
+    if n < i_init:
+        pp = Preproc(pp.s1 + x, pp.s2 + x * x, pp.count + 1)
+    return (x - pp.mean) / s, pp
+
+
+@dataclasses.dataclass
 class State:
     U: np.ndarray        # m x k
     y: np.ndarray        # k
     labels: np.ndarray   # P, uint8 raw labels of the previous frame
     mask: np.ndarray     # P, uint8 median-filtered mask of the previous frame
     n: int = 0           # number of frames processed
+    pre: Optional[Preproc] = None   # pre-processing statistics (when enabled)
 
     def copy(self):
-        return State(self.U.copy(), self.y.copy(), self.labels.copy(), self.mask.copy(), self.n)
+        return State(self.U.copy(), self.y.copy(), self.labels.copy(), self.mask.copy(), self.n,
+                     None if self.pre is None else self.pre.copy())
 
 
 def initial_state(U0, P):
@@ -333,6 +391,7 @@ class FrameInfo:
     zeta: float
     nu: float
     updated: bool
+    x: Optional[np.ndarray] = None   # the frame the steps ran on (pre-processed if enabled)
 
 
 def track_frame(state: State, x, prm: Params):
@@ -340,6 +399,9 @@ def track_frame(state: State, x, prm: Params):
     Step 2 takes one geodesic step on U, Step 3 labels the pixels (Sec. 3.3),
     followed by the 3x3 median (Sec. 3.4).  Returns (new_state, info)."""
     x = np.asarray(x, dtype=np.float64)
+    pre = state.pre
+    if prm.preprocess:
+        x, pre = preprocess(pre if pre is not None else preproc_init(x.size), x, state.n, prm.i_init)
     U = state.U
     src = state.mask if prm.weights_from_filtered else state.labels
     w = pixel_weights(src, prm.omega, prm.channels)
@@ -356,8 +418,8 @@ def track_frame(state: State, x, prm: Params):
     U_lab = U_new if prm.labels_after_update else U
     labels = pixel_labels(U_lab, x, y, prm.thr, prm.channels)
     mask = median3x3(labels, prm.height, prm.width)
-    new = State(U_new, y, labels, mask, state.n + 1)
-    return new, FrameInfo(rec, t, sigma, theta, zeta, nu, updated)
+    new = State(U_new, y, labels, mask, state.n + 1, pre)
+    return new, FrameInfo(rec, t, sigma, theta, zeta, nu, updated, x)
 
 
 def band_pixels(U, x, y, thr, channels, guard):

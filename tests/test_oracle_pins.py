@@ -410,3 +410,84 @@ def test_lpcost_backward_torch_autograd(form, p):
     np.testing.assert_allclose(dX, tX.grad.numpy(), rtol=1e-10, atol=1e-12)
     assert dmu == pytest.approx(float(tmu.grad), rel=1e-10)
     np.testing.assert_allclose(O.lpcost_forward(U, Y, X, w, p, mu, form), f.detach().numpy(), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Pre-processing (Sec. 3.4, Pre- and post-processing)
+# ---------------------------------------------------------------------------
+
+def _frames(seed, n, m):
+    rng = np.random.default_rng(seed)
+    base = rng.random(m)
+    return [base + 0.05 * rng.standard_normal(m) + 0.01 * t for t in range(n)]
+
+
+def test_preprocess_statistics_match_two_pass_definitions():
+    """Running average = arithmetic mean of the frames seen; the scale is the
+    pooled standard deviation of the mean-subtracted entries (numpy's
+    two-pass var with ddof = 1, averaged over entries) of the frames before
+    the current one; frame 0 maps to exactly zero."""
+    m, i_init = 50, 8
+    X = _frames(3, 6, m)
+    pp = O.preproc_init(m)
+    for n, x in enumerate(X):
+        scale_before = O.preproc_scale(pp)
+        seen = np.array(X[:n])
+        if n >= 2:
+            assert scale_before == pytest.approx(math.sqrt(np.var(seen, axis=0, ddof=1).mean()), rel=1e-12)
+        else:
+            assert scale_before == 1.0
+        xt, pp = O.preprocess(pp, x, n, i_init)
+        seen = np.array(X[:n + 1])
+        assert np.allclose(pp.mean, seen.mean(axis=0), rtol=0, atol=1e-14)
+        assert np.allclose(pp.m2, ((seen - seen.mean(axis=0)) ** 2).sum(axis=0), rtol=1e-9, atol=1e-13)
+        assert np.allclose(xt, (x - seen.mean(axis=0)) / scale_before, rtol=1e-12, atol=1e-13)
+        if n == 0:
+            assert np.array_equal(xt, np.zeros(m))
+
+
+def test_preprocess_freezes_after_initialization_phase():
+    m, i_init = 30, 4
+    X = _frames(4, 7, m)
+    pp = O.preproc_init(m)
+    for n, x in enumerate(X):
+        xt, pp2 = O.preprocess(pp, x, n, i_init)
+        if n >= i_init:
+            assert pp2.count == i_init and np.array_equal(pp2.s1, pp.s1)
+            assert np.allclose(xt, (x - pp.mean) / O.preproc_scale(pp), rtol=1e-14, atol=0)
+        pp = pp2
+
+
+def test_preprocess_is_invariant_to_affine_intensity_changes():
+    """(a x + b) for a > 0 and a constant offset per entry gives the same
+    pre-processed frames once two frames are in (mean removes b, the pooled
+    standard deviation absorbs a)."""
+    m, i_init = 40, 10
+    X = _frames(5, 5, m)
+    rng = np.random.default_rng(6)
+    b = rng.random(m)
+    a = 3.7
+    p1, p2 = O.preproc_init(m), O.preproc_init(m)
+    for n, x in enumerate(X):
+        x1, p1 = O.preprocess(p1, x, n, i_init)
+        x2, p2 = O.preprocess(p2, a * x + b, n, i_init)
+        if n >= 2:
+            assert np.allclose(x1, x2, rtol=1e-9, atol=1e-11)
+
+
+def test_tracker_with_preprocessing_on_static_scene_stays_still():
+    """A static background with noise: after pre-processing the frames are
+    zero-mean noise of unit scale, the tracker runs on them and state keeps
+    its shape; frame 0 (all zero after mean removal) changes nothing."""
+    prm = O.Params(12, 10, 1, k=2, preprocess=True, i_init=5)
+    rng = np.random.default_rng(7)
+    st = O.initial_state(V.initial_subspace(prm.m, 2, 8), prm.P)
+    bg = rng.random(prm.m)
+    st1, info = O.track_frame(st, bg + 0.01 * rng.standard_normal(prm.m), prm)
+    assert np.array_equal(info.x, np.zeros(prm.m))
+    assert np.array_equal(st1.U, st.U) and not info.updated
+    assert st1.pre.count == 1
+    for n in range(1, 8):
+        st1, info = O.track_frame(st1, bg + 0.01 * rng.standard_normal(prm.m), prm)
+    assert st1.pre.count == 5
+    assert abs(np.std(info.x) - 1.0) < 0.5
