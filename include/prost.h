@@ -88,7 +88,15 @@ typedef struct pros_params {
   int32_t reorth_every;            /* re-orthonormalise U every N frames; 0 = never */
   int32_t labels_after_update;     /* 1: labels use the updated U (default) */
   int32_t weights_from_filtered;   /* 1: weights from the median-filtered mask */
-  int32_t reserved;                /* must be 0 */
+  int32_t preprocess;              /* 1: Sec. 3.4 pre-processing. During the first
+                                      i_init frames each frame joins a running
+                                      per-entry average; every frame has that
+                                      average subtracted and is divided by the
+                                      standard deviation of the mean-subtracted
+                                      entries of the earlier initialization
+                                      frames (1 before two frames are in); both
+                                      freeze after i_init frames.  0: frames are
+                                      used as given (default). */
 } pros_params;
 
 typedef struct pros_stats {
@@ -150,6 +158,18 @@ PROS_API pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_
  * is not finite); on_device = 1: device memory read in place by the queued
  * kernels.  Asynchronous. */
 PROS_API pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device);
+
+/* Pre-processing statistics (handles created with preprocess = 1):
+ * per-entry running average and sum of squared deviations (m doubles each,
+ * entry order of a frame; NULL sets zeros) over `count` initialization
+ * frames.  Stored in float32 on the device; the entry sum of the squared
+ * deviations is recomputed here.  Synchronises.  PROS_ESTATE when the handle
+ * has no pre-processing. */
+PROS_API pros_status pros_set_preprocess(pros_handle* h, const double* mean, const double* m2, int64_t count);
+
+/* Read them back (each output may be NULL); *scale is the standard
+ * deviation the next frame will be divided by.  Synchronises. */
+PROS_API pros_status pros_get_preprocess(pros_handle* h, double* mean, double* m2, int64_t* count, double* scale);
 
 /* Copy the latest mask: filtered = 1 gives the 3x3-median mask F, 0 the raw
  * labels.  The median of a frame's labels is computed at the start of the

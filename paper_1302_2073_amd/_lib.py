@@ -37,7 +37,7 @@ class pros_params(C.Structure):
         ("t_init", C.c_double), ("t_min", C.c_double), ("i_init", C.c_int32),
         ("storage", C.c_int32), ("reorth_every", C.c_int32),
         ("labels_after_update", C.c_int32), ("weights_from_filtered", C.c_int32),
-        ("reserved", C.c_int32),
+        ("preprocess", C.c_int32),
     ]
 
 
@@ -87,6 +87,8 @@ _SIGS = {
     "pros_get_launch_info": (C.c_int, [C.c_void_p, C.POINTER(pros_launch_info)]),
     "pros_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "pros_debug_trace": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pros_set_preprocess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "pros_get_preprocess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pros_batch_init": (C.c_int, [C.POINTER(pros_params), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pros_batch_destroy": (None, [C.c_void_p]),
     "pros_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),

@@ -158,21 +158,19 @@ pros_status pros_validate(const pros_params* p) {
   if (p->reorth_every < 0) return fail(PROS_EINVAL, "reorth_every must be >= 0");
   if (p->labels_after_update != 0 && p->labels_after_update != 1) return fail(PROS_EINVAL, "labels_after_update must be 0/1");
   if (p->weights_from_filtered != 0 && p->weights_from_filtered != 1) return fail(PROS_EINVAL, "weights_from_filtered must be 0/1");
-  if (p->reserved != 0) return fail(PROS_EINVAL, "reserved must be 0");
+  if (p->preprocess != 0 && p->preprocess != 1) return fail(PROS_EINVAL, "preprocess must be 0 or 1");
   return PROS_OK;
 }
 
 void prost_host::free_handle(pros_handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->U, h->xstage, h->lab, h->mask, h->y, h->nframe, h->stats, h->part, h->sync, h->reorth_ws};
+  void* ptrs[] = {h->U, h->xstage, h->lab, h->mask, h->y, h->nframe, h->stats, h->part, h->sync, h->reorth_ws,
+                  h->pre_mean, h->pre_m2, h->pre_stat};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete h;
 }
 
-// Pick the register rows per thread NR: the largest NR whose gang fits in
-// the resident workgroups, so that the gang (and with it the cost of every
-// gang-wide exchange) is as small as possible.
 int prost_host::tile_pixels(int storage, int NR, int channels, double scale) {
   const int full = prost::kBlock * NR / channels;
   int tpw = (int)std::floor(prost::kBlock * NR * scale / channels);
@@ -196,8 +194,9 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
   int bestNR = 0, bestG = 0, bestT = 0;
   for (int NR : nrs) {
     if (force_nr > 0 && NR != force_nr) continue;
-    const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR)
-                                                  : prost::frame_kernel_f32(h->k, NR);
+    const bool pre = h->prm.preprocess != 0;
+    const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, pre)
+                                                  : prost::frame_kernel_f32(h->k, NR, pre);
     if (!f) continue;
     if (prost::kBlock * NR < h->C) continue;
     const int tpw = prost_host::tile_pixels(h->prm.storage, NR, h->C, 1.0);
@@ -272,6 +271,14 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
   INIT_TRY(hipMemsetAsync(h->nframe, 0, sizeof(long long), h->stream));
   INIT_TRY(hipMemsetAsync(h->stats, 0, sizeof(pros_stats), h->stream));
   INIT_TRY(hipMemsetAsync(h->sync, 0, 64, h->stream));
+  if (prm->preprocess) {
+    INIT_TRY(hipMalloc((void**)&h->pre_mean, sizeof(float) * (size_t)h->m));
+    INIT_TRY(hipMalloc((void**)&h->pre_m2, sizeof(float) * (size_t)h->m));
+    INIT_TRY(hipMalloc((void**)&h->pre_stat, 2 * sizeof(double)));
+    INIT_TRY(hipMemsetAsync(h->pre_mean, 0, sizeof(float) * (size_t)h->m, h->stream));
+    INIT_TRY(hipMemsetAsync(h->pre_m2, 0, sizeof(float) * (size_t)h->m, h->stream));
+    INIT_TRY(hipMemsetAsync(h->pre_stat, 0, 2 * sizeof(double), h->stream));
+  }
   // epoch-tagged exchange slots must start with tag 0 (the first exchange uses 1)
   INIT_TRY(hipMemsetAsync(h->part, 0, sizeof(double) * (2 * (size_t)h->G + prost::kExtraSlots) * prost::kSlot,
                           h->stream));
@@ -468,6 +475,10 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.sync_mode = h->sync_mode;
   a.trace = h->trace;
   a.pair_aligned = (pair_layout(h) && ((uintptr_t)x & 3u) == 0) ? 1 : 0;
+  a.pre_mean = h->pre_mean;
+  a.pre_m2 = h->pre_m2;
+  a.pre_stat = h->pre_stat;
+  a.i_init = p.i_init;
   return a;
 }
 
@@ -613,6 +624,53 @@ pros_status pros_debug_trace(pros_handle* h, long long* device_buffer) {
   if (st != PROS_OK) return st;
   h->trace = device_buffer;
   return PROS_OK;
+}
+
+pros_status pros_set_preprocess(pros_handle* h, const double* mean, const double* m2, int64_t count) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (!h->pre_mean) return fail(PROS_ESTATE, "the handle was created without pre-processing");
+  if (count < 0) return fail(PROS_EINVAL, "count must be >= 0");
+  std::vector<float> mf((size_t)h->m, 0.f), vf((size_t)h->m, 0.f);
+  double sum = 0.0;
+  for (int e = 0; e < h->m; ++e) {
+    if (mean) mf[e] = (float)mean[e];
+    if (m2) vf[e] = (float)m2[e];
+    if (!std::isfinite(mf[e]) || !std::isfinite(vf[e]) || vf[e] < 0.f)
+      return fail(PROS_EINVAL, "pre-processing entry %d is not finite or has a negative deviation sum", e);
+    sum += (double)vf[e];
+  }
+  const double stat[2] = {sum, (double)count};
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(h->pre_mean, mf.data(), sizeof(float) * (size_t)h->m, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->pre_m2, vf.data(), sizeof(float) * (size_t)h->m, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->pre_stat, stat, sizeof(stat), hipMemcpyHostToDevice));
+  return PROS_OK;
+}
+
+pros_status pros_get_preprocess(pros_handle* h, double* mean, double* m2, int64_t* count, double* scale) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (!h->pre_mean) return fail(PROS_ESTATE, "the handle was created without pre-processing");
+  st = sync_and_check(h);
+  if (st != PROS_OK && st != PROS_EBADFRAME) return st;
+  std::vector<float> buf((size_t)h->m);
+  if (mean) {
+    HIP_TRY(hipMemcpy(buf.data(), h->pre_mean, sizeof(float) * (size_t)h->m, hipMemcpyDeviceToHost));
+    for (int e = 0; e < h->m; ++e) mean[e] = buf[e];
+  }
+  if (m2) {
+    HIP_TRY(hipMemcpy(buf.data(), h->pre_m2, sizeof(float) * (size_t)h->m, hipMemcpyDeviceToHost));
+    for (int e = 0; e < h->m; ++e) m2[e] = buf[e];
+  }
+  double stat[2];
+  HIP_TRY(hipMemcpy(stat, h->pre_stat, sizeof(stat), hipMemcpyDeviceToHost));
+  if (count) *count = (int64_t)stat[1];
+  if (scale) {
+    const double var = stat[1] >= 2.0 ? stat[0] / ((double)h->m * (stat[1] - 1.0)) : 0.0;
+    *scale = var > 0.0 ? std::sqrt(var) : 1.0;
+  }
+  return st;
 }
 
 pros_status pros_reorthonormalize(pros_handle* h) {

@@ -15,25 +15,25 @@
 #include "prost_host.hpp"
 
 namespace prost {
-const void* batch_kernel_k2(int, int);
-const void* batch_kernel_k4(int, int);
-const void* batch_kernel_k5(int, int);
-const void* batch_kernel_k8(int, int);
-const void* batch_kernel_k10(int, int);
-const void* batch_kernel_k12(int, int);
-const void* batch_kernel_k15(int, int);
-const void* batch_kernel_k16(int, int);
+const void* batch_kernel_k2(int, int, bool);
+const void* batch_kernel_k4(int, int, bool);
+const void* batch_kernel_k5(int, int, bool);
+const void* batch_kernel_k8(int, int, bool);
+const void* batch_kernel_k10(int, int, bool);
+const void* batch_kernel_k12(int, int, bool);
+const void* batch_kernel_k15(int, int, bool);
+const void* batch_kernel_k16(int, int, bool);
 
-const void* batch_kernel_ptr(int bf16, int K, int budget) {
+const void* batch_kernel_ptr(int bf16, int K, int budget, bool pre) {
   switch (K) {
-    case 2: return batch_kernel_k2(bf16, budget);
-    case 4: return batch_kernel_k4(bf16, budget);
-    case 5: return batch_kernel_k5(bf16, budget);
-    case 8: return batch_kernel_k8(bf16, budget);
-    case 10: return batch_kernel_k10(bf16, budget);
-    case 12: return batch_kernel_k12(bf16, budget);
-    case 15: return batch_kernel_k15(bf16, budget);
-    case 16: return batch_kernel_k16(bf16, budget);
+    case 2: return batch_kernel_k2(bf16, budget, pre);
+    case 4: return batch_kernel_k4(bf16, budget, pre);
+    case 5: return batch_kernel_k5(bf16, budget, pre);
+    case 8: return batch_kernel_k8(bf16, budget, pre);
+    case 10: return batch_kernel_k10(bf16, budget, pre);
+    case 12: return batch_kernel_k12(bf16, budget, pre);
+    case 15: return batch_kernel_k15(bf16, budget, pre);
+    case 16: return batch_kernel_k16(bf16, budget, pre);
     default: return nullptr;
   }
 }
@@ -132,7 +132,9 @@ static pros_status build_schedule(pros_batch* b) {
 
 // (Re)create the per-stream tile configuration, descriptors and schedule.
 static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy, int sync_mode) {
-  const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget);
+  bool pre = false;
+  for (pros_handle* h : b->hs) pre = pre || (h->pre_mean != nullptr);
+  const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget, pre);
   if (!f) return fail(PROS_EUNSUPPORTED, "no batch kernel for k class %d", b->kclass);
   int occ = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0);
@@ -467,9 +469,13 @@ static size_t state_bytes(const pros_handle* h, int which) {
     case 1: return sizeof(double) * PROS_MAX_K;
     case 2: return (size_t)h->P;
     case 3: return (size_t)h->P;
-    default: return sizeof(long long);
+    case 4: return sizeof(long long);
+    case 5: return h->pre_mean ? sizeof(float) * (size_t)h->m : 0;
+    case 6: return h->pre_m2 ? sizeof(float) * (size_t)h->m : 0;
+    default: return h->pre_stat ? 2 * sizeof(double) : 0;
   }
 }
+constexpr int kStateItems = 8;   // U, y, labels, mask, frame counter, pre-processing (3)
 
 static void* state_ptr(pros_handle* h, int which) {
   switch (which) {
@@ -477,16 +483,20 @@ static void* state_ptr(pros_handle* h, int which) {
     case 1: return h->y;
     case 2: return h->lab;
     case 3: return h->mask;
-    default: return h->nframe;
+    case 4: return h->nframe;
+    case 5: return h->pre_mean;
+    case 6: return h->pre_m2;
+    default: return h->pre_stat;
   }
 }
 
 static pros_status snapshot(pros_batch* b, Snapshot& sn, bool restore) {
-  if (!restore) sn.bufs.assign((size_t)b->n * 5, nullptr);
+  if (!restore) sn.bufs.assign((size_t)b->n * kStateItems, nullptr);
   for (int s = 0; s < b->n; ++s)
-    for (int w = 0; w < 5; ++w) {
-      void*& buf = sn.bufs[(size_t)s * 5 + w];
+    for (int w = 0; w < kStateItems; ++w) {
+      void*& buf = sn.bufs[(size_t)s * kStateItems + w];
       const size_t nb = state_bytes(b->hs[s], w);
+      if (nb == 0) continue;
       hipError_t e = hipSuccess;
       if (!restore) e = hipMalloc(&buf, nb);
       if (e == hipSuccess)

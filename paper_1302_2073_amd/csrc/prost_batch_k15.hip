@@ -3,11 +3,15 @@
 #include "prost_batch.hpp"
 
 namespace prost {
-const void* batch_kernel_k15(int storage_bf16, int budget) {
+const void* batch_kernel_k15(int storage_bf16, int budget, bool pre) {
   if (storage_bf16)
-    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(64, 15)>
-                        : (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(128, 15)>;
-  return budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15)>
-                      : (const void*)&batch_kernel<float, 15, batch_nr(128, 15)>;
+    return pre ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(64, 15), true>
+                               : (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(128, 15), true>)
+               : (budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(64, 15), false>
+                               : (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(128, 15), false>);
+  return pre ? (budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15), true>
+                             : (const void*)&batch_kernel<float, 15, batch_nr(128, 15), true>)
+             : (budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15), false>
+                             : (const void*)&batch_kernel<float, 15, batch_nr(128, 15), false>);
 }
 }  // namespace prost

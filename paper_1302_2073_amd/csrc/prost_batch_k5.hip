@@ -3,11 +3,15 @@
 #include "prost_batch.hpp"
 
 namespace prost {
-const void* batch_kernel_k5(int storage_bf16, int budget) {
+const void* batch_kernel_k5(int storage_bf16, int budget, bool pre) {
   if (storage_bf16)
-    return budget == 64 ? (const void*)&batch_kernel<uint16_t, 5, batch_nr_bf16(64, 5)>
-                        : (const void*)&batch_kernel<uint16_t, 5, batch_nr_bf16(128, 5)>;
-  return budget == 64 ? (const void*)&batch_kernel<float, 5, batch_nr(64, 5)>
-                      : (const void*)&batch_kernel<float, 5, batch_nr(128, 5)>;
+    return pre ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 5, batch_nr_bf16(64, 5), true>
+                               : (const void*)&batch_kernel<uint16_t, 5, batch_nr_bf16(128, 5), true>)
+               : (budget == 64 ? (const void*)&batch_kernel<uint16_t, 5, batch_nr_bf16(64, 5), false>
+                               : (const void*)&batch_kernel<uint16_t, 5, batch_nr_bf16(128, 5), false>);
+  return pre ? (budget == 64 ? (const void*)&batch_kernel<float, 5, batch_nr(64, 5), true>
+                             : (const void*)&batch_kernel<float, 5, batch_nr(128, 5), true>)
+             : (budget == 64 ? (const void*)&batch_kernel<float, 5, batch_nr(64, 5), false>
+                             : (const void*)&batch_kernel<float, 5, batch_nr(128, 5), false>);
 }
 }  // namespace prost

@@ -48,6 +48,10 @@ struct FrameArgs {
   long long timeout;     // wall-clock ticks a barrier may wait
   long long* trace;      // optional per-tile timestamps (diagnostics), 64 per tile
   int pair_aligned;      // bfloat16: row pairs are aligned 32-bit words (U planes and frame)
+  float* pre_mean;       // pre-processing (Sec. 3.4): running average (m), NULL when off
+  float* pre_m2;         // per-entry sum of squared deviations (m)
+  double* pre_stat;      // [0] entry sum of pre_m2, [1] initialization frames accumulated
+  int i_init;            // length of the initialization phase
   int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
                          // 2: two-level tagged gather (groups of tiles with equal t % 8),
                          // 3: every workgroup reads all tagged partials
@@ -73,6 +77,10 @@ struct KSpace {
   float yf[K];
   float scal[8];    // row-pass scalars
   int flag[4];      // [0] stop CG, [1] bad frame, [2] do update
+  double pre_sum;   // pre-processing: entry sum of the deviation sums after this frame
+  float pre_inv_s;  // 1 / scale applied to this frame
+  float pre_inv_n;  // 1 / (frames accumulated including this one)
+  int pre_upd;      // this frame joins the running average
 };
 
 // Workgroup-shared scratch of one frame tile (sized for the largest k / NR).
@@ -447,12 +455,52 @@ __device__ __forceinline__ TileCtx tile_begin(const FrameArgs& a, const int tile
     ks.yf[tid] = (float)yv;
   }
   if (tid < 4) ks.flag[tid] = 0;
+  if (tid == 0) {
+    float inv_s = 1.f, inv_n = 1.f;
+    int upd = 0;
+    if (a.pre_mean) {
+      const double cnt = a.pre_stat[1];
+      const double var = cnt >= 2.0 ? a.pre_stat[0] / ((double)a.m * (cnt - 1.0)) : 0.0;
+      inv_s = var > 0.0 ? (float)(1.0 / sqrt(var)) : 1.f;
+      upd = (t.n < (long long)a.i_init) ? 1 : 0;
+      inv_n = (float)(1.0 / (cnt + 1.0));
+    }
+    ks.pre_inv_s = inv_s;
+    ks.pre_inv_n = inv_n;
+    ks.pre_upd = upd;
+    ks.pre_sum = 0.0;
+  }
   __syncthreads();
   trace_point(a, tile, 0);
   median3x3_range(a.lab, a.mask, a.W, a.H, t.p0, t.npx);
   __syncthreads();
   trace_point(a, tile, 1);
   return t;
+}
+
+// Pre-processing of one frame entry (Sec. 3.4): with upd the entry joins the
+// running average (Welford update of mean and deviation sum; the new
+// deviation sum is added to m2_sum), then the frame value minus the average
+// is scaled by inv_s.  Returns the pre-processed value.
+__device__ __forceinline__ float pre_entry(const FrameArgs& a, long long e, float x, bool upd, float inv_n,
+                                           float inv_s, float& m2_sum) {
+  float mean = a.pre_mean[e];
+  if (upd) {
+    const float d = x - mean;
+    mean = fmaf(d, inv_n, mean);
+    m2_sum += fmaf(d, x - mean, a.pre_m2[e]);
+  }
+  return (x - mean) * inv_s;
+}
+
+// Store the running average and deviation sum of one entry after an
+// accepted initialization frame (same arithmetic as pre_entry).
+__device__ __forceinline__ void pre_store(const FrameArgs& a, long long e, float x, float inv_n) {
+  const float mean = a.pre_mean[e];
+  const float d = x - mean;
+  const float mn = fmaf(d, inv_n, mean);
+  a.pre_m2[e] = fmaf(d, x - mn, a.pre_m2[e]);
+  a.pre_mean[e] = mn;
 }
 
 // PR+ conjugate direction from the reduced gradient and cost in ks.red
@@ -588,6 +636,10 @@ __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSp
       __hip_atomic_fetch_or(&a.sync[2], kErrBadFrame, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       *a.nframe = t.n + 1;
+      if (ks.pre_upd) {
+        a.pre_stat[0] = ks.pre_sum;
+        a.pre_stat[1] = a.pre_stat[1] + 1.0;
+      }
     }
     if (a.sync_mode != 0)
       __hip_atomic_store(&a.sync[3], t.ebase + (unsigned)nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -602,7 +654,7 @@ __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSp
 // ---------------------------------------------------------------------------
 // float32 storage: row q = tid + s * kBlock of the tile, K floats per row
 // ---------------------------------------------------------------------------
-template <int K, int NR>
+template <int K, int NR, bool PRE>
 __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
@@ -617,6 +669,10 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   float u[NR][K];
   float r[NR], wt[NR], cw[NR];
   int eix[NR];
+  const bool pre = PRE && a.pre_mean != nullptr;   // compiled out without PRE
+  const bool pupd = PRE && ks.pre_upd != 0;
+  const float pinv_n = ks.pre_inv_n, pinv_s = ks.pre_inv_s;
+  float m2sum = 0.f;
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     const int q = tid + s * kBlock;
@@ -632,6 +688,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       eix[s] = e;
       wt[s] = wsrc[ctx.p0 + pl] ? a.omega : 1.0f;
       float acc = xg[e];
+      if (pre) acc = pre_entry(a, e, acc, pupd, pinv_n, pinv_s, m2sum);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         if (j < a.k) u[s][j] = Ug[(long long)j * a.ldU + e];   // columns >= k stay 0
@@ -645,7 +702,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   int steps = 0, restarts = 0;
   for (int it = 0; it < a.J; ++it) {
     // phase A: gradient and cost at the current y
-    float acc[K + 1];
+    float acc[K + 1];   // g, f
 #pragma unroll
     for (int j = 0; j <= K; ++j) acc[j] = 0.f;
 #pragma unroll
@@ -685,9 +742,11 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 
   if (!bad) {
     // ---- Step 2: eta pass (a = U^T eta, ||eta||^2, final cost) ----
-    float acce[K + 2];
+    constexpr int LE = K + 2 + (PRE ? 1 : 0);   // a, ||eta||^2, f (+ pre-processing deviation sum)
+    float acce[LE];
 #pragma unroll
-    for (int j = 0; j < K + 2; ++j) acce[j] = 0.f;
+    for (int j = 0; j < LE; ++j) acce[j] = 0.f;
+    if constexpr (PRE) acce[LE - 1] = pupd ? m2sum : 0.f;
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       float phi, c;
@@ -699,7 +758,8 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, u[s][j], acce[j]);
     }
-    if (!gang_reduce<K + 2>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    if (!gang_reduce<LE>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    if (PRE && tid == 0 && pupd) ks.pre_sum = ks.red[K + 2];
     geodesic_setup<K>(a, ks, ctx.n, steps, ctx.lead);
     trace_point(a, tile, 60);
 
@@ -725,6 +785,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
             if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = fmaf(coef, ks.vf[j], u[s][j]);
           if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
         }
+        if (pre && pupd) pre_store(a, eix[s], xg[eix[s]], pinv_n);
         s_flag[q] = (fabsf(rl) >= a.delta) ? 1 : 0;
       }
     }
@@ -785,7 +846,7 @@ __device__ __forceinline__ void st_u16(uint16_t* base, unsigned boff, uint16_t v
   *(uint16_t*)((char*)base + boff) = v;
 }
 
-template <int K, int NP>
+template <int K, int NP, bool PRE>
 __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int tile, FrameSmem& sm) {
   static_assert(2 * NP <= kMaxNR && NP <= 16, "row bit masks hold 32 rows");
   KSpace<kMaxK>& ks = sm.ks;
@@ -804,6 +865,10 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   uint32_t vbits = 0;         // bit i: row i exists
   uint32_t fbits = 0;         // bit i: row i's pixel was foreground (weight omega)
   uint32_t sbits = 0;         // bit s: pair s continues in the next colour plane
+  const bool pre = PRE && a.pre_mean != nullptr;   // compiled out without PRE
+  const bool pupd = PRE && ks.pre_upd != 0;
+  const float pinv_n = ks.pre_inv_n, pinv_s = ks.pre_inv_s;
+  float m2sum = 0.f;
 #pragma unroll
   for (int s = 0; s < NP; ++s) {
     const int q0 = 2 * (tid + s * kBlock);
@@ -828,6 +893,10 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
       if (al) xw = ld_u32(xg, b0);
       else xw = ld_u16(xg, b0) | (has1 ? (ld_u16(xg, b1) << 16) : 0u);
       float acc0 = bf_lo(xw), acc1 = bf_hi(xw);
+      if (pre) {
+        acc0 = pre_entry(a, e, acc0, pupd, pinv_n, pinv_s, m2sum);
+        if (has1) acc1 = pre_entry(a, e1, acc1, pupd, pinv_n, pinv_s, m2sum);
+      }
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         if (j < a.k) {
@@ -849,7 +918,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   // ---- Step 1: CG on y ----
   int steps = 0, restarts = 0;
   for (int it = 0; it < a.J; ++it) {
-    float acc[K + 1];
+    float acc[K + 1];   // g, f
 #pragma unroll
     for (int j = 0; j <= K; ++j) acc[j] = 0.f;
     pin_tile(u);
@@ -896,9 +965,11 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   const bool bad = ks.flag[1] != 0;
 
   if (!bad) {
-    float acce[K + 2];
+    constexpr int LE = K + 2 + (PRE ? 1 : 0);   // a, ||eta||^2, f (+ pre-processing deviation sum)
+    float acce[LE];
 #pragma unroll
-    for (int j = 0; j < K + 2; ++j) acce[j] = 0.f;
+    for (int j = 0; j < LE; ++j) acce[j] = 0.f;
+    if constexpr (PRE) acce[LE - 1] = pupd ? m2sum : 0.f;
     pin_tile(u);
 #pragma unroll
     for (int s = 0; s < NP; ++s)
@@ -915,7 +986,8 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 #pragma unroll
         for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, bf_half(u[s][j], h), acce[j]);
       }
-    if (!gang_reduce<K + 2>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    if (!gang_reduce<LE>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    if (PRE && tid == 0 && pupd) ks.pre_sum = ks.red[K + 2];
     geodesic_setup<K>(a, ks, ctx.n, steps, ctx.lead);
     trace_point(a, tile, 60);
 
@@ -962,6 +1034,10 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
           rl1 = fmaf(-coef1, nu_f, rl1);
         }
       }
+      if (pre && pupd) {   // the frame joined the running average: store it
+        pre_store(a, e, bf_lo(ld_u16(xg, 2u * (unsigned)e)), pinv_n);
+        if (has1) pre_store(a, e1, bf_lo(ld_u16(xg, 2u * (unsigned)e1)), pinv_n);
+      }
       s_flag[q0] = (fabsf(rl0) >= a.delta) ? 1 : 0;
       if (has1) s_flag[q0 + 1] = (fabsf(rl1) >= a.delta) ? 1 : 0;
     }
@@ -975,20 +1051,22 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 
 // One workgroup's share of one frame in the storage type's register layout.
 // Returns false when the gang aborted.
-template <int K, int NR, typename TS>
+// PRE: the pre-processing code is compiled in (used when the stream has
+// pre-processing statistics); without it the hot path carries none of it.
+template <int K, int NR, typename TS, bool PRE>
 __device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   if constexpr (sizeof(TS) == 2) {
     static_assert(NR % 2 == 0, "bfloat16 tiles hold row pairs");
-    return frame_tile_packed<K, NR / 2>(a, tile, sm);
+    return frame_tile_packed<K, NR / 2, PRE>(a, tile, sm);
   } else {
-    return frame_tile<K, NR>(a, tile, sm);
+    return frame_tile<K, NR, PRE>(a, tile, sm);
   }
 }
 
-template <int K, int NR, typename TS>
+template <int K, int NR, typename TS, bool PRE>
 __global__ __launch_bounds__(kBlock, 2) void frame_kernel(FrameArgs a) {
   __shared__ FrameSmem sm;
-  run_tile<K, NR, TS>(a, blockIdx.x, sm);
+  run_tile<K, NR, TS, PRE>(a, blockIdx.x, sm);
 }
 
 }  // namespace prost

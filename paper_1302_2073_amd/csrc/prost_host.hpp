@@ -24,6 +24,9 @@ struct pros_handle {
   double* part = nullptr;
   unsigned* sync = nullptr;
   void* reorth_ws = nullptr;
+  float* pre_mean = nullptr;    // pre-processing: running average (m), or NULL
+  float* pre_m2 = nullptr;      // sum of squared deviations (m)
+  double* pre_stat = nullptr;   // [0] entry sum of pre_m2, [1] initialization frames accumulated
   // launch configuration
   const void* kfn = nullptr;
   int G = 0, tpw = 0, NR = 0;

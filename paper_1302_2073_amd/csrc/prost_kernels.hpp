@@ -4,7 +4,9 @@
 
 namespace prost {
 // Frame kernel for exact subspace dimension K (1..16) and NR register rows
-// per thread (1, 2, 4, 8; 16 only for K <= 8).  nullptr when not built.
-const void* frame_kernel_f32(int K, int NR);
-const void* frame_kernel_bf16(int K, int NR);
+// per thread (float32: 1, 2, 4, 8, 16 for K <= 8; bfloat16: 2, 4, 8, 16,
+// 32 for K <= 8), with or without the pre-processing code.  nullptr when
+// not built.
+const void* frame_kernel_f32(int K, int NR, bool pre);
+const void* frame_kernel_bf16(int K, int NR, bool pre);
 }  // namespace prost

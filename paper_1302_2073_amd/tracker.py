@@ -16,7 +16,7 @@ from . import _lib as L
 
 def make_params(width, height, channels=1, k=15, cg_iters=5, cost="lp", p=0.25, mu=1e-3,
                 delta=None, omega=5e-5, t_init=5e-3, t_min=1e-4, i_init=100, storage="f32",
-                reorth_every=0, labels_after_update=True, weights_from_filtered=False):
+                reorth_every=0, labels_after_update=True, weights_from_filtered=False, preprocess=False):
     """pros_params from keyword arguments (Sec. 5.1 defaults)."""
     prm = L.pros_params()
     L.check(L.lib().pros_params_default(C.byref(prm), width, height, channels))
@@ -34,6 +34,7 @@ def make_params(width, height, channels=1, k=15, cg_iters=5, cost="lp", p=0.25, 
     prm.reorth_every = int(reorth_every)
     prm.labels_after_update = int(bool(labels_after_update))
     prm.weights_from_filtered = int(bool(weights_from_filtered))
+    prm.preprocess = int(bool(preprocess))
     return prm
 
 
@@ -103,6 +104,25 @@ class Tracker:
         n = C.c_int64()
         L.check(L.lib().pros_get_state(self._h, _ptr(Ucm), _ptr(y), _ptr(lab), C.byref(n)))
         return Ucm.T.copy(), y, lab, int(n.value)
+
+    def set_preprocess(self, mean=None, m2=None, count=0):
+        """Pre-processing statistics (Sec. 3.4): running average, per-entry
+        sum of squared deviations (length m each) and the frame count."""
+        mv = None if mean is None else np.ascontiguousarray(np.asarray(mean, np.float64))
+        vv = None if m2 is None else np.ascontiguousarray(np.asarray(m2, np.float64))
+        for v in (mv, vv):
+            assert v is None or v.shape == (self.m,)
+        L.check(L.lib().pros_set_preprocess(self._h, None if mv is None else _ptr(mv),
+                                            None if vv is None else _ptr(vv), int(count)))
+
+    def get_preprocess(self):
+        """(mean, m2, count, scale): scale divides the next frame."""
+        mv = np.empty(self.m, np.float64)
+        vv = np.empty(self.m, np.float64)
+        cnt = C.c_int64()
+        sc = C.c_double()
+        L.check(L.lib().pros_get_preprocess(self._h, _ptr(mv), _ptr(vv), C.byref(cnt), C.byref(sc)))
+        return mv, vv, int(cnt.value), float(sc.value)
 
     # -- frames ----------------------------------------------------------
     def track(self, frame):

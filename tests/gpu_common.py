@@ -35,7 +35,7 @@ def tracker_kwargs(prm: O.Params, storage="f32"):
     return dict(cg_iters=prm.cg_iters, cost=prm.cost, p=prm.p, mu=prm.mu, delta=prm.delta,
                 omega=prm.omega, t_init=prm.t_init, t_min=prm.t_min, i_init=prm.i_init,
                 storage=storage, labels_after_update=prm.labels_after_update,
-                weights_from_filtered=prm.weights_from_filtered)
+                weights_from_filtered=prm.weights_from_filtered, preprocess=prm.preprocess)
 
 
 @functools.lru_cache(maxsize=8)
@@ -65,9 +65,15 @@ def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
     (from the state as rounded by the device), return a report dict."""
     trk.set_state(st.U, st.y, st.labels, st.n)
     U0, y0, l0, n0 = trk.get_state()
+    pre_dev = None
+    if prm.preprocess:   # inject the statistics and continue from their float32 copy
+        pre = st.pre if st.pre is not None else O.preproc_init(prm.m)
+        trk.set_preprocess(pre.mean, pre.m2, pre.count)
+        mean_d, m2_d, cnt_d, _ = trk.get_preprocess()
+        pre_dev = O.Preproc(mean_d * cnt_d, m2_d + mean_d * mean_d * cnt_d, cnt_d)
     # the kernel filters the injected labels at the start of the frame, as
     # the oracle's state after a frame holds the median of its labels
-    start = O.State(U0, y0, l0, O.median3x3(l0, prm.height, prm.width), n0)
+    start = O.State(U0, y0, l0, O.median3x3(l0, prm.height, prm.width), n0, pre_dev)
     exp, info = O.track_frame(start, x64, prm)
     if storage == "f32":
         trk.track(x64.astype(np.float32))
@@ -78,7 +84,8 @@ def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
     mask = trk.mask(filtered=True)
     stats = trk.stats()
     U_lab = exp.U if prm.labels_after_update else start.U
-    band = O.band_pixels(U_lab, x64, exp.y, prm.thr, prm.channels, guard)
+    xs = info.x if info.x is not None else x64      # the frame the steps ran on
+    band = O.band_pixels(U_lab, xs, exp.y, prm.thr, prm.channels, guard)
     rep = dict(
         n=n1, n_exp=exp.n,
         y_rel=float(np.linalg.norm(y1 - exp.y) / max(np.linalg.norm(exp.y), 1e-300)),
@@ -92,6 +99,12 @@ def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
         steps=(stats["cg_steps"], info.cg.iters),
         U1=U1, exp=exp, info=info, stats=stats, y1=y1, labels=l1, mask=mask, start=start,
     )
+    if prm.preprocess:
+        mean1, m21, cnt1, _ = trk.get_preprocess()
+        em, ev = exp.pre.mean, exp.pre.m2
+        rep["pre"] = dict(count=(cnt1, exp.pre.count),
+                          mean_err=float(np.max(np.abs(mean1 - em)) / max(np.max(np.abs(em)), 1e-30)),
+                          m2_rel=float(np.linalg.norm(m21 - ev) / max(np.linalg.norm(ev), 1e-30)))
     return rep
 
 
@@ -106,6 +119,11 @@ def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U):
     assert rep["lab_mismatch_outside_band"] == 0
     assert rep["mask_vs_median_of_gpu_labels"] == 0
     assert rep["f_rel"] <= TOL_F
+    if "pre" in rep:   # float32 running statistics against float64
+        say(f"  pre-processing: count {rep['pre']['count']} mean {rep['pre']['mean_err']:.1e} "
+            f"m2 {rep['pre']['m2_rel']:.1e}")
+        assert rep["pre"]["count"][0] == rep["pre"]["count"][1]
+        assert rep["pre"]["mean_err"] <= 1e-6 and rep["pre"]["m2_rel"] <= 1e-4
 
 
 def update_rounding_bound(start, x64, prm, y_final, y_dev=None):
@@ -119,6 +137,12 @@ def update_rounding_bound(start, x64, prm, y_final, y_dev=None):
       the cost's second derivative (largest at r = 0) and into v = y/||y||."""
     import math
     U = start.U
+    x_err = 0.0
+    if prm.preprocess:   # the steps run on the pre-processed frame, itself rounded to float32
+        pre = start.pre if start.pre is not None else O.preproc_init(prm.m)
+        scale = O.preproc_scale(pre)
+        x64, pre2 = O.preprocess(pre, x64, start.n, prm.i_init)
+        x_err = 2.0 ** -21 * (np.abs(x64) + np.abs(pre2.mean) / scale)
     w = O.pixel_weights(start.mask if prm.weights_from_filtered else start.labels, prm.omega, prm.channels)
     eta = O.eta_vector(U, x64, y_final, w, prm.p, prm.mu, prm.cost)
     s, sigma, v, zeta, nu = O.rank_one_svd(U, eta, y_final)
@@ -129,7 +153,7 @@ def update_rounding_bound(start, x64, prm, y_final, y_dev=None):
     term = (abs(math.cos(theta) - 1.0) * np.abs(U @ v) + abs(math.sin(theta) / zeta) * (np.abs(eta) + np.abs(U @ a)))
     bound = 2.0 ** -20 * (np.abs(U) + np.abs(term)[:, None] * np.abs(v)[None, :])
     dy = 0.0 if y_dev is None else float(np.linalg.norm(np.asarray(y_dev) - y_final))
-    dr = 2.0 ** -20 * (np.abs(x64) + np.abs(U) @ np.abs(y_final)) + np.linalg.norm(U, axis=1) * dy
+    dr = 2.0 ** -20 * (np.abs(x64) + np.abs(U) @ np.abs(y_final)) + np.linalg.norm(U, axis=1) * dy + x_err
     if prm.cost == "log":
         phi2 = 2.0 / prm.mu
     else:
