@@ -422,6 +422,43 @@ def track_frame(state: State, x, prm: Params):
     return new, FrameInfo(rec, t, sigma, theta, zeta, nu, updated, x)
 
 
+# ---------------------------------------------------------------------------
+# Segmentation quality against a ground-truth mask (the measures of Sec. 5,
+# changedetection.net: Recall, Specificity, FPR, FNR, PWC, Precision,
+# F-measure) and the threshold sweep behind its ROC curves
+# ---------------------------------------------------------------------------
+
+def quality_counts(mask, truth):
+    """(TP, FP, TN, FN) of a binary mask against the ground truth."""
+    m = np.asarray(mask).astype(bool).ravel()
+    t = np.asarray(truth).astype(bool).ravel()
+    return (int(np.sum(m & t)), int(np.sum(m & ~t)), int(np.sum(~m & ~t)), int(np.sum(~m & t)))
+
+
+def quality_metrics(tp, fp, tn, fn):
+    """The seven measures from the four counts (nan where undefined)."""
+    def div(a, b):
+        return a / b if b else float("nan")
+    recall = div(tp, tp + fn)
+    precision = div(tp, tp + fp)
+    f = div(2.0 * precision * recall, precision + recall) if tp else (0.0 if (fp or fn) else float("nan"))
+    return dict(recall=recall, specificity=div(tn, tn + fp), fpr=div(fp, fp + tn), fnr=div(fn, tp + fn),
+                pwc=div(100.0 * (fn + fp), tp + fn + fp + tn), precision=precision, fmeasure=f)
+
+
+def pixel_scores(U, x, y, channels):
+    """Per-pixel score max_c |x_c - u_c^T y| whose comparison with delta is
+    the Step 3 label (Sec. 3.4 color rule)."""
+    r = np.abs(np.asarray(x, np.float64) - U @ y)
+    return r.reshape(channels, -1).max(axis=0)
+
+
+def roc_counts(scores, truth, thresholds):
+    """Counts (TP, FP, TN, FN) for labels [score >= delta] at each threshold:
+    the delta sweep of Sec. 5 (points FPR, Recall of the ROC curve)."""
+    return [quality_counts(np.asarray(scores) >= d, truth) for d in thresholds]
+
+
 def band_pixels(U, x, y, thr, channels, guard):
     """Pixels whose largest channel residual lies within `guard` of the
     threshold: the only pixels whose label may legitimately differ between

@@ -491,3 +491,67 @@ def test_tracker_with_preprocessing_on_static_scene_stays_still():
         st1, info = O.track_frame(st1, bg + 0.01 * rng.standard_normal(prm.m), prm)
     assert st1.pre.count == 5
     assert abs(np.std(info.x) - 1.0) < 0.5
+
+
+# ---------------------------------------------------------------------------
+# Segmentation quality measures (Sec. 5) and the delta sweep
+# ---------------------------------------------------------------------------
+
+def test_quality_measures_hand_example():
+    mask = np.array([1, 1, 0, 0, 1, 0, 0, 0], np.uint8)
+    truth = np.array([1, 0, 0, 1, 1, 0, 0, 0], np.uint8)
+    tp, fp, tn, fn = O.quality_counts(mask, truth)
+    assert (tp, fp, tn, fn) == (2, 1, 4, 1)
+    q = O.quality_metrics(tp, fp, tn, fn)
+    assert q["recall"] == pytest.approx(2 / 3) and q["precision"] == pytest.approx(2 / 3)
+    assert q["specificity"] == pytest.approx(4 / 5) and q["fpr"] == pytest.approx(1 / 5)
+    assert q["fnr"] == pytest.approx(1 / 3) and q["pwc"] == pytest.approx(100 * 2 / 8)
+    assert q["fmeasure"] == pytest.approx(2 / 3)
+
+
+def test_quality_measures_match_scikit_learn():
+    from sklearn.metrics import confusion_matrix, f1_score, precision_score, recall_score
+    rng = np.random.default_rng(11)
+    truth = rng.random(5000) < 0.1
+    mask = truth ^ (rng.random(5000) < 0.05)
+    tp, fp, tn, fn = O.quality_counts(mask, truth)
+    tn_, fp_, fn_, tp_ = confusion_matrix(truth, mask).ravel()
+    assert (tp, fp, tn, fn) == (tp_, fp_, tn_, fn_)
+    q = O.quality_metrics(tp, fp, tn, fn)
+    assert q["recall"] == pytest.approx(recall_score(truth, mask))
+    assert q["precision"] == pytest.approx(precision_score(truth, mask))
+    assert q["fmeasure"] == pytest.approx(f1_score(truth, mask))
+    assert q["specificity"] + q["fpr"] == pytest.approx(1.0) and q["recall"] + q["fnr"] == pytest.approx(1.0)
+
+
+def test_roc_sweep_matches_scikit_learn_curve():
+    from sklearn.metrics import roc_curve
+    rng = np.random.default_rng(12)
+    truth = rng.random(3000) < 0.2
+    scores = np.abs(rng.standard_normal(3000)) * (1 + 2 * truth)
+    fpr, tpr, thr = roc_curve(truth, scores, drop_intermediate=False)
+    sel = thr[1:60:7]
+    for d, (tp, fp, tn, fn) in zip(sel, O.roc_counts(scores, truth, sel)):
+        i = int(np.where(thr == d)[0][0])
+        assert fp / (fp + tn) == pytest.approx(fpr[i]) and tp / (tp + fn) == pytest.approx(tpr[i])
+
+
+def test_pixel_scores_reproduce_the_step3_labels():
+    prm = O.Params(9, 7, 3, k=2, mu=1e-3)
+    rng = np.random.default_rng(13)
+    U = V.random_orthonormal(prm.m, 2, rng)
+    y = rng.standard_normal(2)
+    x = U @ y + 0.05 * rng.standard_normal(prm.m)
+    lab = O.pixel_labels(U, x, y, prm.thr, 3)
+    assert np.array_equal(lab, (O.pixel_scores(U, x, y, 3) >= prm.thr).astype(np.uint8))
+
+
+def test_paper_table_rows_are_consistent_measures():
+    """The per-category rows printed in Sec. 5 satisfy Specificity = 1 - FPR
+    and FNR = 1 - Recall to the printed precision (tests/golden fixture)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_quality_table.json")
+    d = json.load(open(path))
+    for row in d["rows"]:
+        assert row["specificity"] + row["fpr"] == pytest.approx(1.0, abs=2e-4)
+        if row["category"] not in d["inconsistent_fnr"]:
+            assert row["recall"] + row["fnr"] == pytest.approx(1.0, abs=2e-3)
