@@ -159,6 +159,31 @@ PROS_API pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_
  * kernels.  Asynchronous. */
 PROS_API pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device);
 
+/* Segmentation quality (the measures of Sec. 5 follow from these counts:
+ * Recall = TP/(TP+FN), Specificity = TN/(TN+FP), FPR = FP/(FP+TN),
+ * FNR = FN/(TP+FN), PWC = 100 (FN+FP)/(TP+FN+FP+TN), Precision =
+ * TP/(TP+FP), F-measure = 2 Pr Re/(Pr+Re)).
+ *
+ * pros_set_score_output: the frame kernel also writes |r'_e| (the Step 3
+ * residual whose per-pixel maximum over channels is compared with delta)
+ * for every entry to `device_scores` (m floats, caller-owned, channel-major
+ * like a frame; NULL stops it).  Synchronises.
+ *
+ * pros_quality_counts: counts[0..3] = (TP, FP, TN, FN) of the latest mask
+ * (filtered = 1) or raw labels (0) against `truth` (P bytes, nonzero =
+ * foreground; device pointer when on_device, else host).  Synchronises.
+ *
+ * pros_roc_counts: the delta sweep of Sec. 5 without re-running the
+ * tracker: for each of T <= 256 thresholds (host array),
+ * counts[4 i .. 4 i + 3] = (TP, FP, TN, FN) of the labels
+ * [max_c scores[c P + p] >= thresholds[i]] against truth (device arrays of
+ * C P floats and P bytes).  Queued on hip_stream, then synchronises. */
+PROS_API pros_status pros_set_score_output(pros_handle* h, float* device_scores);
+PROS_API pros_status pros_quality_counts(pros_handle* h, const uint8_t* truth, int32_t on_device, int32_t filtered,
+                                         int64_t* counts);
+PROS_API pros_status pros_roc_counts(const float* scores, const uint8_t* truth, int32_t P, int32_t C,
+                                     const float* thresholds, int32_t T, int64_t* counts, void* hip_stream);
+
 /* Pre-processing statistics (handles created with preprocess = 1):
  * per-entry running average and sum of squared deviations (m doubles each,
  * entry order of a frame; NULL sets zeros) over `count` initialization

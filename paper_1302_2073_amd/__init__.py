@@ -7,11 +7,11 @@ the C ABI of include/prost.h; this package only marshals arguments.
 """
 from . import _lib  # noqa: F401
 
-__all__ = ["Tracker", "make_params"]
+__all__ = ["Tracker", "make_params", "roc_counts"]
 
 
 def __getattr__(name):
-    if name in ("Tracker", "make_params", "bf16_bits", "bf16_to_f64"):
+    if name in ("Tracker", "make_params", "bf16_bits", "bf16_to_f64", "roc_counts"):
         from . import tracker
         return getattr(tracker, name)
     raise AttributeError(name)

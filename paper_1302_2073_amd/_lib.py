@@ -88,6 +88,10 @@ _SIGS = {
     "pros_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "pros_debug_trace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pros_set_preprocess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "pros_set_score_output": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pros_quality_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "pros_roc_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                  C.c_void_p, C.c_void_p]),
     "pros_get_preprocess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pros_batch_init": (C.c_int, [C.POINTER(pros_params), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pros_batch_destroy": (None, [C.c_void_p]),

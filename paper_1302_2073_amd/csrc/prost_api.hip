@@ -194,9 +194,9 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
   int bestNR = 0, bestG = 0, bestT = 0;
   for (int NR : nrs) {
     if (force_nr > 0 && NR != force_nr) continue;
-    const bool pre = h->prm.preprocess != 0;
-    const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, pre)
-                                                  : prost::frame_kernel_f32(h->k, NR, pre);
+    const bool ext = h->prm.preprocess != 0 || h->score != nullptr;
+    const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, ext)
+                                                  : prost::frame_kernel_f32(h->k, NR, ext);
     if (!f) continue;
     if (prost::kBlock * NR < h->C) continue;
     const int tpw = prost_host::tile_pixels(h->prm.storage, NR, h->C, 1.0);
@@ -479,6 +479,7 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.pre_m2 = h->pre_m2;
   a.pre_stat = h->pre_stat;
   a.i_init = p.i_init;
+  a.score = h->score;
   return a;
 }
 
@@ -617,6 +618,17 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   }
   h->sync_mode = sync_mode;
   return prost_host::reset_exchange(h);
+}
+
+pros_status pros_set_score_output(pros_handle* h, float* device_scores) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  float* old = h->score;
+  h->score = device_scores;
+  st = choose_launch(h, h->NR);   // same tile, kernel with or without the optional features
+  if (st != PROS_OK) h->score = old;
+  return st;
 }
 
 pros_status pros_debug_trace(pros_handle* h, long long* device_buffer) {

@@ -24,16 +24,16 @@ const void* batch_kernel_k12(int, int, bool);
 const void* batch_kernel_k15(int, int, bool);
 const void* batch_kernel_k16(int, int, bool);
 
-const void* batch_kernel_ptr(int bf16, int K, int budget, bool pre) {
+const void* batch_kernel_ptr(int bf16, int K, int budget, bool ext) {
   switch (K) {
-    case 2: return batch_kernel_k2(bf16, budget, pre);
-    case 4: return batch_kernel_k4(bf16, budget, pre);
-    case 5: return batch_kernel_k5(bf16, budget, pre);
-    case 8: return batch_kernel_k8(bf16, budget, pre);
-    case 10: return batch_kernel_k10(bf16, budget, pre);
-    case 12: return batch_kernel_k12(bf16, budget, pre);
-    case 15: return batch_kernel_k15(bf16, budget, pre);
-    case 16: return batch_kernel_k16(bf16, budget, pre);
+    case 2: return batch_kernel_k2(bf16, budget, ext);
+    case 4: return batch_kernel_k4(bf16, budget, ext);
+    case 5: return batch_kernel_k5(bf16, budget, ext);
+    case 8: return batch_kernel_k8(bf16, budget, ext);
+    case 10: return batch_kernel_k10(bf16, budget, ext);
+    case 12: return batch_kernel_k12(bf16, budget, ext);
+    case 15: return batch_kernel_k15(bf16, budget, ext);
+    case 16: return batch_kernel_k16(bf16, budget, ext);
     default: return nullptr;
   }
 }
@@ -132,9 +132,9 @@ static pros_status build_schedule(pros_batch* b) {
 
 // (Re)create the per-stream tile configuration, descriptors and schedule.
 static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy, int sync_mode) {
-  bool pre = false;
-  for (pros_handle* h : b->hs) pre = pre || (h->pre_mean != nullptr);
-  const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget, pre);
+  bool ext = false;
+  for (pros_handle* h : b->hs) ext = ext || (h->pre_mean != nullptr);
+  const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget, ext);
   if (!f) return fail(PROS_EUNSUPPORTED, "no batch kernel for k class %d", b->kclass);
   int occ = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0);

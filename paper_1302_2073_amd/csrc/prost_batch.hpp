@@ -57,7 +57,7 @@ __device__ __forceinline__ FrameArgs load_uniform(const FrameArgs* __restrict__ 
   return a;
 }
 
-template <typename TS, int K, int NR, bool PRE>
+template <typename TS, int K, int NR, bool EXT>
 __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __restrict__ descs,
                                                        const BatchItem* __restrict__ items, int rounds) {
   __shared__ FrameSmem sm;
@@ -65,12 +65,12 @@ __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __res
     const BatchItem it = items[(size_t)r * gridDim.x + blockIdx.x];
     if (it.stream < 0) continue;
     const FrameArgs a = load_uniform(descs + it.stream);
-    if (!run_tile<K, NR, TS, PRE>(a, it.tile, sm)) return;
+    if (!run_tile<K, NR, TS, EXT>(a, it.tile, sm)) return;
   }
 }
 
-// Kernel for (storage, class K, budget, pre-processing compiled in);
+// Kernel for (storage, class K, budget, optional features compiled in);
 // nullptr if not built.
-const void* batch_kernel_ptr(int storage_bf16, int K, int budget, bool pre);
+const void* batch_kernel_ptr(int storage_bf16, int K, int budget, bool ext);
 
 }  // namespace prost

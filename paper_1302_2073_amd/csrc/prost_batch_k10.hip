@@ -3,13 +3,13 @@
 #include "prost_batch.hpp"
 
 namespace prost {
-const void* batch_kernel_k10(int storage_bf16, int budget, bool pre) {
+const void* batch_kernel_k10(int storage_bf16, int budget, bool ext) {
   if (storage_bf16)
-    return pre ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 10, batch_nr_bf16(64, 10), true>
+    return ext ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 10, batch_nr_bf16(64, 10), true>
                                : (const void*)&batch_kernel<uint16_t, 10, batch_nr_bf16(128, 10), true>)
                : (budget == 64 ? (const void*)&batch_kernel<uint16_t, 10, batch_nr_bf16(64, 10), false>
                                : (const void*)&batch_kernel<uint16_t, 10, batch_nr_bf16(128, 10), false>);
-  return pre ? (budget == 64 ? (const void*)&batch_kernel<float, 10, batch_nr(64, 10), true>
+  return ext ? (budget == 64 ? (const void*)&batch_kernel<float, 10, batch_nr(64, 10), true>
                              : (const void*)&batch_kernel<float, 10, batch_nr(128, 10), true>)
              : (budget == 64 ? (const void*)&batch_kernel<float, 10, batch_nr(64, 10), false>
                              : (const void*)&batch_kernel<float, 10, batch_nr(128, 10), false>);

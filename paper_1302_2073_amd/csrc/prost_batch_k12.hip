@@ -3,13 +3,13 @@
 #include "prost_batch.hpp"
 
 namespace prost {
-const void* batch_kernel_k12(int storage_bf16, int budget, bool pre) {
+const void* batch_kernel_k12(int storage_bf16, int budget, bool ext) {
   if (storage_bf16)
-    return pre ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 12, batch_nr_bf16(64, 12), true>
+    return ext ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 12, batch_nr_bf16(64, 12), true>
                                : (const void*)&batch_kernel<uint16_t, 12, batch_nr_bf16(128, 12), true>)
                : (budget == 64 ? (const void*)&batch_kernel<uint16_t, 12, batch_nr_bf16(64, 12), false>
                                : (const void*)&batch_kernel<uint16_t, 12, batch_nr_bf16(128, 12), false>);
-  return pre ? (budget == 64 ? (const void*)&batch_kernel<float, 12, batch_nr(64, 12), true>
+  return ext ? (budget == 64 ? (const void*)&batch_kernel<float, 12, batch_nr(64, 12), true>
                              : (const void*)&batch_kernel<float, 12, batch_nr(128, 12), true>)
              : (budget == 64 ? (const void*)&batch_kernel<float, 12, batch_nr(64, 12), false>
                              : (const void*)&batch_kernel<float, 12, batch_nr(128, 12), false>);

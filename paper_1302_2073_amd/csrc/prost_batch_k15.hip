@@ -3,13 +3,13 @@
 #include "prost_batch.hpp"
 
 namespace prost {
-const void* batch_kernel_k15(int storage_bf16, int budget, bool pre) {
+const void* batch_kernel_k15(int storage_bf16, int budget, bool ext) {
   if (storage_bf16)
-    return pre ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(64, 15), true>
+    return ext ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(64, 15), true>
                                : (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(128, 15), true>)
                : (budget == 64 ? (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(64, 15), false>
                                : (const void*)&batch_kernel<uint16_t, 15, batch_nr_bf16(128, 15), false>);
-  return pre ? (budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15), true>
+  return ext ? (budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15), true>
                              : (const void*)&batch_kernel<float, 15, batch_nr(128, 15), true>)
              : (budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15), false>
                              : (const void*)&batch_kernel<float, 15, batch_nr(128, 15), false>);

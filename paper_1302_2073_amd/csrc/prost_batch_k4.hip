@@ -3,13 +3,13 @@
 #include "prost_batch.hpp"
 
 namespace prost {
-const void* batch_kernel_k4(int storage_bf16, int budget, bool pre) {
+const void* batch_kernel_k4(int storage_bf16, int budget, bool ext) {
   if (storage_bf16)
-    return pre ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 4, batch_nr_bf16(64, 4), true>
+    return ext ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 4, batch_nr_bf16(64, 4), true>
                                : (const void*)&batch_kernel<uint16_t, 4, batch_nr_bf16(128, 4), true>)
                : (budget == 64 ? (const void*)&batch_kernel<uint16_t, 4, batch_nr_bf16(64, 4), false>
                                : (const void*)&batch_kernel<uint16_t, 4, batch_nr_bf16(128, 4), false>);
-  return pre ? (budget == 64 ? (const void*)&batch_kernel<float, 4, batch_nr(64, 4), true>
+  return ext ? (budget == 64 ? (const void*)&batch_kernel<float, 4, batch_nr(64, 4), true>
                              : (const void*)&batch_kernel<float, 4, batch_nr(128, 4), true>)
              : (budget == 64 ? (const void*)&batch_kernel<float, 4, batch_nr(64, 4), false>
                              : (const void*)&batch_kernel<float, 4, batch_nr(128, 4), false>);

@@ -3,13 +3,13 @@
 #include "prost_batch.hpp"
 
 namespace prost {
-const void* batch_kernel_k8(int storage_bf16, int budget, bool pre) {
+const void* batch_kernel_k8(int storage_bf16, int budget, bool ext) {
   if (storage_bf16)
-    return pre ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 8, batch_nr_bf16(64, 8), true>
+    return ext ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 8, batch_nr_bf16(64, 8), true>
                                : (const void*)&batch_kernel<uint16_t, 8, batch_nr_bf16(128, 8), true>)
                : (budget == 64 ? (const void*)&batch_kernel<uint16_t, 8, batch_nr_bf16(64, 8), false>
                                : (const void*)&batch_kernel<uint16_t, 8, batch_nr_bf16(128, 8), false>);
-  return pre ? (budget == 64 ? (const void*)&batch_kernel<float, 8, batch_nr(64, 8), true>
+  return ext ? (budget == 64 ? (const void*)&batch_kernel<float, 8, batch_nr(64, 8), true>
                              : (const void*)&batch_kernel<float, 8, batch_nr(128, 8), true>)
              : (budget == 64 ? (const void*)&batch_kernel<float, 8, batch_nr(64, 8), false>
                              : (const void*)&batch_kernel<float, 8, batch_nr(128, 8), false>);

@@ -52,6 +52,7 @@ struct FrameArgs {
   float* pre_m2;         // per-entry sum of squared deviations (m)
   double* pre_stat;      // [0] entry sum of pre_m2, [1] initialization frames accumulated
   int i_init;            // length of the initialization phase
+  float* score;          // optional: |r'| of every entry after Step 3 (m floats), or NULL
   int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
                          // 2: two-level tagged gather (groups of tiles with equal t % 8),
                          // 3: every workgroup reads all tagged partials
@@ -654,7 +655,7 @@ __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSp
 // ---------------------------------------------------------------------------
 // float32 storage: row q = tid + s * kBlock of the tile, K floats per row
 // ---------------------------------------------------------------------------
-template <int K, int NR, bool PRE>
+template <int K, int NR, bool EXT>
 __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
@@ -669,8 +670,8 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   float u[NR][K];
   float r[NR], wt[NR], cw[NR];
   int eix[NR];
-  const bool pre = PRE && a.pre_mean != nullptr;   // compiled out without PRE
-  const bool pupd = PRE && ks.pre_upd != 0;
+  const bool pre = EXT && a.pre_mean != nullptr;   // compiled out without EXT
+  const bool pupd = EXT && ks.pre_upd != 0;
   const float pinv_n = ks.pre_inv_n, pinv_s = ks.pre_inv_s;
   float m2sum = 0.f;
 #pragma unroll
@@ -742,11 +743,11 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 
   if (!bad) {
     // ---- Step 2: eta pass (a = U^T eta, ||eta||^2, final cost) ----
-    constexpr int LE = K + 2 + (PRE ? 1 : 0);   // a, ||eta||^2, f (+ pre-processing deviation sum)
+    constexpr int LE = K + 2 + (EXT ? 1 : 0);   // a, ||eta||^2, f (+ pre-processing deviation sum)
     float acce[LE];
 #pragma unroll
     for (int j = 0; j < LE; ++j) acce[j] = 0.f;
-    if constexpr (PRE) acce[LE - 1] = pupd ? m2sum : 0.f;
+    if constexpr (EXT) acce[LE - 1] = pupd ? m2sum : 0.f;
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       float phi, c;
@@ -759,7 +760,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, u[s][j], acce[j]);
     }
     if (!gang_reduce<LE>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
-    if (PRE && tid == 0 && pupd) ks.pre_sum = ks.red[K + 2];
+    if (EXT && tid == 0 && pupd) ks.pre_sum = ks.red[K + 2];
     geodesic_setup<K>(a, ks, ctx.n, steps, ctx.lead);
     trace_point(a, tile, 60);
 
@@ -786,6 +787,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
           if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
         }
         if (pre && pupd) pre_store(a, eix[s], xg[eix[s]], pinv_n);
+        if (EXT && a.score) a.score[eix[s]] = fabsf(rl);
         s_flag[q] = (fabsf(rl) >= a.delta) ? 1 : 0;
       }
     }
@@ -846,7 +848,7 @@ __device__ __forceinline__ void st_u16(uint16_t* base, unsigned boff, uint16_t v
   *(uint16_t*)((char*)base + boff) = v;
 }
 
-template <int K, int NP, bool PRE>
+template <int K, int NP, bool EXT>
 __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int tile, FrameSmem& sm) {
   static_assert(2 * NP <= kMaxNR && NP <= 16, "row bit masks hold 32 rows");
   KSpace<kMaxK>& ks = sm.ks;
@@ -865,8 +867,8 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   uint32_t vbits = 0;         // bit i: row i exists
   uint32_t fbits = 0;         // bit i: row i's pixel was foreground (weight omega)
   uint32_t sbits = 0;         // bit s: pair s continues in the next colour plane
-  const bool pre = PRE && a.pre_mean != nullptr;   // compiled out without PRE
-  const bool pupd = PRE && ks.pre_upd != 0;
+  const bool pre = EXT && a.pre_mean != nullptr;   // compiled out without EXT
+  const bool pupd = EXT && ks.pre_upd != 0;
   const float pinv_n = ks.pre_inv_n, pinv_s = ks.pre_inv_s;
   float m2sum = 0.f;
 #pragma unroll
@@ -965,11 +967,11 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   const bool bad = ks.flag[1] != 0;
 
   if (!bad) {
-    constexpr int LE = K + 2 + (PRE ? 1 : 0);   // a, ||eta||^2, f (+ pre-processing deviation sum)
+    constexpr int LE = K + 2 + (EXT ? 1 : 0);   // a, ||eta||^2, f (+ pre-processing deviation sum)
     float acce[LE];
 #pragma unroll
     for (int j = 0; j < LE; ++j) acce[j] = 0.f;
-    if constexpr (PRE) acce[LE - 1] = pupd ? m2sum : 0.f;
+    if constexpr (EXT) acce[LE - 1] = pupd ? m2sum : 0.f;
     pin_tile(u);
 #pragma unroll
     for (int s = 0; s < NP; ++s)
@@ -987,7 +989,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
         for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, bf_half(u[s][j], h), acce[j]);
       }
     if (!gang_reduce<LE>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
-    if (PRE && tid == 0 && pupd) ks.pre_sum = ks.red[K + 2];
+    if (EXT && tid == 0 && pupd) ks.pre_sum = ks.red[K + 2];
     geodesic_setup<K>(a, ks, ctx.n, steps, ctx.lead);
     trace_point(a, tile, 60);
 
@@ -1038,6 +1040,10 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
         pre_store(a, e, bf_lo(ld_u16(xg, 2u * (unsigned)e)), pinv_n);
         if (has1) pre_store(a, e1, bf_lo(ld_u16(xg, 2u * (unsigned)e1)), pinv_n);
       }
+      if (EXT && a.score) {
+        a.score[e] = fabsf(rl0);
+        if (has1) a.score[e1] = fabsf(rl1);
+      }
       s_flag[q0] = (fabsf(rl0) >= a.delta) ? 1 : 0;
       if (has1) s_flag[q0 + 1] = (fabsf(rl1) >= a.delta) ? 1 : 0;
     }
@@ -1051,22 +1057,23 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 
 // One workgroup's share of one frame in the storage type's register layout.
 // Returns false when the gang aborted.
-// PRE: the pre-processing code is compiled in (used when the stream has
-// pre-processing statistics); without it the hot path carries none of it.
-template <int K, int NR, typename TS, bool PRE>
+// EXT: the optional features are compiled in (pre-processing when the
+// stream has its statistics, per-entry label scores when a score buffer is
+// given); without it the hot path carries none of their code.
+template <int K, int NR, typename TS, bool EXT>
 __device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   if constexpr (sizeof(TS) == 2) {
     static_assert(NR % 2 == 0, "bfloat16 tiles hold row pairs");
-    return frame_tile_packed<K, NR / 2, PRE>(a, tile, sm);
+    return frame_tile_packed<K, NR / 2, EXT>(a, tile, sm);
   } else {
-    return frame_tile<K, NR, PRE>(a, tile, sm);
+    return frame_tile<K, NR, EXT>(a, tile, sm);
   }
 }
 
-template <int K, int NR, typename TS, bool PRE>
+template <int K, int NR, typename TS, bool EXT>
 __global__ __launch_bounds__(kBlock, 2) void frame_kernel(FrameArgs a) {
   __shared__ FrameSmem sm;
-  run_tile<K, NR, TS, PRE>(a, blockIdx.x, sm);
+  run_tile<K, NR, TS, EXT>(a, blockIdx.x, sm);
 }
 
 }  // namespace prost

@@ -1,5 +1,5 @@
 // Instantiation helper: PROST_FRAME_GROUP(name, TS, K0) defines
-// name(K, NR, pre) returning the frame kernel for K in [K0, K0+3], or nullptr
+// name(K, NR, ext) returning the frame kernel for K in [K0, K0+3], or nullptr
 // for a row count that is not built.  float32 tiles: NR in {1, 2, 4, 8}
 // (16 for K <= 8); bfloat16 tiles hold row pairs: NR in {2, 4, 8, 16}
 // (32 for K <= 8).
@@ -8,25 +8,25 @@
 
 namespace prost {
 
-template <typename TS, int KK, bool PRE>
+template <typename TS, int KK, bool EXT>
 const void* frame_kernel_nr(int NR) {
   constexpr int KS = (KK <= 8) ? KK : 1;   // widest tile only for small K
   if constexpr (sizeof(TS) == 2) {
     switch (NR) {
-      case 2: return (const void*)&frame_kernel<KK, 2, TS, PRE>;
-      case 4: return (const void*)&frame_kernel<KK, 4, TS, PRE>;
-      case 8: return (const void*)&frame_kernel<KK, 8, TS, PRE>;
-      case 16: return (const void*)&frame_kernel<KK, 16, TS, PRE>;
-      case 32: return (KK <= 8) ? (const void*)&frame_kernel<KS, 32, TS, PRE> : nullptr;
+      case 2: return (const void*)&frame_kernel<KK, 2, TS, EXT>;
+      case 4: return (const void*)&frame_kernel<KK, 4, TS, EXT>;
+      case 8: return (const void*)&frame_kernel<KK, 8, TS, EXT>;
+      case 16: return (const void*)&frame_kernel<KK, 16, TS, EXT>;
+      case 32: return (KK <= 8) ? (const void*)&frame_kernel<KS, 32, TS, EXT> : nullptr;
       default: return nullptr;
     }
   } else {
     switch (NR) {
-      case 1: return (const void*)&frame_kernel<KK, 1, TS, PRE>;
-      case 2: return (const void*)&frame_kernel<KK, 2, TS, PRE>;
-      case 4: return (const void*)&frame_kernel<KK, 4, TS, PRE>;
-      case 8: return (const void*)&frame_kernel<KK, 8, TS, PRE>;
-      case 16: return (KK <= 8) ? (const void*)&frame_kernel<KS, 16, TS, PRE> : nullptr;
+      case 1: return (const void*)&frame_kernel<KK, 1, TS, EXT>;
+      case 2: return (const void*)&frame_kernel<KK, 2, TS, EXT>;
+      case 4: return (const void*)&frame_kernel<KK, 4, TS, EXT>;
+      case 8: return (const void*)&frame_kernel<KK, 8, TS, EXT>;
+      case 16: return (KK <= 8) ? (const void*)&frame_kernel<KS, 16, TS, EXT> : nullptr;
       default: return nullptr;
     }
   }
@@ -35,12 +35,12 @@ const void* frame_kernel_nr(int NR) {
 }  // namespace prost
 
 #define PROST_FRAME_GROUP(name, TS, K0)                                                   \
-  const void* name(int K, int NR, bool pre) {                                             \
+  const void* name(int K, int NR, bool ext) {                                             \
     switch (K) {                                                                          \
-      case K0 + 0: return pre ? frame_kernel_nr<TS, K0 + 0, true>(NR) : frame_kernel_nr<TS, K0 + 0, false>(NR); \
-      case K0 + 1: return pre ? frame_kernel_nr<TS, K0 + 1, true>(NR) : frame_kernel_nr<TS, K0 + 1, false>(NR); \
-      case K0 + 2: return pre ? frame_kernel_nr<TS, K0 + 2, true>(NR) : frame_kernel_nr<TS, K0 + 2, false>(NR); \
-      case K0 + 3: return pre ? frame_kernel_nr<TS, K0 + 3, true>(NR) : frame_kernel_nr<TS, K0 + 3, false>(NR); \
+      case K0 + 0: return ext ? frame_kernel_nr<TS, K0 + 0, true>(NR) : frame_kernel_nr<TS, K0 + 0, false>(NR); \
+      case K0 + 1: return ext ? frame_kernel_nr<TS, K0 + 1, true>(NR) : frame_kernel_nr<TS, K0 + 1, false>(NR); \
+      case K0 + 2: return ext ? frame_kernel_nr<TS, K0 + 2, true>(NR) : frame_kernel_nr<TS, K0 + 2, false>(NR); \
+      case K0 + 3: return ext ? frame_kernel_nr<TS, K0 + 3, true>(NR) : frame_kernel_nr<TS, K0 + 3, false>(NR); \
       default: return nullptr;                                                            \
     }                                                                                     \
   }

@@ -124,6 +124,31 @@ class Tracker:
         L.check(L.lib().pros_get_preprocess(self._h, _ptr(mv), _ptr(vv), C.byref(cnt), C.byref(sc)))
         return mv, vv, int(cnt.value), float(sc.value)
 
+    def set_score_output(self, scores=None):
+        """Have every frame write |r'| of each entry (Step 3 residual) into
+        `scores`, a float32 device tensor of m entries (None stops it)."""
+        if scores is not None:
+            import torch
+            assert scores.is_cuda and scores.dtype == torch.float32 and scores.is_contiguous()
+            assert scores.numel() == self.m
+            self._scores = scores           # keep the buffer alive while registered
+        else:
+            self._scores = None
+        L.check(L.lib().pros_set_score_output(self._h, None if scores is None else _ptr(scores)))
+
+    def quality_counts(self, truth, filtered=True):
+        """(TP, FP, TN, FN) of the latest mask (or raw labels) against a
+        ground-truth mask of P pixels (host array or device uint8 tensor)."""
+        out = np.zeros(4, np.int64)
+        if isinstance(truth, np.ndarray):
+            t = np.ascontiguousarray(truth.astype(np.uint8).ravel())
+            assert t.size == self.P
+            L.check(L.lib().pros_quality_counts(self._h, _ptr(t), 0, int(bool(filtered)), _ptr(out)))
+        else:
+            assert truth.is_cuda and truth.numel() == self.P and truth.is_contiguous()
+            L.check(L.lib().pros_quality_counts(self._h, _ptr(truth), 1, int(bool(filtered)), _ptr(out)))
+        return tuple(int(v) for v in out)
+
     # -- frames ----------------------------------------------------------
     def track(self, frame):
         """Queue one frame: a device tensor of the storage dtype (read in
@@ -335,3 +360,20 @@ class BatchTracker:
                 json.dump(db, f, indent=1)
             os.replace(tmp, path)
         return rec
+
+
+def roc_counts(scores, truth, channels, thresholds, stream=None):
+    """Counts (TP, FP, TN, FN) per threshold of the labels
+    [max_c scores[c P + p] >= threshold] against truth (device tensors:
+    float32 scores of C P entries, uint8 truth of P pixels)."""
+    import torch
+    assert scores.is_cuda and scores.dtype == torch.float32 and scores.is_contiguous()
+    assert truth.is_cuda and truth.dtype == torch.uint8 and truth.is_contiguous()
+    P = truth.numel()
+    assert scores.numel() == channels * P
+    thr = np.ascontiguousarray(np.asarray(thresholds, np.float32))
+    out = np.zeros((thr.size, 4), np.int64)
+    L.check(L.lib().pros_roc_counts(_ptr(scores), _ptr(truth), int(P), int(channels), _ptr(thr), int(thr.size),
+                                    _ptr(out), _stream_handle(stream)))
+    return out
+
