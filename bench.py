@@ -264,6 +264,47 @@ def run_lpcost(steps, warmup):
                 spread_ms=[round(lo, 3), round(hi, 3)])
 
 
+def run_quality(frames=150, measure_from=100):
+    """Segmentation quality on the 640x480x3 workload against its planted
+    masks (the Sec. 5 measures on synthetic data): the plain float32 tracker
+    over `frames` frames, counts of the median-filtered mask accumulated
+    from frame `measure_from` on, and the delta sweep of the last frame;
+    plus the time of the sweep kernel."""
+    import torch
+    from paper_1302_2073_amd import Tracker, roc_counts
+    from paper_1302_2073_amd.tracker import quality_measures
+    from synth import video as V
+    wl = V.vga_rgb()
+    sv = V.SyntheticVideo(wl.video)
+    trk = Tracker(WIDTH, HEIGHT, CH, K, mu=wl.mu, storage="f32")
+    trk.set_state(V.initial_subspace(trk.m, K, wl.video.seed))
+    sc = torch.zeros(trk.m, dtype=torch.float32, device="cuda")
+    tot = np.zeros(4, np.int64)
+    truth = None
+    for n in range(frames):
+        x, truth = sv.frame(n, with_mask=True)
+        if n == frames - 1:
+            trk.set_score_output(sc)
+        trk.track(x.astype(np.float32))
+        if n >= measure_from:
+            tot += np.array(trk.quality_counts(truth, True))
+    thr = np.linspace(0.02, 0.4, 12).astype(np.float32)
+    tdev = torch.from_numpy(truth.astype(np.uint8)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        roc = roc_counts(sc, tdev, CH, thr)
+    el = (time.perf_counter() - t0) / reps
+    trk.set_score_output(None)
+    trk.close()
+    pts = [[round(fp / (fp + tn), 5), round(tp / (tp + fn), 4)] for tp, fp, tn, fn in roc]
+    return dict(measures={k: round(v, 5) for k, v in quality_measures(*tot.tolist()).items()},
+                frames=f"{measure_from}..{frames - 1}",
+                roc_delta=[round(float(d), 4) for d in thr], roc_fpr_recall=pts,
+                roc_call_ms=round(el * 1e3, 3))
+
+
 def cpu_baseline(seconds=15.0):
     """The float64 oracle on the same workload, timed on the host cores over
     a bounded number of frames."""
@@ -299,7 +340,7 @@ def main():
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--streams", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--forms", default="plain_f32,plain_bf16,plain_f32_host,batched_bf16,batched_mixed_bf16,lpcost",
+    ap.add_argument("--forms", default="plain_f32,plain_bf16,plain_f32_host,batched_bf16,batched_mixed_bf16,lpcost,quality",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -360,6 +401,11 @@ def main():
                            "alg_GBps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / PEAK_HBM_GBS, 4),
                            "workload": "forward + backward, m = 230400, k = 10, B = 32, float32",
                            "spread_ms": lp["spread_ms"]}
+    if "quality" in want:
+        forms["quality"] = run_quality()
+        forms["quality"]["note"] = ("Sec. 5 measures of the 3x3-median mask against the planted masks of the "
+                                    "synthetic 640x480x3 video; ROC points (FPR, recall) over delta at the last "
+                                    "frame; roc_call_ms is the host-timed sweep call (12 thresholds)")
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -377,3 +377,20 @@ def roc_counts(scores, truth, channels, thresholds, stream=None):
                                     _ptr(out), _stream_handle(stream)))
     return out
 
+
+def quality_measures(tp, fp, tn, fn):
+    """The measures of Sec. 5 from the counts of pros_quality_counts /
+    roc_counts: recall, specificity, FPR, FNR, PWC (percent), precision and
+    F-measure (nan where a denominator is zero)."""
+    nan = float("nan")
+    recall = tp / (tp + fn) if tp + fn else nan
+    precision = tp / (tp + fp) if tp + fp else nan
+    if tp:
+        fm = 2.0 * precision * recall / (precision + recall)
+    else:
+        fm = 0.0 if (fp or fn) else nan
+    return {"recall": recall, "specificity": tn / (tn + fp) if tn + fp else nan,
+            "fpr": fp / (fp + tn) if fp + tn else nan, "fnr": fn / (tp + fn) if tp + fn else nan,
+            "pwc": 100.0 * (fn + fp) / (tp + fn + fp + tn) if tp + fn + fp + tn else nan,
+            "precision": precision, "fmeasure": fm}
+

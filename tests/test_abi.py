@@ -116,3 +116,16 @@ def test_strerror_covers_codes():
     for s in range(0, -8, -1):
         assert L.strerror(s) and "unknown" not in L.strerror(s)
     assert "unknown" in L.strerror(-99)
+
+
+def test_host_quality_measures_agree_with_oracle_definitions():
+    """The binding's host-side measures (Sec. 5) from counts, against the
+    oracle's definitions."""
+    import math
+    from oracle import prost_oracle as O
+    from paper_1302_2073_amd.tracker import quality_measures
+    for c in [(10, 3, 80, 7), (0, 0, 5, 0), (0, 4, 10, 2), (6, 0, 0, 0)]:
+        a, b = quality_measures(*c), O.quality_metrics(*c)
+        for k in b:
+            assert (math.isnan(a[k]) and math.isnan(b[k])) or a[k] == pytest.approx(b[k])
+

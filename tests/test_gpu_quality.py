@@ -91,3 +91,4 @@ def test_roc_counts_match_host_sweep():
     pts = [(fp / (fp + tn), tp / (tp + fn)) for tp, fp, tn, fn in got]
     say(f"  ROC (FPR, recall) at delta = {thr[0]:.2f} .. {thr[-1]:.2f}: {pts[0]} .. {pts[-1]}")
     assert all(a[0] >= b[0] and a[1] >= b[1] for a, b in zip(pts, pts[1:]))   # monotone in delta
+
