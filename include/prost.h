@@ -97,6 +97,11 @@ typedef struct pros_params {
                                       frames (1 before two frames are in); both
                                       freeze after i_init frames.  0: frames are
                                       used as given (default). */
+  int32_t ysolve;                  /* Step 1 solver: 0 = nonlinear CG with the
+                                      Polak-Ribiere-plus direction (default),
+                                      1 = gradient descent (d = -g), both with
+                                      the majoriser step; Sec. 3.3 compares
+                                      the two. */
 } pros_params;
 
 typedef struct pros_stats {

@@ -120,6 +120,7 @@ class Params:
     labels_after_update: bool = True   # READING: step 3 uses U^(i+1)
     weights_from_filtered: bool = False  # READING: raw labels feed the weights
     preprocess: bool = False     # Sec. 3.4 pre-processing (mean subtraction, scaling)
+    ysolve: str = "cg"           # Step 1 solver: "cg" (PR+) or "gd" (gradient descent)
 
     @property
     def P(self):
@@ -257,9 +258,11 @@ class CGRecord:
     iters: int
 
 
-def cg_solve(U, x, w, y0, J, p, mu, form=COST_LP):
+def cg_solve(U, x, w, y0, J, p, mu, form=COST_LP, method="cg"):
     """Minimise h_{mu,w}(x - U y) over y from the warm start y0 with at most J
     nonlinear conjugate-gradient steps (Sec. 3.3 Step 1; J = 5, Sec. 5.1).
+    method = "gd": plain gradient descent with the same step rule (the
+    simpler alternative Sec. 3.3 compares CG with).
 
     READING (the paper names CG but not its variant or line search):
     Polak-Ribiere-plus direction, restart along -g when the direction is not
@@ -276,7 +279,7 @@ def cg_solve(U, x, w, y0, J, p, mu, form=COST_LP):
         g = -(U.T @ (w * dphi(r, p, mu, form)))
         if not np.any(g):
             break
-        if j == 0:
+        if j == 0 or method == "gd":
             d = -g
             beta = 0.0
         else:
@@ -406,7 +409,7 @@ def track_frame(state: State, x, prm: Params):
     src = state.mask if prm.weights_from_filtered else state.labels
     w = pixel_weights(src, prm.omega, prm.channels)
     # Step 1
-    y, rec = cg_solve(U, x, w, state.y, prm.cg_iters, prm.p, prm.mu, prm.cost)
+    y, rec = cg_solve(U, x, w, state.y, prm.cg_iters, prm.p, prm.mu, prm.cost, prm.ysolve)
     # Step 2
     eta = eta_vector(U, x, y, w, prm.p, prm.mu, prm.cost)
     s, sigma, v, zeta, nu = rank_one_svd(U, eta, y)

@@ -38,6 +38,7 @@ class pros_params(C.Structure):
         ("storage", C.c_int32), ("reorth_every", C.c_int32),
         ("labels_after_update", C.c_int32), ("weights_from_filtered", C.c_int32),
         ("preprocess", C.c_int32),
+        ("ysolve", C.c_int32),
     ]
 
 

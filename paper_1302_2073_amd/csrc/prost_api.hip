@@ -159,6 +159,7 @@ pros_status pros_validate(const pros_params* p) {
   if (p->labels_after_update != 0 && p->labels_after_update != 1) return fail(PROS_EINVAL, "labels_after_update must be 0/1");
   if (p->weights_from_filtered != 0 && p->weights_from_filtered != 1) return fail(PROS_EINVAL, "weights_from_filtered must be 0/1");
   if (p->preprocess != 0 && p->preprocess != 1) return fail(PROS_EINVAL, "preprocess must be 0 or 1");
+  if (p->ysolve != 0 && p->ysolve != 1) return fail(PROS_EINVAL, "ysolve must be 0 (CG) or 1 (gradient descent)");
   return PROS_OK;
 }
 
@@ -480,6 +481,7 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.pre_stat = h->pre_stat;
   a.i_init = p.i_init;
   a.score = h->score;
+  a.ysolve = p.ysolve;
   return a;
 }
 

@@ -53,6 +53,7 @@ struct FrameArgs {
   double* pre_stat;      // [0] entry sum of pre_m2, [1] initialization frames accumulated
   int i_init;            // length of the initialization phase
   float* score;          // optional: |r'| of every entry after Step 3 (m floats), or NULL
+  int ysolve;            // 0: CG with the PR+ direction, 1: gradient descent
   int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
                          // 2: two-level tagged gather (groups of tiles with equal t % 8),
                          // 3: every workgroup reads all tagged partials
@@ -524,7 +525,7 @@ __device__ __forceinline__ void cg_direction(const FrameArgs& a, KSpace<kMaxK>& 
     if (gg == 0.0) stop = 1;
     if (lead && lane == 0) a.stats->f[it] = f;
     double beta = 0.0, dj = -g;
-    if (!stop && it > 0) {
+    if (!stop && it > 0 && a.ysolve == 0) {
       const double gp = (lane < K) ? ks.gp[lane] : 0.0;
       const double num = row16_sum(g * (g - gp));
       const double den = row16_sum(gp * gp);

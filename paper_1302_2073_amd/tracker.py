@@ -16,7 +16,8 @@ from . import _lib as L
 
 def make_params(width, height, channels=1, k=15, cg_iters=5, cost="lp", p=0.25, mu=1e-3,
                 delta=None, omega=5e-5, t_init=5e-3, t_min=1e-4, i_init=100, storage="f32",
-                reorth_every=0, labels_after_update=True, weights_from_filtered=False, preprocess=False):
+                reorth_every=0, labels_after_update=True, weights_from_filtered=False, preprocess=False,
+                ysolve="cg"):
     """pros_params from keyword arguments (Sec. 5.1 defaults)."""
     prm = L.pros_params()
     L.check(L.lib().pros_params_default(C.byref(prm), width, height, channels))
@@ -35,6 +36,7 @@ def make_params(width, height, channels=1, k=15, cg_iters=5, cost="lp", p=0.25, 
     prm.labels_after_update = int(bool(labels_after_update))
     prm.weights_from_filtered = int(bool(weights_from_filtered))
     prm.preprocess = int(bool(preprocess))
+    prm.ysolve = {"cg": 0, "gd": 1}[ysolve]
     return prm
 
 

@@ -35,7 +35,7 @@ def tracker_kwargs(prm: O.Params, storage="f32"):
     return dict(cg_iters=prm.cg_iters, cost=prm.cost, p=prm.p, mu=prm.mu, delta=prm.delta,
                 omega=prm.omega, t_init=prm.t_init, t_min=prm.t_min, i_init=prm.i_init,
                 storage=storage, labels_after_update=prm.labels_after_update,
-                weights_from_filtered=prm.weights_from_filtered, preprocess=prm.preprocess)
+                weights_from_filtered=prm.weights_from_filtered, preprocess=prm.preprocess, ysolve=prm.ysolve)
 
 
 @functools.lru_cache(maxsize=8)

@@ -50,8 +50,8 @@ def test_binding_covers_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     L = _lib()
-    # pros_params: 6 int32 + 6 double + 6 int32 (with padding)
-    assert C.sizeof(L.pros_params) == 6 * 4 + 6 * 8 + 6 * 4
+    # pros_params: 6 int32 + 6 double + 7 int32, padded to 8 bytes
+    assert C.sizeof(L.pros_params) == 6 * 4 + 6 * 8 + 8 * 4
     assert C.sizeof(L.pros_stats) == 8 + 4 * 4 + 8 * (17 + 16 + 16 + 5) + 8
 
 
@@ -73,7 +73,7 @@ def test_defaults_are_the_paper_parameters():
     ("cg_iters", 0), ("cg_iters", 17), ("cost", 2), ("p", 0.0), ("p", 2.5), ("mu", 0.0),
     ("mu", float("nan")), ("omega", -0.1), ("omega", 1.5), ("t_init", 0.0), ("t_min", -1.0),
     ("i_init", 0), ("storage", 3), ("reorth_every", -1), ("labels_after_update", 2),
-    ("weights_from_filtered", 7), ("preprocess", 2), ("delta", float("inf")),
+    ("weights_from_filtered", 7), ("preprocess", 2), ("ysolve", 2), ("delta", float("inf")),
 ])
 def test_validate_rejects(field, value):
     L = _lib()

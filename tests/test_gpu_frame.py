@@ -194,3 +194,16 @@ def test_launch_variants(nr, sync_mode):
         rep = compare_step(trk, prm, states[12], f32(sv.frame(12)))
         assert rep["stats"]["fg_pixels"] == int(rep["labels"].sum())
     assert_parity(rep)
+
+
+@pytest.mark.parametrize("over", [(("ysolve", "gd"),), (("p", 0.5),), (("p", 1.0),), (("p", 2.0),),
+                                  (("ysolve", "gd"), ("p", 1.0))])
+def test_solver_and_exponent_variants(over):
+    """Step 1 by gradient descent instead of CG, and p in {0.5, 1, 2} (p = 2:
+    a smoothed least-squares tracker), state-injected frames of the 320x240
+    workload."""
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 8, over)
+    say(f"qvga variant {dict(over)}")
+    with _tracker(prm) as trk:
+        rep = compare_step(trk, prm, states[8], f32(sv.frame(8)))
+    assert_parity(rep)

@@ -555,3 +555,46 @@ def test_paper_table_rows_are_consistent_measures():
         assert row["specificity"] + row["fpr"] == pytest.approx(1.0, abs=2e-4)
         if row["category"] not in d["inconsistent_fnr"]:
             assert row["recall"] + row["fnr"] == pytest.approx(1.0, abs=2e-3)
+
+
+# ---------------------------------------------------------------------------
+# Step 1 variants: gradient descent with the same step rule
+# ---------------------------------------------------------------------------
+
+def test_gradient_descent_variant_on_quadratic_has_orthogonal_gradients():
+    """p = 2 makes the cost quadratic, so the majoriser step is the exact
+    line minimum: successive steepest-descent gradients are orthogonal, the
+    cost decreases every step, and the first step equals CG's."""
+    rng = np.random.default_rng(21)
+    m, k = 300, 4
+    U = V.random_orthonormal(m, k, rng)
+    w = np.exp(rng.uniform(-3, 0, m))
+    x = rng.standard_normal(m)
+    y0 = np.zeros(k)
+    ys = []
+    for J in range(1, 4):
+        y, rec = O.cg_solve(U, x, w, y0, J, 2.0, 1e-3, O.COST_LP, "gd")
+        ys.append(y)
+        assert all(b <= a + 1e-12 for a, b in zip(rec.f, rec.f[1:]))
+    gs = [-(U.T @ (w * O.dphi(x - U @ y, 2.0, 1e-3))) for y in [y0] + ys]
+    for a, b in zip(gs, gs[1:]):
+        assert abs(a @ b) <= 1e-8 * np.linalg.norm(a) * np.linalg.norm(b)
+    y1cg, _ = O.cg_solve(U, x, w, y0, 1, 2.0, 1e-3, O.COST_LP, "cg")
+    assert np.allclose(ys[0], y1cg, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", [22, 23, 24])
+def test_cg_beats_gradient_descent_on_a_quadratic(seed):
+    """Sec. 3.3's argument for CG: on a quadratic (p = 2) CG with exact
+    steps minimises over the Krylov space that also holds the gradient
+    descent iterates, so after the same number of steps its cost is never
+    higher (and here lower)."""
+    rng = np.random.default_rng(seed)
+    m, k = 400, 8
+    U = V.random_orthonormal(m, k, rng)
+    w = np.exp(rng.uniform(-6, 0, m))
+    x = U @ (3 * rng.standard_normal(k)) + 0.1 * rng.standard_normal(m)
+    for J in (2, 3, 4):
+        _, rc = O.cg_solve(U, x, w, np.zeros(k), J, 2.0, 1e-3, O.COST_LP, "cg")
+        _, rg = O.cg_solve(U, x, w, np.zeros(k), J, 2.0, 1e-3, O.COST_LP, "gd")
+        assert rc.f[-1] < rg.f[-1]
