@@ -120,7 +120,7 @@ class Params:
     labels_after_update: bool = True   # READING: step 3 uses U^(i+1)
     weights_from_filtered: bool = False  # READING: raw labels feed the weights
     preprocess: bool = False     # Sec. 3.4 pre-processing (mean subtraction, scaling)
-    ysolve: str = "cg"           # Step 1 solver: "cg" (PR+) or "gd" (gradient descent)
+    ysolve: str = "cg"           # Step 1 solver: "cg" (PR+), "gd" (gradient descent), "irls" (-H^-1 g)
 
     @property
     def P(self):
@@ -258,11 +258,20 @@ class CGRecord:
     iters: int
 
 
+def cho_solve_lower(L, b):
+    """Solve (L L^T) z = b by two triangular solves (library routines)."""
+    import scipy.linalg
+    return scipy.linalg.solve_triangular(L.T, scipy.linalg.solve_triangular(L, b, lower=True), lower=False)
+
+
 def cg_solve(U, x, w, y0, J, p, mu, form=COST_LP, method="cg"):
     """Minimise h_{mu,w}(x - U y) over y from the warm start y0 with at most J
     nonlinear conjugate-gradient steps (Sec. 3.3 Step 1; J = 5, Sec. 5.1).
     method = "gd": plain gradient descent with the same step rule (the
-    simpler alternative Sec. 3.3 compares CG with).
+    simpler alternative Sec. 3.3 compares CG with).  method = "irls": the
+    full majoriser step, y += -H^{-1} g (iteratively reweighted least
+    squares / Newton on the majoriser); stops when H is not positive
+    definite.
 
     READING (the paper names CG but not its variant or line search):
     Polak-Ribiere-plus direction, restart along -g when the direction is not
@@ -279,6 +288,17 @@ def cg_solve(U, x, w, y0, J, p, mu, form=COST_LP, method="cg"):
         g = -(U.T @ (w * dphi(r, p, mu, form)))
         if not np.any(g):
             break
+        if method == "irls":
+            H = U.T @ (U * (w * curv(r, p, mu, form))[:, None])
+            try:
+                L = np.linalg.cholesky(H)
+            except np.linalg.LinAlgError:
+                break
+            y = y - cho_solve_lower(L, g)
+            rec.alpha.append(1.0)
+            rec.beta.append(0.0)
+            rec.iters += 1
+            continue
         if j == 0 or method == "gd":
             d = -g
             beta = 0.0

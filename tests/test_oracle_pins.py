@@ -598,3 +598,32 @@ def test_cg_beats_gradient_descent_on_a_quadratic(seed):
         _, rc = O.cg_solve(U, x, w, np.zeros(k), J, 2.0, 1e-3, O.COST_LP, "cg")
         _, rg = O.cg_solve(U, x, w, np.zeros(k), J, 2.0, 1e-3, O.COST_LP, "gd")
         assert rc.f[-1] < rg.f[-1]
+
+
+def test_irls_variant_solves_weighted_least_squares_in_one_step():
+    """p = 2: the majoriser is the cost itself, so one IRLS step lands on the
+    weighted least-squares solution (numpy lstsq on sqrt(w)-scaled rows)."""
+    rng = np.random.default_rng(25)
+    m, k = 200, 5
+    U = V.random_orthonormal(m, k, rng)
+    w = np.exp(rng.uniform(-3, 0, m))
+    x = rng.standard_normal(m)
+    y, rec = O.cg_solve(U, x, w, rng.standard_normal(k), 1, 2.0, 1e-3, O.COST_LP, "irls")
+    sw = np.sqrt(w)
+    ref = np.linalg.lstsq(U * sw[:, None], x * sw, rcond=None)[0]
+    assert np.allclose(y, ref, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [0.25, 1.0])
+def test_irls_variant_is_monotone_and_reaches_a_stationary_point(p):
+    rng = np.random.default_rng(26)
+    m, k = 300, 4
+    U = V.random_orthonormal(m, k, rng)
+    w = np.where(rng.random(m) < 0.1, 5e-5, 1.0)
+    x = U @ rng.standard_normal(k) + 0.02 * rng.standard_normal(m)
+    x[rng.random(m) < 0.1] += 1.0
+    y, rec = O.cg_solve(U, x, w, np.zeros(k), 30, p, 1e-3, O.COST_LP, "irls")
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(rec.f, rec.f[1:]))
+    g = -(U.T @ (w * O.dphi(x - U @ y, p, 1e-3)))
+    g0 = -(U.T @ (w * O.dphi(x, p, 1e-3)))
+    assert np.linalg.norm(g) <= 1e-6 * np.linalg.norm(g0)
