@@ -101,7 +101,17 @@ typedef struct pros_params {
                                       Polak-Ribiere-plus direction (default),
                                       1 = gradient descent (d = -g), both with
                                       the majoriser step; Sec. 3.3 compares
-                                      the two. */
+                                      the two.  2 = iteratively reweighted
+                                      least squares: each step is the full
+                                      step -H^-1 g of the quadratic majoriser
+                                      (H = U^T diag(w c) U), the classical
+                                      reading of the majorise-minimise scheme
+                                      of Sec. 3.3; float32 storage, a tagged
+                                      exchange (sync_mode 1..3) and the
+                                      single-stream tracker only (a batch
+                                      refuses it).
+                                      A singular H ends the solve with the
+                                      current y. */
 } pros_params;
 
 typedef struct pros_stats {

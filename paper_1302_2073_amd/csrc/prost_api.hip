@@ -159,7 +159,8 @@ pros_status pros_validate(const pros_params* p) {
   if (p->labels_after_update != 0 && p->labels_after_update != 1) return fail(PROS_EINVAL, "labels_after_update must be 0/1");
   if (p->weights_from_filtered != 0 && p->weights_from_filtered != 1) return fail(PROS_EINVAL, "weights_from_filtered must be 0/1");
   if (p->preprocess != 0 && p->preprocess != 1) return fail(PROS_EINVAL, "preprocess must be 0 or 1");
-  if (p->ysolve != 0 && p->ysolve != 1) return fail(PROS_EINVAL, "ysolve must be 0 (CG) or 1 (gradient descent)");
+  if (p->ysolve < 0 || p->ysolve > 2) return fail(PROS_EINVAL, "ysolve must be 0 (CG), 1 (gradient descent) or 2 (IRLS)");
+  if (p->ysolve == 2 && p->storage != PROS_F32) return fail(PROS_EINVAL, "the IRLS step needs float32 storage");
   return PROS_OK;
 }
 
@@ -180,6 +181,12 @@ int prost_host::tile_pixels(int storage, int NR, int channels, double scale) {
   return tpw;
 }
 
+size_t prost_host::part_bytes(const pros_handle* h, int G) {
+  size_t d = (2 * (size_t)G + prost::kExtraSlots) * prost::kSlot;
+  if (h->prm.ysolve == 2) d += ((size_t)G + 16) * prost::kWideMax;
+  return sizeof(double) * d;
+}
+
 bool prost_host::pair_layout(const pros_handle* h) {
   return h->prm.storage == PROS_BF16 && h->P % 2 == 0 && h->tpw % 2 == 0 && h->ldU % 2 == 0;
 }
@@ -195,7 +202,7 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
   int bestNR = 0, bestG = 0, bestT = 0;
   for (int NR : nrs) {
     if (force_nr > 0 && NR != force_nr) continue;
-    const bool ext = h->prm.preprocess != 0 || h->score != nullptr;
+    const bool ext = h->prm.preprocess != 0 || h->score != nullptr || h->prm.ysolve == 2;
     const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, ext)
                                                   : prost::frame_kernel_f32(h->k, NR, ext);
     if (!f) continue;
@@ -263,7 +270,7 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
   INIT_TRY(hipMalloc((void**)&h->y, sizeof(double) * PROS_MAX_K));
   INIT_TRY(hipMalloc((void**)&h->nframe, sizeof(long long)));
   INIT_TRY(hipMalloc((void**)&h->stats, sizeof(pros_stats)));
-  INIT_TRY(hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)h->G + prost::kExtraSlots) * prost::kSlot));
+  INIT_TRY(hipMalloc((void**)&h->part, prost_host::part_bytes(h, h->G)));
   INIT_TRY(hipMalloc((void**)&h->sync, 64));
   INIT_TRY(hipMemsetAsync(h->U, 0, es * (size_t)h->ldU * h->k, h->stream));
   INIT_TRY(hipMemsetAsync(h->lab, 0, (size_t)h->P, h->stream));
@@ -281,7 +288,7 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
     INIT_TRY(hipMemsetAsync(h->pre_stat, 0, 2 * sizeof(double), h->stream));
   }
   // epoch-tagged exchange slots must start with tag 0 (the first exchange uses 1)
-  INIT_TRY(hipMemsetAsync(h->part, 0, sizeof(double) * (2 * (size_t)h->G + prost::kExtraSlots) * prost::kSlot,
+  INIT_TRY(hipMemsetAsync(h->part, 0, prost_host::part_bytes(h, h->G),
                           h->stream));
   INIT_TRY(hipStreamSynchronize(h->stream));
 #undef INIT_TRY
@@ -591,7 +598,7 @@ pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
 // Clear the exchange slots and restart the epoch and arrival counters (after
 // any change of the gang; stale tags must never match a new epoch).
 pros_status prost_host::reset_exchange(pros_handle* h) {
-  HIP_TRY(hipMemsetAsync(h->part, 0, sizeof(double) * (2 * (size_t)h->G + prost::kExtraSlots) * prost::kSlot, h->stream));
+  HIP_TRY(hipMemsetAsync(h->part, 0, prost_host::part_bytes(h, h->G), h->stream));
   HIP_TRY(hipMemsetAsync(h->sync, 0, 16, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return PROS_OK;
@@ -601,6 +608,7 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
   if (sync_mode < 0 || sync_mode > 3) return fail(PROS_EINVAL, "sync_mode must be 0..3");
+  if (sync_mode == 0 && h->prm.ysolve == 2) return fail(PROS_EINVAL, "the IRLS step needs a tagged exchange (sync_mode 1..3)");
   if (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 && rows_per_thread != 4 &&
       rows_per_thread != 8 && rows_per_thread != 16 && rows_per_thread != 32)
     return fail(PROS_EINVAL, "rows_per_thread must be 0 (automatic), 1, 2, 4, 8, 16 or 32");
@@ -611,7 +619,7 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   if (h->G > oldG) {
     (void)hipFree(h->part);
     h->part = nullptr;
-    hipError_t e = hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)h->G + prost::kExtraSlots) * prost::kSlot);
+    hipError_t e = hipMalloc((void**)&h->part, prost_host::part_bytes(h, h->G));
     if (e != hipSuccess) {
       h->broken = true;
       h->broken_status = PROS_ENOMEM;

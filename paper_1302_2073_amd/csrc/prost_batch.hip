@@ -133,7 +133,9 @@ static pros_status build_schedule(pros_batch* b) {
 // (Re)create the per-stream tile configuration, descriptors and schedule.
 static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy, int sync_mode) {
   bool ext = false;
-  for (pros_handle* h : b->hs) ext = ext || (h->pre_mean != nullptr);
+  for (pros_handle* h : b->hs) {
+    ext = ext || (h->pre_mean != nullptr);
+  }
   const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget, ext);
   if (!f) return fail(PROS_EUNSUPPORTED, "no batch kernel for k class %d", b->kclass);
   int occ = 0;
@@ -151,7 +153,7 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
     if (G != h->G) {   // partial buffer sized by the gang
       (void)hipFree(h->part);
       h->part = nullptr;
-      e = hipMalloc((void**)&h->part, sizeof(double) * (2 * (size_t)G + prost::kExtraSlots) * prost::kSlot);
+      e = hipMalloc((void**)&h->part, prost_host::part_bytes(h, G));
       if (e != hipSuccess) return fail(PROS_ENOMEM, "partials: %s", hipGetErrorString(e));
     }
     h->NR = NR;
@@ -233,6 +235,8 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
     if (per_stream[s].storage != storage) return fail(PROS_EINVAL, "all streams of a batch share one storage type");
     if (per_stream[s].reorth_every != 0)
       return fail(PROS_EINVAL, "stream %d: use pros_batch_reorthonormalize in a batch", s);
+    if (per_stream[s].ysolve == 2)
+      return fail(PROS_EINVAL, "stream %d: the IRLS step runs in the single-stream kernel only", s);
   }
   pros_batch* b = new pros_batch();
   b->n = n;
@@ -272,7 +276,7 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
     free_batch(b);
     return fail(PROS_ENOMEM, "batch tables: %s", hipGetErrorString(e));
   }
-  pros_status st = configure(b, 128, 2, 1.0, 0, 2);
+  pros_status st = configure(b, 128, 2, 1.0, 0, 2);   // sync mode 2 suits every stream
   if (st != PROS_OK) {
     free_batch(b);
     return st;

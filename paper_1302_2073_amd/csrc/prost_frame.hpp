@@ -19,6 +19,8 @@
 // all of them hold bit-identical k-vectors without a broadcast step.
 #pragma once
 
+#include <utility>
+
 #include "prost_device.hpp"
 #include "../../include/prost.h"
 
@@ -86,6 +88,12 @@ struct KSpace {
 };
 
 // Workgroup-shared scratch of one frame tile (sized for the largest k / NR).
+// Wide exchange of the IRLS step: g, f and the upper triangle of H
+// (K + 1 + K (K + 1) / 2 <= 153 values) in vectors of kWideMax float64.
+constexpr int kWideChunks = 5;
+constexpr int kWideMax = kWideChunks * kSlot;
+constexpr int kWideIn = kWideMax + kSlot;   // room for the last zero-padded chunk
+
 struct FrameSmem {
   KSpace<kMaxK> ks;
   double red[kWaves][kSlot];
@@ -93,6 +101,9 @@ struct FrameSmem {
   double big[kBlock];          // one float64 per thread (gathers)
   int ctl[4];
   uint8_t flag[kBlock * kMaxNR];
+  double wide_in[kWideIn];     // IRLS: this workgroup's partials
+  double wide_out[kWideMax];   // IRLS: gang totals
+  double hs[kMaxK][kMaxK + 1]; // IRLS: augmented [H | -g] for the k-space solve
 };
 
 
@@ -303,6 +314,68 @@ __device__ __forceinline__ bool gang_reduce_allread(const double* wg_sum, const 
   if (!poll_sum_slots<L>(slots, a.G, ep, a, s_big, s_out)) return false;
   if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
+}
+
+// Poll n tagged vectors of LT values (vector q at base + q * qstride) until
+// every value carries epoch ep; out[v] = sum over q in order.  Threads:
+// value tid % kWideMax, vectors tid / kWideMax + 3 i.  Uniform exit.
+__device__ __forceinline__ bool poll_sum_wide(const double* base, int n, int qstride, int LT, unsigned ep,
+                                              const FrameArgs& a, double* s_big, double* out) {
+  const int tid = thread_index();
+  constexpr int kRowsW = kBlock / kWideMax;
+  const int v = tid % kWideMax, row = tid / kWideMax;
+  const bool act = row < kRowsW && v < LT;
+  const long long t0 = now_ticks();
+  double acc = 0.0;
+  while (true) {
+    int ok = 1;
+    acc = 0.0;
+    if (act)
+      for (int q = row; q < n; q += kRowsW) {
+        const double val = ld_tagged(&base[(size_t)q * qstride + v]);
+        ok &= (tag_of(val) == ep) ? 1 : 0;
+        acc += untag(val);
+      }
+    if (__syncthreads_and(ok)) break;
+    const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
+                                    (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
+    if (__syncthreads_or(late)) {
+      if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  s_big[tid] = acc;
+  __syncthreads();
+  if (tid < LT) {
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsW; ++r) t += s_big[r * kWideMax + tid];
+    out[tid] = t;
+  }
+  __syncthreads();
+  return true;
+}
+
+// Gang sum of LT (<= kWideMax) float64 values per workgroup, in the
+// two-hop form of sync mode 2 (groups of tiles t = x mod 8), in its own
+// region of the exchange buffer after the regular slots.  Every workgroup
+// ends with bit-identical totals in out.
+__device__ __forceinline__ bool gang_reduce_wide(const double* in, int LT, const FrameArgs& a, const int tile,
+                                                 int& nbar, unsigned ebase, double* s_big, double* out) {
+  const int tid = thread_index();
+  ++nbar;
+  const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
+  const int x = tile & 7;
+  const int ngrp = min(8, a.G);
+  double* slots = a.part + (size_t)(2 * a.G + kExtraSlots) * kSlot;           // G vectors
+  double* gs = slots + (size_t)a.G * kWideMax + (size_t)(nbar & 1) * 8 * kWideMax;   // 2 x 8 group sums
+  for (int q = tid; q < LT; q += kBlock) st_tagged(&slots[(size_t)tile * kWideMax + q], tag_value(in[q], ep));
+  if (tile < 8) {   // group leader: members x, x + 8, ...
+    const int n = (a.G - x + 7) >> 3;
+    if (!poll_sum_wide(slots + (size_t)x * kWideMax, n, 8 * kWideMax, LT, ep, a, s_big, out)) return false;
+    for (int q = tid; q < LT; q += kBlock) st_tagged(&gs[(size_t)x * kWideMax + q], tag_value(out[q], ep));
+  }
+  return poll_sum_wide(gs, ngrp, kWideMax, LT, ep, a, s_big, out);
 }
 
 // Workgroup sum of L float partials (one value per thread each), float64
@@ -553,6 +626,158 @@ __device__ __forceinline__ void cg_direction(const FrameArgs& a, KSpace<kMaxK>& 
   __syncthreads();
 }
 
+// ---- IRLS step (Step 1 variant): d = -H^{-1} g, one exchange per step ----
+
+// Upper-triangle pair p -> (row, column) of a K x K matrix, row-major.
+__host__ __device__ constexpr int tri_row(int p, int K) {
+  int i = 0;
+  while (p >= K - i) { p -= K - i; ++i; }
+  return i;
+}
+__host__ __device__ constexpr int tri_col(int p, int K) {
+  int i = 0;
+  while (p >= K - i) { p -= K - i; ++i; }
+  return i + p;
+}
+
+template <int K, int P>
+struct TriPair {   // compile-time (row, column) of upper-triangle pair P
+  static constexpr int i = tri_row(P, K);
+  static constexpr int j = tri_col(P, K);
+};
+
+// One register row's contribution to chunk C (pairs C*32 .. C*32+31) of H.
+template <int K, int C, typename UF, int... Q>
+__device__ __forceinline__ void irls_h_row(float (&h)[kSlot], float wci, int row, UF uval,
+                                           std::integer_sequence<int, Q...>) {
+  constexpr int NP = K * (K + 1) / 2;
+  ((C * kSlot + Q < NP
+        ? (void)(h[Q] = fmaf(wci * uval(row, TriPair<K, (C * kSlot + Q < NP ? C * kSlot + Q : 0)>::i),
+                             uval(row, TriPair<K, (C * kSlot + Q < NP ? C * kSlot + Q : 0)>::j), h[Q]))
+        : (void)0),
+   ...);
+}
+
+template <int K, int ROWS, int C, typename UF, typename PF>
+__device__ __forceinline__ void irls_h_chunk(const float (&wc)[ROWS], UF uval, PF pin, FrameSmem& sm) {
+  float h[kSlot];
+#pragma unroll
+  for (int q = 0; q < kSlot; ++q) h[q] = 0.f;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    pin();
+    irls_h_row<K, C>(h, wc[i], i, uval, std::make_integer_sequence<int, kSlot>{});
+  }
+  wg_reduce<kSlot>(h, sm.red, sm.wide_in + K + 1 + C * kSlot);
+}
+
+template <int K, int ROWS, typename UF, typename PF, int... C>
+__device__ __forceinline__ void irls_h_chunks(const float (&wc)[ROWS], UF uval, PF pin, FrameSmem& sm,
+                                              std::integer_sequence<int, C...>) {
+  (irls_h_chunk<K, ROWS, C>(wc, uval, pin, sm), ...);
+}
+
+// This workgroup's partial sums of H = U^T diag(w c) U (upper triangle),
+// 32 entries at a time, into sm.wide_in[K + 1 ...].  uval(i, j): entry j of
+// the thread's register row i (j a compile-time constant); wc[i] = w c(r)
+// of that row; pin() is called before each row (keeps widened copies of a
+// packed tile from being held across rows).
+template <int K, int ROWS, typename UF, typename PF>
+__device__ __forceinline__ void irls_h_partials(const float (&wc)[ROWS], UF uval, PF pin, FrameSmem& sm) {
+  constexpr int NP = K * (K + 1) / 2;
+  irls_h_chunks<K, ROWS>(wc, uval, pin, sm, std::make_integer_sequence<int, (NP + kSlot - 1) / kSlot>{});
+}
+
+// Solve H d = -g from the gang totals (g, f, H in sm.wide_out) by Gaussian
+// elimination without pivoting (H is symmetric positive definite for a
+// non-degenerate frame) on the augmented matrix in LDS, all threads, fixed
+// order.  Sets ks.d / df, ks.gd, the stop flag (zero gradient or H not
+// positive definite) and, in the first step, the bad-frame flag.
+template <int K>
+__device__ __forceinline__ void irls_direction(const FrameArgs& a, FrameSmem& sm, int it, bool lead) {
+  KSpace<kMaxK>& ks = sm.ks;
+  const double* tot = sm.wide_out;
+  const int tid = thread_index(), lane = tid & 63;
+  for (int q = tid; q < K * (K + 1); q += kBlock) {
+    const int i = q / (K + 1), j = q - i * (K + 1);
+    double v;
+    if (j == K) {
+      v = tot[i];                     // -g = U^T (w phi'(r))
+    } else {
+      const int lo = min(i, j), hi = max(i, j);
+      v = tot[K + 1 + lo * K - lo * (lo - 1) / 2 + (hi - lo)];
+    }
+    sm.hs[i][j] = v;
+  }
+  if (tid == 0) ks.flag[3] = 0;
+  __syncthreads();
+  if (tid < 64) {
+    const double g = (lane < K) ? -tot[lane] : 0.0;
+    const double gg = row16_sum(g * g);
+    const double f = tot[K];
+    int stop = (gg == 0.0) ? 1 : 0;
+    if (it == 0 && !(isfinite(f) && isfinite(gg))) {
+      stop = 1;
+      if (lane == 0) ks.flag[1] = 1;
+    }
+    if (lead && lane == 0) {
+      a.stats->f[it] = f;
+      a.stats->beta[it] = 0.0;
+    }
+    if (lane == 0) ks.flag[3] = stop;
+  }
+  __syncthreads();
+  for (int k = 0; k < K; ++k) {          // elimination, rows below k
+    const double piv = sm.hs[k][k];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (tid == 0) ks.flag[3] = 1;      // not positive definite: no step
+      break;                             // uniform: every thread reads the same pivot
+    }
+    const double inv = 1.0 / piv;
+    const int w = K - k - 1;
+    for (int q = tid; q < w * (w + 1); q += kBlock) {
+      const int i = k + 1 + q / (w + 1), j = k + 1 + q % (w + 1);
+      sm.hs[i][j] -= sm.hs[i][k] * inv * sm.hs[k][j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const bool ok = ks.flag[3] == 0;
+  if (ok)
+    for (int k = K - 1; k >= 0; --k) {   // back substitution, d_k in place of the right-hand side
+      if (tid == 0) sm.hs[k][K] = sm.hs[k][K] / sm.hs[k][k];
+      __syncthreads();
+      const double dk = sm.hs[k][K];
+      for (int i = tid; i < k; i += kBlock) sm.hs[i][K] -= sm.hs[i][k] * dk;
+      __syncthreads();
+    }
+  if (tid < 64) {
+    const double g = (lane < K) ? -tot[lane] : 0.0;
+    const double dj = (ok && lane < K) ? sm.hs[lane][K] : 0.0;
+    const double gd = row16_sum(g * dj);
+    if (lane < K) {
+      ks.d[lane] = dj;
+      ks.df[lane] = (float)dj;
+    }
+    if (lane == 0) {
+      ks.gd = gd;
+      ks.flag[0] = ok ? 0 : 1;
+    }
+  }
+  __syncthreads();
+}
+
+// y += d (unit step of the IRLS iteration).
+template <int K>
+__device__ __forceinline__ void irls_advance(const FrameArgs& a, KSpace<kMaxK>& ks, int it, bool lead) {
+  const int tid = thread_index();
+  if (tid < K) {
+    ks.y[tid] += ks.d[tid];
+    ks.dp[tid] = ks.d[tid];
+  }
+  if (lead && tid == 0) a.stats->alpha[it] = 1.0;
+}
+
 // Majoriser step along d: alpha = -g.d / d^T H d, y += alpha d.  Returns
 // alpha as float for the residual update.
 template <int K>
@@ -656,7 +881,7 @@ __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSp
 // ---------------------------------------------------------------------------
 // float32 storage: row q = tid + s * kBlock of the tile, K floats per row
 // ---------------------------------------------------------------------------
-template <int K, int NR, bool EXT>
+template <int K, int NR, bool EXT, bool IRLS>
 __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
@@ -717,6 +942,25 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       acc[K] = fmaf(wt[s], phi, acc[K]);
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, u[s][j], acc[j]);
+    }
+    if (IRLS && a.ysolve == 2) {   // IRLS: g, f and H in one (wide) exchange, step -H^{-1} g
+      wg_reduce<K + 1>(acc, sm.red, sm.wide_in);
+      irls_h_partials<K, NR>(cw, [&](int i, int j) { return u[i][j]; }, [] {}, sm);
+      if (!gang_reduce_wide(sm.wide_in, K + 1 + K * (K + 1) / 2, a, tile, nbar, ctx.ebase, sm.big, sm.wide_out))
+        return false;
+      irls_direction<K>(a, sm, it, ctx.lead);
+      if (ks.flag[0]) break;
+      irls_advance<K>(a, ks, it, ctx.lead);
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        float t = 0.f;
+#pragma unroll
+        for (int j = 0; j < K; ++j) t = fmaf(u[s][j], ks.df[j], t);
+        r[s] -= t;
+      }
+      ++steps;
+      __syncthreads();
+      continue;
     }
     if (!gang_reduce<K + 1>(acc, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
     cg_direction<K>(a, ks, it, ctx.lead, restarts);
@@ -1060,21 +1304,23 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 // Returns false when the gang aborted.
 // EXT: the optional features are compiled in (pre-processing when the
 // stream has its statistics, per-entry label scores when a score buffer is
-// given); without it the hot path carries none of their code.
-template <int K, int NR, typename TS, bool EXT>
+// given); without it the hot path carries none of their code.  IRLS: the
+// IRLS Step 1 variant is compiled in as well (float32 tiles of the
+// single-stream kernel only; its H partials would spill the packed tile).
+template <int K, int NR, typename TS, bool EXT, bool IRLS = false>
 __device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   if constexpr (sizeof(TS) == 2) {
     static_assert(NR % 2 == 0, "bfloat16 tiles hold row pairs");
     return frame_tile_packed<K, NR / 2, EXT>(a, tile, sm);
   } else {
-    return frame_tile<K, NR, EXT>(a, tile, sm);
+    return frame_tile<K, NR, EXT, IRLS>(a, tile, sm);
   }
 }
 
 template <int K, int NR, typename TS, bool EXT>
 __global__ __launch_bounds__(kBlock, 2) void frame_kernel(FrameArgs a) {
   __shared__ FrameSmem sm;
-  run_tile<K, NR, TS, EXT>(a, blockIdx.x, sm);
+  run_tile<K, NR, TS, EXT, EXT>(a, blockIdx.x, sm);
 }
 
 }  // namespace prost

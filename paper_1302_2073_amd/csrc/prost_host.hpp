@@ -65,6 +65,9 @@ int tile_pixels(int storage, int NR, int channels, double scale);
 // bfloat16 row pairs can be accessed as aligned 32-bit words in U (frame
 // alignment is checked separately).
 bool pair_layout(const pros_handle* h);
+// Bytes of the exchange buffer for a gang of G workgroups: the regular
+// slots, plus the wide region of the IRLS step when the stream uses it.
+size_t part_bytes(const pros_handle* h, int G);
 
 uint16_t bf16_rne(float f);
 float bf16_to_f32(uint16_t b);

@@ -36,7 +36,7 @@ def make_params(width, height, channels=1, k=15, cg_iters=5, cost="lp", p=0.25, 
     prm.labels_after_update = int(bool(labels_after_update))
     prm.weights_from_filtered = int(bool(weights_from_filtered))
     prm.preprocess = int(bool(preprocess))
-    prm.ysolve = {"cg": 0, "gd": 1}[ysolve]
+    prm.ysolve = {"cg": 0, "gd": 1, "irls": 2}[ysolve]
     return prm
 
 

@@ -73,7 +73,7 @@ def test_defaults_are_the_paper_parameters():
     ("cg_iters", 0), ("cg_iters", 17), ("cost", 2), ("p", 0.0), ("p", 2.5), ("mu", 0.0),
     ("mu", float("nan")), ("omega", -0.1), ("omega", 1.5), ("t_init", 0.0), ("t_min", -1.0),
     ("i_init", 0), ("storage", 3), ("reorth_every", -1), ("labels_after_update", 2),
-    ("weights_from_filtered", 7), ("preprocess", 2), ("ysolve", 2), ("delta", float("inf")),
+    ("weights_from_filtered", 7), ("preprocess", 2), ("ysolve", 3), ("ysolve", -1), ("delta", float("inf")),
 ])
 def test_validate_rejects(field, value):
     L = _lib()
@@ -81,6 +81,26 @@ def test_validate_rejects(field, value):
     setattr(p, field, value)
     assert L.lib().pros_validate(C.byref(p)) == L.PROS_EINVAL
     assert L.last_error()
+
+
+def test_irls_needs_float32_storage():
+    L = _lib()
+    p = _default(L)
+    p.ysolve = 2
+    assert L.lib().pros_validate(C.byref(p)) == L.PROS_OK
+    p.storage = L.PROS_BF16
+    assert L.lib().pros_validate(C.byref(p)) == L.PROS_EINVAL
+    assert "float32" in L.last_error()
+
+
+def test_batch_refuses_irls_without_touching_the_gpu():
+    L = _lib()
+    ps = (L.pros_params * 2)(_default(L), _default(L))
+    ps[1].ysolve = 2
+    h = C.c_void_p(123)
+    assert L.lib().pros_batch_init(ps, 2, None, C.byref(h)) == L.PROS_EINVAL
+    assert h.value is None
+    assert "IRLS" in L.last_error()
 
 
 def test_k_larger_than_frame_rejected():

@@ -197,7 +197,8 @@ def test_launch_variants(nr, sync_mode):
 
 
 @pytest.mark.parametrize("over", [(("ysolve", "gd"),), (("p", 0.5),), (("p", 1.0),), (("p", 2.0),),
-                                  (("ysolve", "gd"), ("p", 1.0))])
+                                  (("ysolve", "gd"), ("p", 1.0)), (("ysolve", "irls"),),
+                                  (("ysolve", "irls"), ("p", 1.0)), (("ysolve", "irls"), ("p", 2.0))])
 def test_solver_and_exponent_variants(over):
     """Step 1 by gradient descent instead of CG, and p in {0.5, 1, 2} (p = 2:
     a smoothed least-squares tracker), state-injected frames of the 320x240
@@ -206,4 +207,31 @@ def test_solver_and_exponent_variants(over):
     say(f"qvga variant {dict(over)}")
     with _tracker(prm) as trk:
         rep = compare_step(trk, prm, states[8], f32(sv.frame(8)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("sync_mode", [1, 2, 3])
+@pytest.mark.parametrize("nr", [1, 8])
+def test_irls_launch_variants(nr, sync_mode):
+    """The IRLS step (one wide exchange of g, f and H per step) under each
+    tagged exchange and gang size; the counter exchange is refused for it."""
+    over = (("ysolve", "irls"),)
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 8, over)
+    with _tracker(prm) as trk:
+        with pytest.raises(RuntimeError):
+            trk.set_launch(nr, 0)
+        trk.set_launch(nr, sync_mode)
+        say(f"qvga irls launch {trk.launch_info()}")
+        rep = compare_step(trk, prm, states[8], f32(sv.frame(8)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("frame", [0, 3, 40])
+def test_irls_small_gray_ragged(frame):
+    """IRLS on the small gray workload (a ragged last tile), early frames
+    included (t = t_init, few updates behind U)."""
+    over = (("ysolve", "irls"),)
+    wl, prm, sv, states = oracle_trajectory("small_gray", frame, over)
+    with _tracker(prm) as trk:
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
     assert_parity(rep)
