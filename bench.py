@@ -95,13 +95,15 @@ def timed_median(fn, steps, stream):
     return ts[len(ts) // 2], ts[0], ts[-1]
 
 
-def run_plain(storage, steps, warmup, pool):
+def run_plain(storage, steps, warmup, pool, curvature=0):
     import torch
     from paper_1302_2073_amd import Tracker
     from synth import video as V
     wl, sv, frames = make_frames(pool, storage)
     trk = Tracker(WIDTH, HEIGHT, CH, K, mu=wl.mu, storage=storage)
     trk.set_state(V.initial_subspace(trk.m, K, wl.video.seed))
+    if curvature:
+        trk.set_curvature(curvature)
     stream = torch.cuda.current_stream()   # the tracker was created on this stream
     for i in range(max(warmup, 50)):
         trk.track(frames[i % pool])
@@ -340,7 +342,8 @@ def main():
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--streams", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--forms", default="plain_f32,plain_bf16,plain_f32_host,batched_bf16,batched_mixed_bf16,lpcost,quality",
+    ap.add_argument("--forms", default="plain_f32,plain_f32_curv1,plain_bf16,plain_f32_host,batched_bf16,"
+                    "batched_mixed_bf16,lpcost,quality",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -374,6 +377,10 @@ def main():
     if "plain_f32" in want:
         plain = run_plain("f32", args.steps * 4, args.warmup, args.pool)
         achieved = record("plain_f32", plain, 4, 4)
+    if "plain_f32_curv1" in want:
+        curv = run_plain("f32", args.steps * 4, args.warmup, args.pool, curvature=1)
+        record("plain_f32_curv1", curv, 4, 4)
+        forms["plain_f32_curv1"]["note"] = "curvature schedule 1: H reduced with the gradient, J + 1 exchanges"
     if "plain_bf16" in want:
         plain_bf16 = run_plain("bf16", args.steps * 4, args.warmup, args.pool)
         record("plain_bf16", plain_bf16, 2, 2)

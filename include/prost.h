@@ -238,6 +238,7 @@ typedef struct pros_launch_info {
   int32_t pixels_per_wg;     /* pixels of one workgroup tile */
   int32_t barriers_per_frame;/* gang-wide reductions per frame */
   int32_t sync_mode;         /* gang exchange, as in pros_set_launch */
+  int32_t curvature;         /* CG curvature schedule, as in pros_set_curvature */
 } pros_launch_info;
 PROS_API pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out);
 
@@ -343,6 +344,19 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
  * Results agree to float64 rounding.
  * Synchronises. */
 PROS_API pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode);
+
+/* Curvature schedule of the Step 1 solver (Sec. 3.3): how d^T H d of the
+ * majoriser step alpha = -g.d / d^T H d, H = U^T diag(w c) U, is formed.
+ * 0 (default): a second pass per step sums w c (u_e . d)^2 after the
+ * direction is known (two gang exchanges per step, 2 J + 1 per frame);
+ * 1: the gradient pass also reduces the k (k + 1) / 2 entries of H, and the
+ * direction, d^T H d and the step follow from the one (wide) exchange
+ * (J + 1 per frame; k (k + 1) / 2 more multiply-adds per entry).  The same
+ * method: the two agree to float32 rounding of the sums.  Schedule 1 needs
+ * float32 storage (PROS_EUNSUPPORTED otherwise) and a tagged exchange
+ * (sync_mode 1..3).  The IRLS solver (ysolve = 2) always reduces H.
+ * Synchronises; the tile (rows per thread) is kept. */
+PROS_API pros_status pros_set_curvature(pros_handle* h, int32_t schedule);
 
 /* Diagnostics: record wall-clock timestamps (64 per workgroup tile, int64,
  * device memory of at least 64 * workgroups entries) around every gang-wide

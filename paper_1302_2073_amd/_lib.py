@@ -55,7 +55,8 @@ class pros_stats(C.Structure):
 
 class pros_launch_info(C.Structure):
     _fields_ = [("workgroups", C.c_int32), ("threads", C.c_int32), ("rows_per_thread", C.c_int32),
-                ("pixels_per_wg", C.c_int32), ("barriers_per_frame", C.c_int32), ("sync_mode", C.c_int32)]
+                ("pixels_per_wg", C.c_int32), ("barriers_per_frame", C.c_int32), ("sync_mode", C.c_int32),
+                ("curvature", C.c_int32)]
 
 
 class pros_batch_config(C.Structure):
@@ -87,6 +88,7 @@ _SIGS = {
     "pros_reorthonormalize": (C.c_int, [C.c_void_p]),
     "pros_get_launch_info": (C.c_int, [C.c_void_p, C.POINTER(pros_launch_info)]),
     "pros_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pros_set_curvature": (C.c_int, [C.c_void_p, C.c_int32]),
     "pros_debug_trace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pros_set_preprocess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "pros_set_score_output": (C.c_int, [C.c_void_p, C.c_void_p]),

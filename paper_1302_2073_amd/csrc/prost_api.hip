@@ -181,9 +181,14 @@ int prost_host::tile_pixels(int storage, int NR, int channels, double scale) {
   return tpw;
 }
 
+// The frame's steps reduce H with the gradient (IRLS, or CG under the
+// one-exchange curvature schedule): wide exchange slots, optional-feature
+// kernels.
+static bool wide_exchange(const pros_handle* h) { return h->prm.ysolve == 2 || h->curv == 1; }
+
 size_t prost_host::part_bytes(const pros_handle* h, int G) {
   size_t d = (2 * (size_t)G + prost::kExtraSlots) * prost::kSlot;
-  if (h->prm.ysolve == 2) d += ((size_t)G + 16) * prost::kWideMax;
+  if (wide_exchange(h)) d += ((size_t)G + 16) * prost::kWideMax;
   return sizeof(double) * d;
 }
 
@@ -202,7 +207,7 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
   int bestNR = 0, bestG = 0, bestT = 0;
   for (int NR : nrs) {
     if (force_nr > 0 && NR != force_nr) continue;
-    const bool ext = h->prm.preprocess != 0 || h->score != nullptr || h->prm.ysolve == 2;
+    const bool ext = h->prm.preprocess != 0 || h->score != nullptr || wide_exchange(h);
     const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, ext)
                                                   : prost::frame_kernel_f32(h->k, NR, ext);
     if (!f) continue;
@@ -481,6 +486,7 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.weights_from_filtered = p.weights_from_filtered;
   a.timeout = h->timeout_ticks;
   a.sync_mode = h->sync_mode;
+  a.curv = h->curv;
   a.trace = h->trace;
   a.pair_aligned = (pair_layout(h) && ((uintptr_t)x & 3u) == 0) ? 1 : 0;
   a.pre_mean = h->pre_mean;
@@ -590,8 +596,9 @@ pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
   out->threads = prost::kBlock;
   out->rows_per_thread = h->NR;
   out->pixels_per_wg = h->tpw;
-  out->barriers_per_frame = 2 * h->prm.cg_iters + 1;
+  out->barriers_per_frame = (wide_exchange(h) ? 1 : 2) * h->prm.cg_iters + 1;
   out->sync_mode = h->sync_mode;
+  out->curvature = h->curv;
   return PROS_OK;
 }
 
@@ -608,7 +615,8 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
   if (sync_mode < 0 || sync_mode > 3) return fail(PROS_EINVAL, "sync_mode must be 0..3");
-  if (sync_mode == 0 && h->prm.ysolve == 2) return fail(PROS_EINVAL, "the IRLS step needs a tagged exchange (sync_mode 1..3)");
+  if (sync_mode == 0 && wide_exchange(h))
+    return fail(PROS_EINVAL, "the wide exchange (IRLS, curvature schedule 1) needs a tagged exchange (sync_mode 1..3)");
   if (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 && rows_per_thread != 4 &&
       rows_per_thread != 8 && rows_per_thread != 16 && rows_per_thread != 32)
     return fail(PROS_EINVAL, "rows_per_thread must be 0 (automatic), 1, 2, 4, 8, 16 or 32");
@@ -627,6 +635,33 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
     }
   }
   h->sync_mode = sync_mode;
+  return prost_host::reset_exchange(h);
+}
+
+pros_status pros_set_curvature(pros_handle* h, int32_t schedule) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (schedule != 0 && schedule != 1) return fail(PROS_EINVAL, "curvature schedule must be 0 or 1");
+  if (schedule == 1 && h->prm.storage != PROS_F32)
+    return fail(PROS_EUNSUPPORTED, "curvature schedule 1 needs float32 storage");
+  if (schedule == 1 && h->sync_mode == 0)
+    return fail(PROS_EINVAL, "curvature schedule 1 needs a tagged exchange (sync_mode 1..3)");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int old = h->curv;
+  h->curv = schedule;
+  st = choose_launch(h, h->NR);   // same tile; kernel with or without the wide exchange
+  if (st != PROS_OK) {
+    h->curv = old;
+    return st;
+  }
+  (void)hipFree(h->part);        // the wide exchange has its own slots
+  h->part = nullptr;
+  hipError_t e = hipMalloc((void**)&h->part, prost_host::part_bytes(h, h->G));
+  if (e != hipSuccess) {
+    h->broken = true;
+    h->broken_status = PROS_ENOMEM;
+    return fail(PROS_ENOMEM, "partials: %s", hipGetErrorString(e));
+  }
   return prost_host::reset_exchange(h);
 }
 

@@ -59,6 +59,8 @@ struct FrameArgs {
   int sync_mode;         // 0: counter barrier + all-read, 1: tagged gather/broadcast,
                          // 2: two-level tagged gather (groups of tiles with equal t % 8),
                          // 3: every workgroup reads all tagged partials
+  int curv;              // curvature schedule of a CG step: 0 = d^T H d in a second pass
+                         // and exchange, 1 = H reduced with the gradient (one wide exchange)
 };
 
 constexpr int kReplicas = 8;      // copies of a gathered result (spread the pollers)
@@ -88,7 +90,7 @@ struct KSpace {
 };
 
 // Workgroup-shared scratch of one frame tile (sized for the largest k / NR).
-// Wide exchange of the IRLS step: g, f and the upper triangle of H
+// Wide exchange (IRLS step, one-exchange curvature schedule): g, f and the upper triangle of H
 // (K + 1 + K (K + 1) / 2 <= 153 values) in vectors of kWideMax float64.
 constexpr int kWideChunks = 5;
 constexpr int kWideMax = kWideChunks * kSlot;
@@ -101,8 +103,8 @@ struct FrameSmem {
   double big[kBlock];          // one float64 per thread (gathers)
   int ctl[4];
   uint8_t flag[kBlock * kMaxNR];
-  double wide_in[kWideIn];     // IRLS: this workgroup's partials
-  double wide_out[kWideMax];   // IRLS: gang totals
+  double wide_in[kWideIn];     // wide exchange: this workgroup's partials
+  double wide_out[kWideMax];   // wide exchange: gang totals
   double hs[kMaxK][kMaxK + 1]; // IRLS: augmented [H | -g] for the k-space solve
 };
 
@@ -626,7 +628,7 @@ __device__ __forceinline__ void cg_direction(const FrameArgs& a, KSpace<kMaxK>& 
   __syncthreads();
 }
 
-// ---- IRLS step (Step 1 variant): d = -H^{-1} g, one exchange per step ----
+// ---- steps with H reduced alongside the gradient (one wide exchange per step) ----
 
 // Upper-triangle pair p -> (row, column) of a K x K matrix, row-major.
 __host__ __device__ constexpr int tri_row(int p, int K) {
@@ -778,6 +780,36 @@ __device__ __forceinline__ void irls_advance(const FrameArgs& a, KSpace<kMaxK>& 
   if (lead && tid == 0) a.stats->alpha[it] = 1.0;
 }
 
+// CG step of the one-exchange curvature schedule: g and f come from the wide
+// totals in sm.wide_out (with the upper triangle of H = U^T diag(w c) U);
+// the direction is the one cg_direction forms, and d^T H d is summed from
+// the reduced H in a fixed order (lane i: row i of H times d, then the
+// 16-lane sum), into ks.red[K + 1].  Same value, up to rounding, as the
+// second pass sum_e w c (u_e . d)^2.
+template <int K>
+__device__ __forceinline__ void wide_cg_direction(const FrameArgs& a, FrameSmem& sm, int it, bool lead,
+                                                  int& restarts) {
+  KSpace<kMaxK>& ks = sm.ks;
+  const double* tot = sm.wide_out;
+  const int tid = thread_index(), lane = tid & 63;
+  if (tid <= K) ks.red[tid] = tot[tid];
+  __syncthreads();
+  cg_direction<K>(a, ks, it, lead, restarts);
+  if (tid < 64) {
+    double t = 0.0;
+    if (lane < K) {
+      for (int j = 0; j < K; ++j) {
+        const int lo = min(lane, j), hi = max(lane, j);
+        t = fma(tot[K + 1 + lo * K - lo * (lo - 1) / 2 + (hi - lo)], ks.d[j], t);
+      }
+      t *= ks.d[lane];
+    }
+    const double dhd = row16_sum(t);
+    if (lane == 0) ks.red[K + 1] = dhd;
+  }
+  __syncthreads();
+}
+
 // Majoriser step along d: alpha = -g.d / d^T H d, y += alpha d.  Returns
 // alpha as float for the residual update.
 template <int K>
@@ -881,7 +913,7 @@ __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSp
 // ---------------------------------------------------------------------------
 // float32 storage: row q = tid + s * kBlock of the tile, K floats per row
 // ---------------------------------------------------------------------------
-template <int K, int NR, bool EXT, bool IRLS>
+template <int K, int NR, bool EXT, bool WIDE>
 __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
@@ -943,20 +975,29 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, u[s][j], acc[j]);
     }
-    if (IRLS && a.ysolve == 2) {   // IRLS: g, f and H in one (wide) exchange, step -H^{-1} g
+    if (WIDE && (a.ysolve == 2 || a.curv == 1)) {   // g, f and H in one (wide) exchange
       wg_reduce<K + 1>(acc, sm.red, sm.wide_in);
       irls_h_partials<K, NR>(cw, [&](int i, int j) { return u[i][j]; }, [] {}, sm);
       if (!gang_reduce_wide(sm.wide_in, K + 1 + K * (K + 1) / 2, a, tile, nbar, ctx.ebase, sm.big, sm.wide_out))
         return false;
-      irls_direction<K>(a, sm, it, ctx.lead);
-      if (ks.flag[0]) break;
-      irls_advance<K>(a, ks, it, ctx.lead);
+      float af = 1.0f;
+      if (a.ysolve == 2) {   // IRLS: unit step along -H^{-1} g
+        irls_direction<K>(a, sm, it, ctx.lead);
+        if (ks.flag[0]) break;
+        irls_advance<K>(a, ks, it, ctx.lead);
+      } else {               // CG / gradient descent with d^T H d from the reduced H
+        wide_cg_direction<K>(a, sm, it, ctx.lead, restarts);
+        if (ks.flag[0]) break;
+        const double dHd = ks.red[K + 1];
+        if (!(dHd > 0.0)) break;
+        af = cg_advance<K>(a, ks, dHd, it, ctx.lead);
+      }
 #pragma unroll
       for (int s = 0; s < NR; ++s) {
         float t = 0.f;
 #pragma unroll
         for (int j = 0; j < K; ++j) t = fmaf(u[s][j], ks.df[j], t);
-        r[s] -= t;
+        r[s] = fmaf(-af, t, r[s]);
       }
       ++steps;
       __syncthreads();
@@ -1304,16 +1345,18 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 // Returns false when the gang aborted.
 // EXT: the optional features are compiled in (pre-processing when the
 // stream has its statistics, per-entry label scores when a score buffer is
-// given); without it the hot path carries none of their code.  IRLS: the
-// IRLS Step 1 variant is compiled in as well (float32 tiles of the
-// single-stream kernel only; its H partials would spill the packed tile).
-template <int K, int NR, typename TS, bool EXT, bool IRLS = false>
+// given); without it the hot path carries none of their code.  WIDE: the
+// steps that reduce H with the gradient in one wide exchange (the IRLS
+// variant and the one-exchange curvature schedule of CG) are compiled in as
+// well: float32 tiles of the single-stream kernel only, as the H partials
+// would spill the packed tile and the batch kernel's registers.
+template <int K, int NR, typename TS, bool EXT, bool WIDE = false>
 __device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   if constexpr (sizeof(TS) == 2) {
     static_assert(NR % 2 == 0, "bfloat16 tiles hold row pairs");
     return frame_tile_packed<K, NR / 2, EXT>(a, tile, sm);
   } else {
-    return frame_tile<K, NR, EXT, IRLS>(a, tile, sm);
+    return frame_tile<K, NR, EXT, WIDE>(a, tile, sm);
   }
 }
 

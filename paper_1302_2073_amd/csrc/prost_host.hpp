@@ -32,6 +32,7 @@ struct pros_handle {
   const void* kfn = nullptr;
   int G = 0, tpw = 0, NR = 0;
   int sync_mode = 2;       // 0: counter barrier, 1: tagged gather/broadcast, 2: two-level tagged, 3: tagged all-read
+  int curv = 0;            // CG curvature schedule: 0 = second pass per step, 1 = H with the gradient
   long long* trace = nullptr;   // optional per-tile timestamps (diagnostics)
   bool mask_stale = true;       // mask not yet computed from the latest labels
   long long timeout_ticks = 0;

@@ -199,10 +199,15 @@ class Tracker:
         L.check(L.lib().pros_get_launch_info(self._h, C.byref(li)))
         return dict(workgroups=li.workgroups, threads=li.threads, rows_per_thread=li.rows_per_thread,
                     pixels_per_wg=li.pixels_per_wg, barriers_per_frame=li.barriers_per_frame,
-                    sync_mode=li.sync_mode)
+                    sync_mode=li.sync_mode, curvature=li.curvature)
 
     def set_launch(self, rows_per_thread=0, sync_mode=2):
         L.check(L.lib().pros_set_launch(self._h, int(rows_per_thread), int(sync_mode)))
+
+    def set_curvature(self, schedule):
+        """0: d^T H d in a second pass per CG step; 1: H reduced with the
+        gradient (one exchange per step, float32 storage)."""
+        L.check(L.lib().pros_set_curvature(self._h, int(schedule)))
 
 
 def bf16_bits(a):

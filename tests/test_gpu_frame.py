@@ -54,10 +54,12 @@ def test_vga_rgb_step(frame):
     assert_parity(rep)
 
 
+@pytest.mark.parametrize("curvature", [0, 1])
 @pytest.mark.parametrize("cost", ["lp", "log"])
 @pytest.mark.parametrize("shape", [(7, 5, 3, 4), (33, 17, 1, 1), (41, 29, 2, 16), (123, 77, 3, 9)])
-def test_random_shapes(shape, cost):
-    """Ragged sizes, k = 1 and k = 16, 1-3 channels, both cost forms."""
+def test_random_shapes(shape, cost, curvature):
+    """Ragged sizes, k = 1 and k = 16, 1-3 channels, both cost forms, both
+    curvature schedules (k = 16: the widest exchange, 153 values)."""
     W, H, Cc, k = shape
     rank = min(k, 3)
     spec = V.VideoSpec(W, H, Cc, rank=rank, seed=30 + W, noise=0.01, fg_kind="rects",
@@ -68,8 +70,9 @@ def test_random_shapes(shape, cost):
     st = O.initial_state(V.initial_subspace(prm.m, k, 3), prm.P)
     for n in range(6):
         st, _ = O.track_frame(st, f32(sv.frame(n)), prm)
-    say(f"random shape {shape} cost {cost}")
+    say(f"random shape {shape} cost {cost} curvature {curvature}")
     with _tracker(prm) as trk:
+        trk.set_curvature(curvature)
         rep = compare_step(trk, prm, st, f32(sv.frame(6)))
     assert_parity(rep)
 
@@ -235,3 +238,71 @@ def test_irls_small_gray_ragged(frame):
     with _tracker(prm) as trk:
         rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
     assert_parity(rep)
+
+
+def _curv_tracker(prm, nr=0, sync_mode=2):
+    trk = _tracker(prm)
+    if nr or sync_mode != 2:
+        trk.set_launch(nr, sync_mode)
+    trk.set_curvature(1)
+    return trk
+
+
+@pytest.mark.parametrize("over", [(), (("ysolve", "gd"),), (("p", 1.0),), (("cost", "log"),)])
+def test_curvature_schedule_qvga(over):
+    """CG with H reduced alongside the gradient (one exchange per step)
+    against the oracle, which forms d^T H d from H: 320x240x3, k = 10."""
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 8, over)
+    with _curv_tracker(prm) as trk:
+        info = trk.launch_info()
+        say(f"qvga curvature 1 {dict(over)} {info}")
+        assert info["curvature"] == 1 and info["barriers_per_frame"] == prm.cg_iters + 1
+        rep = compare_step(trk, prm, states[8], f32(sv.frame(8)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("sync_mode", [1, 3])
+@pytest.mark.parametrize("nr", [1, 4, 8])
+def test_curvature_schedule_launch_variants(nr, sync_mode):
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 12)
+    with _curv_tracker(prm, nr, sync_mode) as trk:
+        say(f"qvga curvature 1 launch {trk.launch_info()}")
+        rep = compare_step(trk, prm, states[12], f32(sv.frame(12)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("frame", [0, 1, 57, 199])
+def test_curvature_schedule_small_gray(frame):
+    wl, prm, sv, states = oracle_trajectory("small_gray", frame)
+    with _curv_tracker(prm) as trk:
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
+    assert_parity(rep)
+
+
+def test_curvature_schedule_vga():
+    """The benchmark's frame shape, 640x480x3, k = 15 (8 rows per thread)."""
+    wl, prm, sv, states = oracle_trajectory("vga_rgb", 3)
+    with _curv_tracker(prm) as trk:
+        say(f"vga curvature 1 {trk.launch_info()}")
+        rep = compare_step(trk, prm, states[3], f32(sv.frame(3)))
+    assert_parity(rep)
+
+
+def test_curvature_schedule_refusals():
+    from paper_1302_2073_amd._lib import ProstError
+    wl, prm, sv, states = oracle_trajectory("small_gray", 0)
+    with _tracker(prm, "bf16") as trk:
+        with pytest.raises(ProstError):
+            trk.set_curvature(1)
+    with _tracker(prm) as trk:
+        trk.set_launch(0, 0)
+        with pytest.raises(ProstError):
+            trk.set_curvature(1)
+        trk.set_launch(0, 2)
+        trk.set_curvature(1)
+        with pytest.raises(ProstError):
+            trk.set_launch(0, 0)
+        with pytest.raises(ProstError):
+            trk.set_curvature(2)
+        trk.set_curvature(0)
+        assert trk.launch_info()["barriers_per_frame"] == 2 * prm.cg_iters + 1
