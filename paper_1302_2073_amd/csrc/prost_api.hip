@@ -199,15 +199,34 @@ bool prost_host::pair_layout(const pros_handle* h) {
 // Register rows per thread for a single stream.  A frame is latency-bound
 // (its gang-wide exchanges), so the fastest tile is the smallest one whose
 // gang still fits one workgroup per compute unit: more rows per thread only
-// add work per workgroup.  Frames too large for that take the largest tile
-// that is resident.  force_nr > 0 asks for one row count.
+// add work per workgroup.  A frame that fits one workgroup takes that tile
+// instead (its reductions stay inside the workgroup, no memory round trip).
+// Frames too large for that take the largest tile that is resident.
+// force_nr > 0 asks for one row count.
 static pros_status choose_launch(pros_handle* h, int force_nr) {
   const int nrs[] = {1, 2, 4, 8, 16, 32};
   const void* best = nullptr;
   int bestNR = 0, bestG = 0, bestT = 0;
+  const bool ext = h->prm.preprocess != 0 || h->score != nullptr || wide_exchange(h);
+  if (force_nr == 0) {
+    for (int NR : nrs) {
+      const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, ext)
+                                                    : prost::frame_kernel_f32(h->k, NR, ext);
+      if (!f || prost::kBlock * NR < h->C) continue;
+      const int tpw = prost_host::tile_pixels(h->prm.storage, NR, h->C, 1.0);
+      if (tpw < h->P) continue;
+      int occ = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0));
+      if (occ < 1) continue;
+      h->kfn = f;
+      h->NR = NR;
+      h->G = 1;
+      h->tpw = tpw;
+      return PROS_OK;
+    }
+  }
   for (int NR : nrs) {
     if (force_nr > 0 && NR != force_nr) continue;
-    const bool ext = h->prm.preprocess != 0 || h->score != nullptr || wide_exchange(h);
     const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, ext)
                                                   : prost::frame_kernel_f32(h->k, NR, ext);
     if (!f) continue;

@@ -366,6 +366,11 @@ __device__ __forceinline__ bool gang_reduce_wide(const double* in, int LT, const
                                                  int& nbar, unsigned ebase, double* s_big, double* out) {
   const int tid = thread_index();
   ++nbar;
+  if (a.G == 1) {   // a gang of one workgroup: its sums are the totals
+    for (int q = tid; q < LT; q += kBlock) out[q] = in[q];
+    __syncthreads();
+    return true;
+  }
   const unsigned ep = (ebase + (unsigned)nbar) & 0xFFu;
   const int x = tile & 7;
   const int ngrp = min(8, a.G);
@@ -453,6 +458,11 @@ template <int L>
 __device__ __forceinline__ bool gang_reduce_impl(float (&acc)[L], const FrameArgs& a, const int tile, int& nbar,
                                                  unsigned base, unsigned ebase, FrameSmem& sm, double* s_out,
                                                  bool fenced) {
+  if (a.G == 1) {   // a gang of one workgroup: its sums are the totals, no memory exchange
+    ++nbar;
+    wg_reduce<L>(acc, sm.red, s_out);
+    return true;
+  }
   if (a.sync_mode == 1) {
     wg_reduce<L>(acc, sm.red, sm.wg);
     return gang_reduce_tagged<L>(sm.wg, a, tile, nbar, ebase, sm.big, s_out, sm.ctl, fenced);
@@ -900,7 +910,9 @@ __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSp
         a.pre_stat[1] = a.pre_stat[1] + 1.0;
       }
     }
-    if (a.sync_mode != 0)
+    if (a.G == 1) {
+      // a one-workgroup gang used no slots or counters: the bases stay
+    } else if (a.sync_mode != 0)
       __hip_atomic_store(&a.sync[3], t.ebase + (unsigned)nbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
       __hip_atomic_store(&a.sync[1], t.base + (unsigned)a.G * (unsigned)nbar, __ATOMIC_RELAXED,

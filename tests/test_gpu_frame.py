@@ -25,10 +25,27 @@ def _tracker(prm, storage="f32"):
 
 @pytest.mark.parametrize("frame", [0, 1, 2, 10, 57, 120, 199])
 def test_small_gray_step(frame):
+    """80x60x1, k = 5: the whole frame fits one workgroup (16 rows per
+    thread), so every reduction stays inside it."""
     wl, prm, sv, states = oracle_trajectory("small_gray", 199)
     say(f"small_gray frame {frame}")
     with _tracker(prm) as trk:
-        say("  launch", trk.launch_info())
+        info = trk.launch_info()
+        say("  launch", info)
+        assert info["workgroups"] == 1
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("sync_mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("frame", [1, 57])
+def test_small_gray_multi_workgroup(frame, sync_mode):
+    """The same frames split over a gang of 10 workgroups (one row per
+    thread) under each exchange protocol."""
+    wl, prm, sv, states = oracle_trajectory("small_gray", 57)
+    with _tracker(prm) as trk:
+        trk.set_launch(1, sync_mode)
+        assert trk.launch_info()["workgroups"] == 10
         rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
     assert_parity(rep)
 
