@@ -358,6 +358,59 @@ PROS_API pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, in
  * Synchronises; the tile (rows per thread) is kept. */
 PROS_API pros_status pros_set_curvature(pros_handle* h, int32_t schedule);
 
+/* ---------------------------------------------------------------------------
+ * Video ingest.  Sec. 5.1 re-samples every sequence to one small resolution
+ * (160 x 120) before tracking; Sec. 5.3 brings the mask computed at the
+ * small size back up for evaluation.
+ *
+ * pros_resample_rgb8: `src` (device) holds an interleaved 8-bit frame,
+ * src_h rows of src_w pixels of `channels` (1..4) bytes, rows src_row_stride
+ * bytes apart (as a video decoder writes it).  `dst` (device, m =
+ * channels * dst_w * dst_h entries of dst_dtype, PROS_F32 or PROS_BF16)
+ * receives the tracker's planar frame: for each channel plane and
+ * destination pixel, scale times the mean of the source over the pixel's
+ * footprint (area averaging; the source is piecewise constant over its
+ * pixels).  Weights are exact integers and the sums exact, so the value is
+ * the correctly rounded float64 mean, rounded once to float32 (then to
+ * nearest-even bfloat16).  Any sizes 1..32768 (shrinking or enlarging).
+ * Asynchronous on hip_stream; PROS_EINVAL for bad sizes or NULL pointers,
+ * before any device work.
+ *
+ * pros_mask_upsample: `mask` (device, height x width bytes) to `out`
+ * (device, out_h x out_w bytes) by nearest neighbour: out pixel (i, j)
+ * copies the source pixel containing its centre, row
+ * floor((2i+1) height / (2 out_h)), column floor((2j+1) width / (2 out_w)).
+ * Asynchronous on hip_stream.
+ *
+ * pros_ingest: frames from host memory, pipelined.  pros_ingest_init binds
+ * a pipeline to a tracker whose frame is the resampled size (its
+ * width x height, its channels) for source frames src_w x src_h
+ * (interleaved 8-bit, rows packed), with `slots` (1..16) pinned host
+ * buffers and device buffers and its own copy stream.  pros_ingest_slot
+ * hands out the next pinned buffer to fill (waits only if that buffer's
+ * previous copy is still in flight); pros_ingest_submit copies it to the
+ * device on the copy stream and queues resample + pros_track_frame on the
+ * tracker's stream behind the copy (events order the two streams), so the
+ * copy of the next frame overlaps the tracking of this one.
+ * pros_ingest_push = slot + memcpy + submit.  pros_ingest_mask writes the
+ * latest mask (filtered = 1: 3x3 median, 0: raw labels) upsampled to the
+ * source size (src_w x src_h bytes; device when on_device, queued; host
+ * otherwise, synchronises).  The pipeline owns its buffers; destroy it
+ * before its tracker.  Not thread-safe. */
+typedef struct pros_ingest pros_ingest;
+PROS_API pros_status pros_resample_rgb8(const uint8_t* src, int32_t src_w, int32_t src_h, int32_t channels,
+                                        int64_t src_row_stride, void* dst, int32_t dst_dtype, int32_t dst_w,
+                                        int32_t dst_h, double scale, void* hip_stream);
+PROS_API pros_status pros_mask_upsample(const uint8_t* mask, int32_t width, int32_t height, uint8_t* out,
+                                        int32_t out_w, int32_t out_h, void* hip_stream);
+PROS_API pros_status pros_ingest_init(pros_handle* h, int32_t src_w, int32_t src_h, int32_t slots, double scale,
+                                      pros_ingest** out);
+PROS_API pros_status pros_ingest_slot(pros_ingest* g, uint8_t** host_slot);
+PROS_API pros_status pros_ingest_submit(pros_ingest* g);
+PROS_API pros_status pros_ingest_push(pros_ingest* g, const uint8_t* frame_rgb8);
+PROS_API pros_status pros_ingest_mask(pros_ingest* g, uint8_t* out, int32_t filtered, int32_t on_device);
+PROS_API void pros_ingest_destroy(pros_ingest* g);
+
 /* Diagnostics: record wall-clock timestamps (64 per workgroup tile, int64,
  * device memory of at least 64 * workgroups entries) around every gang-wide
  * exchange of the following frames; NULL stops recording. */

@@ -446,6 +446,53 @@ def track_frame(state: State, x, prm: Params):
 
 
 # ---------------------------------------------------------------------------
+# Video ingest: every sequence is re-sampled to one small resolution before
+# tracking (Sec. 5.1, 160 x 120), and the mask is brought back to the
+# source resolution for evaluation (Sec. 5.3, "Subspace dimension")
+# ---------------------------------------------------------------------------
+
+def _box_weights(n_src, n_dst):
+    """W[i, s] = length of the overlap of source cell [s, s+1) with the
+    footprint [i*n_src/n_dst, (i+1)*n_src/n_dst) of destination cell i,
+    divided by the footprint length (rows of W sum to 1)."""
+    step = n_src / n_dst
+    W = np.zeros((n_dst, n_src))
+    for i in range(n_dst):
+        a, b = i * step, (i + 1) * step
+        for s in range(int(math.floor(a)), min(n_src, int(math.ceil(b)))):
+            W[i, s] = max(0.0, min(b, s + 1.0) - max(a, float(s)))
+    return W / step
+
+
+def resample_area(img, dst_w, dst_h, scale=1.0 / 255.0):
+    """READING: the paper re-samples every video to 160 x 120 without naming
+    the filter; taken as area averaging (each destination pixel is the mean
+    of the source image, piecewise constant over its pixels, over the
+    destination pixel's footprint), the filter that neither aliases nor
+    drops pixels when shrinking.  img: H x W x C (interleaved, e.g. uint8
+    RGB as a decoder delivers it).  Returns the tracker's frame layout:
+    C planes of dst_h x dst_w, times `scale`, flattened (entry c*P + p)."""
+    a = np.asarray(img, dtype=np.float64)
+    if a.ndim == 2:
+        a = a[:, :, None]
+    H, W, C = a.shape
+    Wy, Wx = _box_weights(H, dst_h), _box_weights(W, dst_w)
+    planes = [Wy @ a[:, :, c] @ Wx.T for c in range(C)]
+    return (scale * np.stack(planes)).reshape(-1)
+
+
+def mask_upsample(mask, width, height, out_w, out_h):
+    """READING: the mask is brought to a larger (or any) resolution by
+    nearest neighbour: output pixel (i, j) takes the label of the source
+    pixel that contains its centre ((i + 1/2) h / out_h, (j + 1/2) w / out_w),
+    in exact integer arithmetic."""
+    m = np.asarray(mask, dtype=np.uint8).reshape(height, width)
+    rows = [((2 * i + 1) * height) // (2 * out_h) for i in range(out_h)]
+    cols = [((2 * j + 1) * width) // (2 * out_w) for j in range(out_w)]
+    return m[np.ix_(rows, cols)].reshape(-1)
+
+
+# ---------------------------------------------------------------------------
 # Segmentation quality against a ground-truth mask (the measures of Sec. 5,
 # changedetection.net: Recall, Specificity, FPR, FNR, PWC, Precision,
 # F-measure) and the threshold sweep behind its ROC curves

@@ -96,6 +96,17 @@ _SIGS = {
     "pros_roc_counts": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                   C.c_void_p, C.c_void_p]),
     "pros_get_preprocess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pros_resample_rgb8": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_void_p, C.c_int32,
+                                     C.c_int32, C.c_int32, C.c_double, C.c_void_p]),
+    "pros_mask_upsample": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_int32,
+                                     C.c_void_p]),
+    "pros_ingest_init": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                   C.POINTER(C.c_void_p)]),
+    "pros_ingest_slot": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pros_ingest_submit": (C.c_int, [C.c_void_p]),
+    "pros_ingest_push": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "pros_ingest_mask": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    "pros_ingest_destroy": (None, [C.c_void_p]),
     "pros_batch_init": (C.c_int, [C.POINTER(pros_params), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pros_batch_destroy": (None, [C.c_void_p]),
     "pros_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),

@@ -220,3 +220,69 @@ def lpcost_batch(m=230400, k=10, B=32, seed=5, weighted=False):
     else:
         w = np.ones(m)
     return U, Y, X, w
+
+
+# ---------------------------------------------------------------------------
+# Camera-like 8-bit source frames for the ingest path
+# ---------------------------------------------------------------------------
+
+class CameraVideo:
+    """Interleaved 8-bit frames (H x W x C bytes, as a video decoder writes
+    them) at the source resolution: a smooth static scene in [0.2, 0.8],
+    `rank` smooth illumination patterns of amplitude 0.06 modulated by
+    periodic coefficients, moving rectangles with U[0,1] texture, additive
+    N(0, noise^2) (in units of the full range), quantised to 0..255.  The
+    ground truth is the set of rectangle pixels.  Frame n is regenerated
+    from (seed, n) alone."""
+
+    def __init__(self, width, height, channels=3, rank=3, seed=0, fg_count=3, fg_density=0.05, noise=0.008,
+                 speed=(2.0, 6.0)):
+        self.width, self.height, self.channels = width, height, channels
+        self.seed, self.noise = seed, noise
+        rng = np.random.default_rng([seed, 0xCA])
+        yy = np.arange(height)[:, None] / height
+        xx = np.arange(width)[None, :] / width
+
+        def field():
+            f = np.zeros((channels, height, width))
+            for c in range(channels):
+                for _ in range(3):
+                    fy, fx = rng.uniform(0.3, 2.5, size=2)
+                    py, px = rng.uniform(0, 2 * math.pi, size=2)
+                    f[c] += np.cos(2 * math.pi * fy * yy + py) * np.cos(2 * math.pi * fx * xx + px)
+            lo, hi = f.min(), f.max()
+            return (f - lo) / (hi - lo) if hi > lo else np.zeros_like(f)
+
+        self.base = 0.2 + 0.6 * field()
+        self.patterns = [0.06 * (2.0 * field() - 1.0) for _ in range(rank)]
+        self.T = rng.uniform(40.0, 160.0, size=rank)
+        self.ph = rng.uniform(0.0, 2.0 * math.pi, size=rank)
+        self.objects = []
+        area = fg_density * width * height / max(fg_count, 1)
+        for _ in range(fg_count):
+            aspect = rng.uniform(0.6, 1.6)
+            bw = min(width, max(1, int(round(math.sqrt(area * aspect)))))
+            bh = min(height, max(1, int(round(area / bw))))
+            sp = rng.uniform(speed[0], speed[1])
+            ang = rng.uniform(0.0, 2.0 * math.pi)
+            self.objects.append(dict(w=bw, h=bh, x0=rng.uniform(0, width - bw), y0=rng.uniform(0, height - bh),
+                                     vx=sp * math.cos(ang), vy=sp * math.sin(ang),
+                                     tex=rng.uniform(0.0, 1.0, size=(channels, bh, bw))))
+
+    def frame(self, n, with_mask=False):
+        rng = np.random.default_rng([self.seed, 0xCB, int(n)])
+        img = self.base.copy()
+        for pat, T, ph in zip(self.patterns, self.T, self.ph):
+            img += math.sin(2.0 * math.pi * n / T + ph) * pat
+        mask = np.zeros((self.height, self.width), bool)
+        for o in self.objects:
+            px = int(round(_bounce(o["x0"], o["vx"], n, 0.0, self.width - o["w"])))
+            py = int(round(_bounce(o["y0"], o["vy"], n, 0.0, self.height - o["h"])))
+            img[:, py:py + o["h"], px:px + o["w"]] = o["tex"]
+            mask[py:py + o["h"], px:px + o["w"]] = True
+        img += self.noise * rng.standard_normal(img.shape)
+        q = np.clip(np.rint(255.0 * img), 0, 255).astype(np.uint8)
+        out = np.ascontiguousarray(np.moveaxis(q, 0, 2))
+        if with_mask:
+            return out, mask.reshape(-1)
+        return out

@@ -149,3 +149,26 @@ def test_host_quality_measures_agree_with_oracle_definitions():
         for k in b:
             assert (math.isnan(a[k]) and math.isnan(b[k])) or a[k] == pytest.approx(b[k])
 
+
+
+@pytest.mark.parametrize("sw,sh,c,stride,dt,dw,dh,scale", [
+    (0, 10, 3, 30, 0, 4, 4, 1.0), (10, 10, 5, 50, 0, 4, 4, 1.0), (10, 10, 3, 29, 0, 4, 4, 1.0),
+    (10, 10, 3, 30, 7, 4, 4, 1.0), (10, 10, 3, 30, 0, 0, 4, 1.0), (10, 10, 3, 30, 0, 4, 40000, 1.0),
+    (10, 10, 3, 30, 0, 4, 4, 0.0), (10, 10, 3, 30, 0, 4, 4, float("nan")),
+])
+def test_resample_rejects_bad_arguments_without_touching_the_gpu(sw, sh, c, stride, dt, dw, dh, scale):
+    L = _lib()
+    dummy = C.c_void_p(16)   # never dereferenced: validation comes first
+    assert L.lib().pros_resample_rgb8(dummy, sw, sh, c, stride, dummy, dt, dw, dh, scale, None) == L.PROS_EINVAL
+    assert L.last_error()
+
+
+def test_upsample_and_ingest_reject_bad_arguments_without_touching_the_gpu():
+    L = _lib()
+    dummy = C.c_void_p(16)
+    assert L.lib().pros_mask_upsample(dummy, 0, 4, dummy, 8, 8, None) == L.PROS_EINVAL
+    assert L.lib().pros_mask_upsample(None, 4, 4, dummy, 8, 8, None) == L.PROS_EINVAL
+    g = C.c_void_p(123)
+    assert L.lib().pros_ingest_init(None, 64, 48, 2, 1.0 / 255, C.byref(g)) == L.PROS_EINVAL
+    assert g.value is None
+    assert L.lib().pros_ingest_submit(None) == L.PROS_EINVAL

@@ -627,3 +627,66 @@ def test_irls_variant_is_monotone_and_reaches_a_stationary_point(p):
     g = -(U.T @ (w * O.dphi(x - U @ y, p, 1e-3)))
     g0 = -(U.T @ (w * O.dphi(x, p, 1e-3)))
     assert np.linalg.norm(g) <= 1e-6 * np.linalg.norm(g0)
+
+
+# --- video ingest: area re-sampling (Sec. 5.1) and mask upsampling (Sec. 5.3) ---
+
+def test_resample_integer_factor_is_the_block_mean():
+    """640x480 -> 160x120 (factor 4): each output pixel is the plain mean of
+    its 4 x 4 source block."""
+    rng = np.random.default_rng(11)
+    img = rng.integers(0, 256, size=(48, 64, 3), dtype=np.uint8)
+    out = O.resample_area(img, 16, 12, scale=1.0)
+    blocks = img.astype(np.float64).reshape(12, 4, 16, 4, 3).mean(axis=(1, 3))
+    np.testing.assert_allclose(out, np.moveaxis(blocks, 2, 0).reshape(-1), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("src,dst", [((7, 5), (3, 2)), ((5, 7), (4, 3)), ((3, 2), (7, 5)), ((11, 13), (11, 13)),
+                                     ((1, 1), (4, 3)), ((9, 4), (1, 1))])
+def test_resample_matches_supersampled_block_mean(src, dst):
+    """Any sizes: replicating every source pixel dst_h x dst_w times makes each
+    destination footprint an exact block of H x W cells, whose plain mean is
+    the area average (brute force on tiny inputs)."""
+    (W, H), (w, h) = src, dst
+    rng = np.random.default_rng(W * 100 + H)
+    img = rng.integers(0, 256, size=(H, W, 2), dtype=np.uint8)
+    big = np.repeat(np.repeat(img.astype(np.float64), h, axis=0), w, axis=1)
+    ref = big.reshape(h, H, w, W, 2).mean(axis=(1, 3))
+    out = O.resample_area(img, w, h, scale=1.0)
+    np.testing.assert_allclose(out, np.moveaxis(ref, 2, 0).reshape(-1), rtol=0, atol=1e-10)
+
+
+def test_resample_identity_constant_and_mass():
+    rng = np.random.default_rng(5)
+    img = rng.integers(0, 256, size=(10, 14, 3), dtype=np.uint8)
+    same = O.resample_area(img, 14, 10)
+    np.testing.assert_allclose(same, np.moveaxis(img, 2, 0).reshape(-1) / 255.0, rtol=0, atol=1e-15)
+    const = O.resample_area(np.full((9, 13, 1), 200, np.uint8), 5, 4)
+    np.testing.assert_allclose(const, 200 / 255.0, rtol=1e-15)
+    out = O.resample_area(img, 6, 7, scale=1.0).reshape(3, 7, 6)
+    # the integral over the image is preserved: mean of each plane unchanged
+    np.testing.assert_allclose(out.mean(axis=(1, 2)), img.astype(np.float64).mean(axis=(0, 1)), rtol=1e-12)
+
+
+def test_mask_upsample_integer_factor_replicates_pixels():
+    rng = np.random.default_rng(2)
+    m = (rng.random((6, 8)) < 0.3).astype(np.uint8)
+    out = O.mask_upsample(m.reshape(-1), 8, 6, 32, 24).reshape(24, 32)
+    np.testing.assert_array_equal(out, np.kron(m, np.ones((4, 4), np.uint8)))
+    np.testing.assert_array_equal(O.mask_upsample(m.reshape(-1), 8, 6, 8, 6), m.reshape(-1))
+
+
+def test_mask_upsample_picks_the_pixel_under_each_centre():
+    """Non-integer ratio: every output centre falls inside the source pixel
+    it copies (checked with exact fractions)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(4)
+    w, h, ow, oh = 7, 5, 16, 9
+    m = (rng.random(h * w) < 0.5).astype(np.uint8)
+    out = O.mask_upsample(m, w, h, ow, oh).reshape(oh, ow)
+    for i in range(oh):
+        for j in range(ow):
+            cy, cx = Fraction(2 * i + 1, 2) * Fraction(h, oh), Fraction(2 * j + 1, 2) * Fraction(w, ow)
+            r, c = int(cy), int(cx)
+            assert r <= cy < r + 1 and c <= cx < c + 1
+            assert out[i, j] == m[r * w + c]
