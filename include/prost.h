@@ -330,8 +330,11 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
                             float* dX, float* dU, float* dY, float* dmu,
                             void* workspace, size_t workspace_bytes, void* hip_stream);
 
-/* Launch tuning of a single-stream handle: rows_per_thread (0 = automatic:
- * the smallest tile whose gang fits one workgroup per compute unit; else
+/* Launch tuning of a single-stream handle.  pros_init chooses automatically:
+ * one workgroup if the frame fits one, else the smallest tile reaching a
+ * gang of <= 32 workgroups, else the smallest tile whose gang fits one
+ * workgroup per compute unit; exchange 3 for gangs of <= 64 workgroups, 2
+ * above.  This call overrides it: rows_per_thread (0 = automatic tile; else
  * 1, 2, 4, 8, 16 (k <= 8 for float32) or, for bfloat16 storage, whose tiles
  * hold row pairs, 2, 4, 8, 16 or 32 (k <= 8); the frame's pixels must fit
  * the resident workgroups) and the gang exchange used for the frame's
@@ -339,7 +342,7 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
  * 0 = one arrival counter per gang and every workgroup reading all partial
  * sums, 1 = epoch-tagged partial sums gathered by the gang's first
  * workgroup and broadcast back, 2 = the same in two levels (groups of
- * tiles t = x mod 8; every workgroup reads the 8 group sums; default),
+ * tiles t = x mod 8; every workgroup reads the 8 group sums),
  * 3 = every workgroup reads all tagged partials (one hop, G^2 reads).
  * Results agree to float64 rounding.
  * Synchronises. */

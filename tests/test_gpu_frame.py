@@ -323,3 +323,26 @@ def test_curvature_schedule_refusals():
             trk.set_curvature(2)
         trk.set_curvature(0)
         assert trk.launch_info()["barriers_per_frame"] == 2 * prm.cg_iters + 1
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_small_gang_automatic_launch(storage):
+    """160x120x3 at k = 15 (the resolution Sec. 5.1 tracks at): the automatic
+    launch takes a gang of <= 32 workgroups with every workgroup reading all
+    partials; parity against the oracle at that launch."""
+    spec = V.VideoSpec(160, 120, 3, rank=10, seed=44, noise=0.01, fg_kind="rects", fg_count=3, fg_density=0.05)
+    sv = V.SyntheticVideo(spec)
+    prm = O.Params(160, 120, 3, k=15, mu=1e-3, t_init=5e-3, t_min=1e-4, i_init=20)
+    st = O.initial_state(V.initial_subspace(prm.m, 15, 4), prm.P)
+    for n in range(4):
+        st, _ = O.track_frame(st, f32(sv.frame(n)), prm)
+    with _tracker(prm, storage) as trk:
+        info = trk.launch_info()
+        say(f"160x120x3 {storage} launch {info}")
+        assert info["workgroups"] <= 32 and info["sync_mode"] == 3
+        if storage == "f32":
+            rep = compare_step(trk, prm, st, f32(sv.frame(4)))
+            assert_parity(rep)
+        else:
+            from test_gpu_precision import _bf16_check, rne_bf16
+            _bf16_check(trk, prm, st, rne_bf16(sv.frame(4)), "160x120x3 small gang")
