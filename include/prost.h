@@ -257,7 +257,11 @@ PROS_API pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out)
 typedef struct pros_batch pros_batch;
 
 typedef struct pros_batch_config {
-  int32_t register_budget;   /* floats of U held in registers per thread: 64 or 128 */
+  int32_t register_budget;   /* floats of U held in registers per thread: 64 or 128;
+                                192 = the LDS form (bfloat16, k class 10..16, default
+                                features): the 128 tile in registers plus 3-4
+                                row pairs per thread in LDS (one workgroup per
+                                CU) */
   int32_t workgroups_per_cu; /* resident workgroups per CU used by the launch */
   double tile_scale;         /* (0, 1]: fraction of the register tile each workgroup fills */
   int32_t strategy;          /* 0: gangs packed by decreasing size, 1: in stream order */

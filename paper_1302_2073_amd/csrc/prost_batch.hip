@@ -45,7 +45,7 @@ using prost::FrameArgs;
 #define fail prost_host::set_error
 
 namespace {
-constexpr int kBudgets[] = {64, 128};
+constexpr int kBudgets[] = {64, 128, prost::kBudgetLds};
 }  // namespace
 
 struct pros_batch {
@@ -112,9 +112,11 @@ static pros_status build_schedule(pros_batch* b) {
   for (int s : order) {
     const int G = b->hs[s]->G;
     if (G > nwg) return fail(PROS_EUNSUPPORTED, "stream %d needs %d resident workgroups, the launch has %d", s, G, nwg);
-    // gangs start at a multiple of 8 slots (tile t on a workgroup with the
-    // same index modulo 8, i.e. on one XCD with consecutive round-robin placement)
-    auto start = [&](int rr) { return (used[rr] + 7) / 8 * 8; };
+    // gangs are packed back to back: with round-robin placement of
+    // consecutive workgroups over the XCDs, the tiles t = x (mod 8) of a
+    // gang (one group of the two-hop exchange) land on one XCD wherever the
+    // gang starts
+    auto start = [&](int rr) { return used[rr]; };
     int r = 0;
     while (r < (int)used.size() && start(r) + G > nwg) ++r;
     if (r == (int)used.size()) {
@@ -446,7 +448,8 @@ pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg) {
   pros_status st = check_batch(b);
   if (st != PROS_OK) return st;
   if (!cfg) return fail(PROS_EINVAL, "cfg is NULL");
-  if (cfg->register_budget != 64 && cfg->register_budget != 128) return fail(PROS_EINVAL, "register_budget must be 64 or 128");
+  if (cfg->register_budget != 64 && cfg->register_budget != 128 && cfg->register_budget != prost::kBudgetLds)
+    return fail(PROS_EINVAL, "register_budget must be 64, 128 or %d", prost::kBudgetLds);
   if (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 8) return fail(PROS_EINVAL, "workgroups_per_cu must be 1..8");
   if (!(cfg->tile_scale > 0.0 && cfg->tile_scale <= 1.0)) return fail(PROS_EINVAL, "tile_scale must be in (0, 1]");
   if (cfg->strategy < 0 || cfg->strategy > 1) return fail(PROS_EINVAL, "strategy must be 0 or 1");

@@ -35,7 +35,23 @@ __host__ __device__ constexpr int batch_nr(int budget, int K) {
 __host__ __device__ constexpr int batch_nr_bf16(int budget, int K) {
   return 2 * batch_nr(budget, K);
 }
+// The LDS form (register_budget kBudgetLds, bfloat16, k class >= 10): the
+// register tile of budget 128, plus the row pairs whose K words and two
+// residuals per thread fit the LDS left beside the frame scratch (at most 16
+// pairs in all).  A 640x480x3 k = 15 stream then needs 82 workgroups
+// instead of 113, so three such streams share a round instead of two.
+constexpr int kBudgetLds = 192;
+constexpr int kLdsBytes = 160 * 1024;
+__host__ __device__ constexpr int batch_lds_np(int K) { return batch_nr(128, K); }
+__host__ __device__ constexpr int batch_lds_nl(int K) {
+  const int fit = (kLdsBytes - (int)sizeof(FrameSmem) - 1024) / ((K + 2) * 4 * kBlock);
+  const int room = 16 - batch_lds_np(K);
+  return fit < room ? fit : room;
+}
+__host__ __device__ constexpr bool batch_lds_form(int K) { return K >= 10; }
+
 __host__ __device__ constexpr int batch_rows(int storage_bf16, int budget, int K) {
+  if (budget == kBudgetLds) return 2 * (batch_lds_np(K) + batch_lds_nl(K));
   return storage_bf16 ? batch_nr_bf16(budget, K) : batch_nr(budget, K);
 }
 
@@ -57,16 +73,26 @@ __device__ __forceinline__ FrameArgs load_uniform(const FrameArgs* __restrict__ 
   return a;
 }
 
-template <typename TS, int K, int NR, bool EXT>
+template <typename TS, int K, int NR, bool EXT, int NL = 0>
 __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __restrict__ descs,
                                                        const BatchItem* __restrict__ items, int rounds) {
   __shared__ FrameSmem sm;
+  __shared__ uint32_t lt[NL > 0 ? NL * (K + 2) * kBlock : 1];   // LDS row pairs of the tile and their residuals
   for (int r = 0; r < rounds; ++r) {
     const BatchItem it = items[(size_t)r * gridDim.x + blockIdx.x];
     if (it.stream < 0) continue;
     const FrameArgs a = load_uniform(descs + it.stream);
-    if (!run_tile<K, NR, TS, EXT>(a, it.tile, sm)) return;
+    if (!run_tile<K, NR, TS, EXT, false, NL>(a, it.tile, sm, lt)) return;
   }
+}
+
+// The LDS form of class K (bfloat16, default features).
+template <int K>
+const void* batch_kernel_lds() {
+  static_assert(batch_lds_form(K), "LDS form for k class >= 10");
+  constexpr int NL = batch_lds_nl(K);
+  static_assert(NL >= 1 && sizeof(FrameSmem) + NL * (K + 2) * 4 * kBlock + 1024 <= kLdsBytes, "LDS budget");
+  return (const void*)&batch_kernel<uint16_t, K, 2 * batch_lds_np(K), false, NL>;
 }
 
 // Kernel for (storage, class K, budget, optional features compiled in);

@@ -4,6 +4,7 @@
 
 namespace prost {
 const void* batch_kernel_k10(int storage_bf16, int budget, bool ext) {
+  if (budget == kBudgetLds) return (storage_bf16 && !ext) ? batch_kernel_lds<10>() : nullptr;
   if (storage_bf16)
     return ext ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 10, batch_nr_bf16(64, 10), true>
                                : (const void*)&batch_kernel<uint16_t, 10, batch_nr_bf16(128, 10), true>)

@@ -4,6 +4,7 @@
 
 namespace prost {
 const void* batch_kernel_k16(int storage_bf16, int budget, bool ext) {
+  if (budget == kBudgetLds) return (storage_bf16 && !ext) ? batch_kernel_lds<16>() : nullptr;
   if (storage_bf16)
     return ext ? (budget == 64 ? (const void*)&batch_kernel<uint16_t, 16, batch_nr_bf16(64, 16), true>
                                : (const void*)&batch_kernel<uint16_t, 16, batch_nr_bf16(128, 16), true>)

@@ -1107,6 +1107,10 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 // When a.pair_aligned is set (even P, even tpw, 4-byte aligned frame) a pair
 // is one aligned 32-bit word in the U planes and in the frame; otherwise the
 // two halves are accessed separately and may lie in two colour planes.
+// NL > 0 (batched form): pairs NP .. NP + NL - 1 of every thread are held in
+// LDS instead (lt[((s - NP) K + j) kBlock + tid], their residuals after the
+// NL K kBlock words, each thread its own words: no barriers), processed by a
+// loop that is not unrolled; results are identical.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
@@ -1146,9 +1150,12 @@ __device__ __forceinline__ void st_u16(uint16_t* base, unsigned boff, uint16_t v
   *(uint16_t*)((char*)base + boff) = v;
 }
 
-template <int K, int NP, bool EXT>
-__device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int tile, FrameSmem& sm) {
-  static_assert(2 * NP <= kMaxNR && NP <= 16, "row bit masks hold 32 rows");
+template <int K, int NP, bool EXT, int NL = 0>
+__device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int tile, FrameSmem& sm,
+                                                  uint32_t* __restrict__ lt = nullptr) {
+  constexpr int NT = NP + NL;   // row pairs per thread: NP in registers, NL in LDS
+  static_assert(2 * NT <= kMaxNR && NT <= 16, "row bit masks hold 32 rows");
+  static_assert(NL == 0 || !EXT, "the LDS pairs serve the default features only");
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
   const int tid = thread_index();
@@ -1161,7 +1168,11 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   const uint16_t* __restrict__ xg = (const uint16_t*)(a.xtab ? a.xtab[ctx.n % a.ring] : a.x);
   const uint8_t* __restrict__ wsrc = a.weights_from_filtered ? a.mask : a.lab;
   uint32_t u[NP][K];
+  // cw: w c in phase A, u.d in phase B, eta in the update (register rows);
+  // the LDS rows keep r in LDS and recompute these where needed (the same
+  // operations on the same values, so the same results)
   float r[2 * NP], cw[2 * NP];
+  float* __restrict__ lr = NL > 0 ? (float*)(lt + NL * K * kBlock) : nullptr;   // r of the LDS rows
   uint32_t vbits = 0;         // bit i: row i exists
   uint32_t fbits = 0;         // bit i: row i's pixel was foreground (weight omega)
   uint32_t sbits = 0;         // bit s: pair s continues in the next colour plane
@@ -1210,6 +1221,46 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
       r[2 * s + 1] = has1 ? acc1 : 0.f;
     }
   }
+#pragma unroll 1
+  for (int s = NP; s < NT; ++s) {   // pairs held in LDS: the same load
+    const int q0 = 2 * (tid + s * kBlock);
+    uint32_t* lts = lt + (s - NP) * K * kBlock + tid;
+    float* rls = lr + (s - NP) * 2 * kBlock + tid;
+    rls[0] = rls[kBlock] = 0.f;
+    if (q0 < ctx.nq) {
+      const int c = q0 / ctx.npx;
+      const int pl = q0 - c * ctx.npx;
+      const int e = c * a.P + ctx.p0 + pl;
+      const bool has1 = q0 + 1 < ctx.nq;
+      const bool split = (pl + 1 == ctx.npx);
+      const int e1 = split ? e + 1 + (a.P - ctx.npx) : e + 1;
+      vbits |= (has1 ? 3u : 1u) << (2 * s);
+      if (split) sbits |= 1u << s;
+      if (wsrc[ctx.p0 + pl]) fbits |= 1u << (2 * s);
+      if (has1 && wsrc[ctx.p0 + (split ? 0 : pl + 1)]) fbits |= 2u << (2 * s);
+      const unsigned b0 = 2u * (unsigned)e, b1 = 2u * (unsigned)e1;
+      uint32_t xw;
+      if (al) xw = ld_u32(xg, b0);
+      else xw = ld_u16(xg, b0) | (has1 ? (ld_u16(xg, b1) << 16) : 0u);
+      float acc0 = bf_lo(xw), acc1 = bf_hi(xw);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        uint32_t v = 0u;
+        if (j < a.k) {
+          const uint16_t* col = Ug + (long long)j * a.ldU;
+          v = al ? ld_u32(col, b0) : (ld_u16(col, b0) | (has1 ? (ld_u16(col, b1) << 16) : 0u));
+        }
+        lts[j * kBlock] = v;
+        acc0 = fmaf(-bf_lo(v), ks.yf[j], acc0);
+        acc1 = fmaf(-bf_hi(v), ks.yf[j], acc1);
+      }
+      rls[0] = acc0;
+      rls[kBlock] = has1 ? acc1 : 0.f;
+    } else {
+#pragma unroll
+      for (int j = 0; j < K; ++j) lts[j * kBlock] = 0u;
+    }
+  }
   const float om = a.omega;
   auto weight = [&](int i) -> float {
     return ((vbits >> i) & 1u) ? (((fbits >> i) & 1u) ? om : 1.0f) : 0.f;
@@ -1237,6 +1288,27 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = fmaf(wd, bf_half(u[s][j], h), acc[j]);
       }
+#pragma unroll 1
+    for (int s = NP; s < NT; ++s) {   // LDS pairs: each word read once for both rows
+      const uint32_t* lts = lt + (s - NP) * K * kBlock + tid;
+      float* rls = lr + (s - NP) * 2 * kBlock + tid;
+      float wd[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float ri = rls[h * kBlock];
+        const float wt = weight(2 * s + h);
+        float phi, c;
+        cost_eval(ri, a.cp, phi, c);
+        wd[h] = wt * c * ri;
+        acc[K] = fmaf(wt, phi, acc[K]);
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t v = lts[j * kBlock];
+        acc[j] = fmaf(wd[0], bf_lo(v), acc[j]);
+        acc[j] = fmaf(wd[1], bf_hi(v), acc[j]);
+      }
+    }
     if (!gang_reduce<K + 1>(acc, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
     cg_direction<K>(a, ks, it, ctx.lead, restarts);
     if (ks.flag[0]) break;
@@ -1253,12 +1325,47 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
         accb[0] = fmaf(cw[i] * t, t, accb[0]);
         cw[i] = t;
       }
+#pragma unroll 1
+    for (int s = NP; s < NT; ++s) {
+      const uint32_t* lts = lt + (s - NP) * K * kBlock + tid;
+      float* rls = lr + (s - NP) * 2 * kBlock + tid;
+      float t0 = 0.f, t1 = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t v = lts[j * kBlock];
+        t0 = fmaf(bf_lo(v), ks.df[j], t0);
+        t1 = fmaf(bf_hi(v), ks.df[j], t1);
+      }
+      float wc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float phi, c;
+        cost_eval(rls[h * kBlock], a.cp, phi, c);
+        wc[h] = weight(2 * s + h) * c;
+      }
+      accb[0] = fmaf(wc[0] * t0, t0, accb[0]);
+      accb[0] = fmaf(wc[1] * t1, t1, accb[0]);
+    }
     if (!gang_reduce<1>(accb, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
     const double dHd = ks.red[0];
     if (!(dHd > 0.0)) break;
     const float af = cg_advance<K>(a, ks, dHd, it, ctx.lead);
 #pragma unroll
     for (int i = 0; i < 2 * NP; ++i) r[i] = fmaf(-af, cw[i], r[i]);
+#pragma unroll 1
+    for (int s = NP; s < NT; ++s) {   // u.d of the LDS rows again, as in phase B
+      const uint32_t* lts = lt + (s - NP) * K * kBlock + tid;
+      float* rls = lr + (s - NP) * 2 * kBlock + tid;
+      float t0 = 0.f, t1 = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t v = lts[j * kBlock];
+        t0 = fmaf(bf_lo(v), ks.df[j], t0);
+        t1 = fmaf(bf_hi(v), ks.df[j], t1);
+      }
+      rls[0] = fmaf(-af, t0, rls[0]);
+      rls[kBlock] = fmaf(-af, t1, rls[kBlock]);
+    }
     ++steps;
     __syncthreads();
   }
@@ -1286,6 +1393,29 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 #pragma unroll
         for (int j = 0; j < K; ++j) acce[j] = fmaf(eta, bf_half(u[s][j], h), acce[j]);
       }
+#pragma unroll 1
+    for (int s = NP; s < NT; ++s) {
+      const uint32_t* lts = lt + (s - NP) * K * kBlock + tid;
+      float* rls = lr + (s - NP) * 2 * kBlock + tid;
+      float et[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float ri = rls[h * kBlock];
+        const float wt = weight(2 * s + h);
+        float phi, c;
+        cost_eval(ri, a.cp, phi, c);
+        const float eta = -wt * c * ri;
+        et[h] = eta;
+        acce[K] = fmaf(eta, eta, acce[K]);
+        acce[K + 1] = fmaf(wt, phi, acce[K + 1]);
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint32_t v = lts[j * kBlock];
+        acce[j] = fmaf(et[0], bf_lo(v), acce[j]);
+        acce[j] = fmaf(et[1], bf_hi(v), acce[j]);
+      }
+    }
     if (!gang_reduce<LE>(acce, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
     if (EXT && tid == 0 && pupd) ks.pre_sum = ks.red[K + 2];
     geodesic_setup<K>(a, ks, ctx.n, steps, ctx.lead);
@@ -1345,6 +1475,59 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
       s_flag[q0] = (fabsf(rl0) >= a.delta) ? 1 : 0;
       if (has1) s_flag[q0 + 1] = (fabsf(rl1) >= a.delta) ? 1 : 0;
     }
+#pragma unroll 1
+    for (int s = NP; s < NT; ++s) {   // LDS pairs (no optional features)
+      const int q0 = 2 * (tid + s * kBlock);
+      if (q0 >= ctx.nq) continue;
+      const uint32_t* lts = lt + (s - NP) * K * kBlock + tid;
+      float* rls = lr + (s - NP) * 2 * kBlock + tid;
+      const bool has1 = (vbits >> (2 * s + 1)) & 1u;
+      const int c = q0 / ctx.npx;
+      const int e = c * a.P + ctx.p0 + (q0 - c * ctx.npx);
+      const int e1 = ((sbits >> s) & 1u) ? e + 1 + (a.P - ctx.npx) : e + 1;
+      float rl0 = rls[0], rl1 = rls[kBlock];
+      if (upd) {
+        float uv0 = 0.f, ua0 = 0.f, uv1 = 0.f, ua1 = 0.f;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const uint32_t v = lts[j * kBlock];
+          const float a0 = bf_lo(v), a1 = bf_hi(v);
+          uv0 = fmaf(a0, ks.vf[j], uv0);
+          ua0 = fmaf(a0, ks.af[j], ua0);
+          uv1 = fmaf(a1, ks.vf[j], uv1);
+          ua1 = fmaf(a1, ks.af[j], ua1);
+        }
+        float et[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          float phi, c;
+          const float ri = rls[h * kBlock];
+          cost_eval(ri, a.cp, phi, c);
+          et[h] = -weight(2 * s + h) * c * ri;
+        }
+        const float coef0 = fmaf(cm1, uv0, -sz * (et[0] - ua0));
+        const float coef1 = fmaf(cm1, uv1, -sz * (et[1] - ua1));
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+          if (j < a.k) {
+            const uint32_t v = lts[j * kBlock];
+            const uint32_t nw = pack_bf16_rne(fmaf(coef0, ks.vf[j], bf_lo(v)), fmaf(coef1, ks.vf[j], bf_hi(v)));
+            uint16_t* col = Uw + (long long)j * a.ldU;
+            if (al) {
+              st_u32(col, 2u * (unsigned)e, nw);
+            } else {
+              st_u16(col, 2u * (unsigned)e, (uint16_t)(nw & 0xFFFFu));
+              if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(nw >> 16));
+            }
+          }
+        if (a.labels_after_update) {
+          rl0 = fmaf(-coef0, nu_f, rl0);
+          rl1 = fmaf(-coef1, nu_f, rl1);
+        }
+      }
+      s_flag[q0] = (fabsf(rl0) >= a.delta) ? 1 : 0;
+      if (has1) s_flag[q0 + 1] = (fabsf(rl1) >= a.delta) ? 1 : 0;
+    }
     trace_point(a, tile, 61);
     write_labels(a, s_flag, ctx.p0, ctx.npx);
     trace_point(a, tile, 62);
@@ -1362,12 +1545,14 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 // variant and the one-exchange curvature schedule of CG) are compiled in as
 // well: float32 tiles of the single-stream kernel only, as the H partials
 // would spill the packed tile and the batch kernel's registers.
-template <int K, int NR, typename TS, bool EXT, bool WIDE = false>
-__device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
+template <int K, int NR, typename TS, bool EXT, bool WIDE = false, int NL = 0>
+__device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm,
+                                         uint32_t* __restrict__ lt = nullptr) {
   if constexpr (sizeof(TS) == 2) {
     static_assert(NR % 2 == 0, "bfloat16 tiles hold row pairs");
-    return frame_tile_packed<K, NR / 2, EXT>(a, tile, sm);
+    return frame_tile_packed<K, NR / 2, EXT, NL>(a, tile, sm, lt);
   } else {
+    static_assert(NL == 0, "LDS row pairs: bfloat16 tiles only");
     return frame_tile<K, NR, EXT, WIDE>(a, tile, sm);
   }
 }

@@ -140,7 +140,10 @@ def test_tuner_restores_state_and_keeps_parity(tmp_path):
         assert rec2["config"] == rec["config"]
 
 
-def test_batch_bf16_matches_oracle():
+@pytest.mark.parametrize("budget", [128, 192])
+def test_batch_bf16_matches_oracle(budget):
+    """bfloat16 batch against each stream's oracle step; budget 192 is the
+    LDS form (row pairs of the tile held in LDS beside the registers)."""
     from paper_1302_2073_amd.tracker import BatchTracker
 
     def rne(a):
@@ -150,6 +153,8 @@ def test_batch_bf16_matches_oracle():
 
     streams = _streams(SHAPES[:4])
     with BatchTracker(_specs(streams), storage="bf16") as bt:
+        bt.configure(register_budget=budget, workgroups_per_cu=1)
+        say("  config", bt.config())
         bt.set_frames(_frames_tensor(streams, 4, 1, "bf16"))
         starts = _load(bt, streams)
         bt.step()
@@ -166,10 +171,12 @@ def test_batch_bf16_matches_oracle():
             assert y_rel <= 1e-4 and over == 0
 
 
-def test_batch_bf16_two_vga_streams_share_a_round():
-    """Two 640x480x3 k=15 streams in bfloat16 (the benchmark's streams): the
-    row-pair tiles halve each gang, so both frames run side by side in one
-    round; each stream matches its own oracle step."""
+@pytest.mark.parametrize("nstreams,budget", [(2, 0), (3, 192)])
+def test_batch_bf16_vga_streams_share_a_round(nstreams, budget):
+    """640x480x3 k=15 streams in bfloat16 (the benchmark's streams): the
+    row-pair tiles halve each gang, so two frames run side by side in one
+    round, and three with the LDS form; each stream matches its own oracle
+    step."""
     from paper_1302_2073_amd.tracker import BatchTracker, bf16_bits
     import torch
 
@@ -178,16 +185,18 @@ def test_batch_bf16_two_vga_streams_share_a_round():
         u = f.view(np.uint32).astype(np.uint64)
         return ((((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)).view(np.float32).astype(np.float64)
 
-    wls = [V.vga_rgb(stream=s) for s in range(2)]
+    wls = [V.vga_rgb(stream=s) for s in range(nstreams)]
     svs = [V.SyntheticVideo(w.video) for w in wls]
     specs = [dict(width=640, height=480, channels=3, k=15, mu=w.mu) for w in wls]
     with BatchTracker(specs, storage="bf16") as bt:
+        if budget:
+            bt.configure(register_budget=budget, workgroups_per_cu=1)
         cfg = bt.config()
         say("  config", cfg)
         assert cfg["rounds"] == 1
         frames = [[torch.from_numpy(bf16_bits(sv.frame(0)).view(np.int16)).cuda().view(torch.bfloat16)]
                   for sv in svs]
-        for s in range(2):
+        for s in range(nstreams):
             bt.set_state(s, V.initial_subspace(640 * 480 * 3, 15, 3, s))
         bt.set_frames(frames)
         starts = []
