@@ -835,6 +835,26 @@ __device__ __forceinline__ float cg_advance(const FrameArgs& a, KSpace<kMaxK>& k
   return (float)alpha;
 }
 
+// Step size and angle of the geodesic step and the trigonometric scalars of
+// the row pass: t = max(exp(-tau n) t_init, t_min) (Sec. 3.4),
+// theta = sigma t, cos(theta) - 1 = -2 sin^2(theta / 2), sin(theta) / zeta.
+// Out of line on purpose: inlined into the persistent kernels, the float64
+// polynomial constants of exp and sin were hoisted out of the tile loop and
+// held in registers (and spilled) for the whole launch.
+struct GeoScalars {
+  double t, theta, cm1, sz;
+};
+__device__ __attribute__((noinline)) GeoScalars geodesic_scalars(double tau_n, double t_init, double t_min,
+                                                                 double sigma, double zeta) {
+  GeoScalars g;
+  g.t = fmax(exp(-tau_n) * t_init, t_min);
+  g.theta = sigma * g.t;
+  const double sh = sin(0.5 * g.theta);
+  g.cm1 = -2.0 * sh * sh;
+  g.sz = zeta > 0.0 ? sin(g.theta) / zeta : 0.0;
+  return g;
+}
+
 // Scalars of the rank-one geodesic step (Sec. 3.3, Step 2) from the reduced
 // a = U^T eta, ||eta||^2 and the final cost in ks.red: zeta = ||pi(eta)||,
 // nu = ||y||, sigma = zeta nu, theta = sigma t_n; row-pass coefficients in
@@ -852,8 +872,6 @@ __device__ __forceinline__ void geodesic_setup(const FrameArgs& a, KSpace<kMaxK>
     const double zeta = sqrt(fmax(ee - aa, 0.0));
     const double nu = sqrt(yy);
     const double sigma = zeta * nu;
-    const double t = fmax(exp(-a.tau * (double)n) * a.t_init, a.t_min);
-    const double theta = sigma * t;
     const int upd = (zeta > 0.0 && nu > 0.0) ? 1 : 0;
     if (lane < K) {
       ks.af[lane] = (float)av;
@@ -861,16 +879,16 @@ __device__ __forceinline__ void geodesic_setup(const FrameArgs& a, KSpace<kMaxK>
       ks.yf[lane] = (float)yv;
     }
     if (lane == 0) {
-      const double sh = sin(0.5 * theta);
-      ks.scal[0] = upd ? (float)(-2.0 * sh * sh) : 0.f;          // cos(theta) - 1
-      ks.scal[1] = upd ? (float)(sin(theta) / zeta) : 0.f;       // sin(theta) / zeta
+      const GeoScalars g = geodesic_scalars(a.tau * (double)n, a.t_init, a.t_min, sigma, zeta);
+      ks.scal[0] = upd ? (float)g.cm1 : 0.f;   // cos(theta) - 1
+      ks.scal[1] = upd ? (float)g.sz : 0.f;    // sin(theta) / zeta
       ks.scal[2] = (float)nu;
       ks.flag[2] = upd;
       if (lead) {
         a.stats->f[steps] = ks.red[K + 1];
-        a.stats->t = t;
+        a.stats->t = g.t;
         a.stats->sigma = sigma;
-        a.stats->theta = theta;
+        a.stats->theta = g.theta;
         a.stats->zeta = zeta;
         a.stats->nu = nu;
         a.stats->updated = upd;
