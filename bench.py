@@ -95,7 +95,7 @@ def timed_median(fn, steps, stream):
     return ts[len(ts) // 2], ts[0], ts[-1]
 
 
-def run_plain(storage, steps, warmup, pool, curvature=0):
+def run_plain(storage, steps, warmup, pool, curvature=0, cooperative=1):
     import torch
     from paper_1302_2073_amd import Tracker
     from synth import video as V
@@ -104,6 +104,8 @@ def run_plain(storage, steps, warmup, pool, curvature=0):
     trk.set_state(V.initial_subspace(trk.m, K, wl.video.seed))
     if curvature:
         trk.set_curvature(curvature)
+    if not cooperative:
+        trk.set_dispatch(0)
     stream = torch.cuda.current_stream()   # the tracker was created on this stream
     for i in range(max(warmup, 50)):
         trk.track(frames[i % pool])
@@ -146,7 +148,7 @@ def run_plain_host(steps, warmup, pool):
     return dict(ms_total=el * 1e3, ms_per_frame=el * 1e3 / steps, fps=steps / el)
 
 
-def run_batched(storage, nstreams, steps, warmup, pool, tune=True):
+def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1):
     """nstreams independent 640x480x3 k=15 streams, each with its own seeded
     video, one persistent launch per batch step (hipGraph replay)."""
     import torch
@@ -169,6 +171,8 @@ def run_batched(storage, nstreams, steps, warmup, pool, tune=True):
     for s in range(nstreams):
         bt.set_state(s, V.initial_subspace(WIDTH * HEIGHT * CH, K, 3, s))
     bt.set_frames(frames)
+    if not cooperative:
+        bt.set_dispatch(0)
     tuned = bt.tune(steps=3) if tune else None
     bt.use_graph(True)
     stream = torch.cuda.current_stream()
@@ -390,8 +394,8 @@ def main():
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--streams", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--forms", default="plain_f32,plain_f32_curv1,plain_bf16,plain_f32_host,batched_bf16,"
-                    "batched_mixed_bf16,lpcost,quality,ingest",
+    ap.add_argument("--forms", default="plain_f32,plain_f32_curv1,plain_f32_ordinary,plain_bf16,plain_f32_host,"
+                    "batched_bf16,batched_bf16_ordinary,batched_mixed_bf16,lpcost,quality,ingest",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -429,6 +433,10 @@ def main():
         curv = run_plain("f32", args.steps * 4, args.warmup, args.pool, curvature=1)
         record("plain_f32_curv1", curv, 4, 4)
         forms["plain_f32_curv1"]["note"] = "curvature schedule 1: H reduced with the gradient, J + 1 exchanges"
+    if "plain_f32_ordinary" in want:
+        pod = run_plain("f32", args.steps * 4, args.warmup, args.pool, cooperative=0)
+        record("plain_f32_ordinary", pod, 4, 4)
+        forms["plain_f32_ordinary"]["note"] = "ordinary (non-cooperative) launches of the resident grid"
     if "plain_bf16" in want:
         plain_bf16 = run_plain("bf16", args.steps * 4, args.warmup, args.pool)
         record("plain_bf16", plain_bf16, 2, 2)
@@ -441,6 +449,11 @@ def main():
         achieved = record("batched_bf16", batched, 2, 2, args.streams)
         if plain:
             forms["batched_bf16"]["vs_plain_f32"] = round(batched["fps"] / plain["fps"], 3)
+    if "batched_bf16_ordinary" in want:
+        bod = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune,
+                          cooperative=0)
+        record("batched_bf16_ordinary", bod, 2, 2, args.streams)
+        forms["batched_bf16_ordinary"]["note"] = "ordinary (non-cooperative) launches of the resident grid"
     if "batched_mixed_bf16" in want:
         mixed = run_batched_mixed(64, max(args.steps // 4, 10), args.warmup, args.pool)
         per = mixed["ms_per_step"]

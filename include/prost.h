@@ -352,6 +352,22 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
  * Synchronises. */
 PROS_API pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode);
 
+/* Dispatch of the persistent kernels.  A frame's gang of workgroups waits on
+ * itself at every exchange, so all of its workgroups must be resident at
+ * once.  cooperative = 1 (default): hipLaunchCooperativeKernel, which
+ * guarantees it; on this device each such launch costs about 17 us more
+ * than an ordinary one (measured: 19.6 vs 2.7 us per launch of an empty
+ * kernel of 113-256 workgroups).  cooperative = 0: an ordinary launch.  The
+ * grid is already sized to what the device holds at once (occupancy query
+ * at configuration), so on a device running nothing else every workgroup
+ * starts immediately; if other work holds compute units, waiting
+ * workgroups end the frame through the bounded exchange waits with
+ * PROS_ETIMEOUT (no hang) and the handle becomes unusable.  Use 0 on a
+ * dedicated device.  pros_batch_set_dispatch does the same for a batch
+ * (and drops a captured graph).  Results are identical either way. */
+PROS_API pros_status pros_set_dispatch(pros_handle* h, int32_t cooperative);
+PROS_API pros_status pros_batch_set_dispatch(pros_batch* b, int32_t cooperative);
+
 /* Curvature schedule of the Step 1 solver (Sec. 3.3): how d^T H d of the
  * majoriser step alpha = -g.d / d^T H d, H = U^T diag(w c) U, is formed.
  * 0 (default): a second pass per step sums w c (u_e . d)^2 after the

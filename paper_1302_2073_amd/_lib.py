@@ -89,6 +89,8 @@ _SIGS = {
     "pros_get_launch_info": (C.c_int, [C.c_void_p, C.POINTER(pros_launch_info)]),
     "pros_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "pros_set_curvature": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pros_set_dispatch": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pros_batch_set_dispatch": (C.c_int, [C.c_void_p, C.c_int32]),
     "pros_debug_trace": (C.c_int, [C.c_void_p, C.c_void_p]),
     "pros_set_preprocess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "pros_set_score_output": (C.c_int, [C.c_void_p, C.c_void_p]),

@@ -586,7 +586,8 @@ pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, i
   }
   FrameArgs a = make_args(h, x);
   void* args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(h->kfn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream);
+  hipError_t e = h->coop ? hipLaunchCooperativeKernel(h->kfn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream)
+                         : hipLaunchKernel(h->kfn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream);
   if (e != hipSuccess) {
     h->broken = true;
     h->broken_status = PROS_EHIP;
@@ -678,6 +679,14 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   }
   h->sync_mode = sync_mode;
   return prost_host::reset_exchange(h);
+}
+
+pros_status pros_set_dispatch(pros_handle* h, int32_t cooperative) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (cooperative != 0 && cooperative != 1) return fail(PROS_EINVAL, "cooperative must be 0 or 1");
+  h->coop = cooperative != 0;
+  return PROS_OK;
 }
 
 pros_status pros_set_curvature(pros_handle* h, int32_t schedule) {

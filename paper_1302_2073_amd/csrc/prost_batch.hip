@@ -75,6 +75,7 @@ struct pros_batch {
   std::vector<BatchItem> items;
   // graph
   bool use_graph = false;
+  bool coop = true;              // cooperative launch, or an ordinary dispatch of the resident grid
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool broken = false;
@@ -199,7 +200,8 @@ static pros_status launch(pros_batch* b, hipStream_t on) {
   BatchItem* it = b->d_items;
   int rounds = b->rounds;
   void* args[] = {&d, &it, &rounds};
-  hipError_t e = hipLaunchCooperativeKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on);
+  hipError_t e = b->coop ? hipLaunchCooperativeKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on)
+                         : hipLaunchKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on);
   if (e != hipSuccess) {
     b->broken = true;
     return fail(PROS_EHIP, "batch kernel launch: %s", hipGetErrorString(e));
@@ -386,6 +388,17 @@ pros_status pros_batch_track(pros_batch* b) {
     ++h->submitted;
     h->mask_stale = true;
   }
+  return PROS_OK;
+}
+
+pros_status pros_batch_set_dispatch(pros_batch* b, int32_t cooperative) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (cooperative != 0 && cooperative != 1) return fail(PROS_EINVAL, "cooperative must be 0 or 1");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
+  b->coop = cooperative != 0;
+  drop_graph(b);   // a captured launch keeps its launch kind
   return PROS_OK;
 }
 

@@ -33,6 +33,7 @@ struct pros_handle {
   int G = 0, tpw = 0, NR = 0;
   int sync_mode = 2;       // 0: counter barrier, 1: tagged gather/broadcast, 2: two-level tagged, 3: tagged all-read
   int curv = 0;            // CG curvature schedule: 0 = second pass per step, 1 = H with the gradient
+  bool coop = true;        // cooperative launch (co-residency guaranteed) or an ordinary dispatch
   long long* trace = nullptr;   // optional per-tile timestamps (diagnostics)
   bool mask_stale = true;       // mask not yet computed from the latest labels
   long long timeout_ticks = 0;

@@ -204,6 +204,11 @@ class Tracker:
     def set_launch(self, rows_per_thread=0, sync_mode=2):
         L.check(L.lib().pros_set_launch(self._h, int(rows_per_thread), int(sync_mode)))
 
+    def set_dispatch(self, cooperative):
+        """1: cooperative launches (default); 0: ordinary launches of the
+        resident grid (about 17 us less per frame; dedicated device only)."""
+        L.check(L.lib().pros_set_dispatch(self._h, int(cooperative)))
+
     def set_curvature(self, schedule):
         """0: d^T H d in a second pass per CG step; 1: H reduced with the
         gradient (one exchange per step, float32 storage)."""
@@ -303,6 +308,11 @@ class BatchTracker:
 
     def use_graph(self, on=True):
         L.check(L.lib().pros_batch_use_graph(self._b, int(bool(on))))
+
+    def set_dispatch(self, cooperative):
+        """1: cooperative launches (default); 0: ordinary launches of the
+        resident grid (dedicated device only)."""
+        L.check(L.lib().pros_batch_set_dispatch(self._b, int(cooperative)))
 
     def sync(self):
         return L.lib().pros_batch_sync(self._b)

@@ -261,3 +261,25 @@ def test_mixed_streams_workload_parity_sample():
             U0 = V.initial_subspace(v.m, wl.k, 4, i).astype(np.float32).astype(np.float64)
             st = O.initial_state(U0, prm.P)
             _check_stream(bt, i, prm, st, f32(svs[i].frame(0)))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_ordinary_dispatch_is_bitwise_equal(graph):
+    """Ordinary launches (and their captured graph) give the same states as
+    cooperative launches."""
+    from paper_1302_2073_amd.tracker import BatchTracker
+    streams = _streams(SHAPES[:3])
+    res = []
+    for coop in (1, 0):
+        with BatchTracker(_specs(streams)) as bt:
+            bt.set_dispatch(coop)
+            bt.use_graph(graph)
+            bt.set_frames(_frames_tensor(streams, 4, 2))
+            _load(bt, streams)
+            for _ in range(3):
+                bt.step()
+            assert bt.sync() == 0
+            res.append([bt.get_state(s) for s in range(len(streams))])
+    for sa, sb in zip(res[0], res[1]):
+        for a, b in zip(sa, sb):
+            np.testing.assert_array_equal(a, b)

@@ -346,3 +346,27 @@ def test_small_gang_automatic_launch(storage):
         else:
             from test_gpu_precision import _bf16_check, rne_bf16
             _bf16_check(trk, prm, st, rne_bf16(sv.frame(4)), "160x120x3 small gang")
+
+
+@pytest.mark.parametrize("name,frame", [("qvga_rgb", 8), ("vga_rgb", 3)])
+def test_ordinary_dispatch_gives_identical_frames(name, frame):
+    """An ordinary launch of the resident grid computes exactly what the
+    cooperative launch does (same kernel, same gang), and both match the
+    oracle."""
+    wl, prm, sv, states = oracle_trajectory(name, frame)
+    x = f32(sv.frame(frame)).astype(np.float32)
+    outs = []
+    for coop in (1, 0):
+        with _tracker(prm) as trk:
+            trk.set_dispatch(coop)
+            trk.set_state(states[frame].U, states[frame].y, states[frame].labels, states[frame].n)
+            trk.track(x)
+            trk.track(x)
+            outs.append(trk.get_state())
+            assert trk.sync() == 0
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    with _tracker(prm) as trk:
+        trk.set_dispatch(0)
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
+    assert_parity(rep)
