@@ -121,6 +121,32 @@ def run_plain(storage, steps, warmup, pool, curvature=0, cooperative=1):
                 cg_steps=stats["cg_steps"], spread_ms=[round(lo, 3), round(hi, 3)])
 
 
+def run_plain_seq(storage, steps, warmup, pool, chunk=64):
+    """One stream fed buffered sequences (pros_track_frames): `chunk` frames
+    per call, up to 256 per kernel launch, the U tile kept in registers
+    between frames.  Same results as one call per frame."""
+    import torch
+    from paper_1302_2073_amd import Tracker
+    from synth import video as V
+    wl, sv, frames = make_frames(pool, storage)
+    trk = Tracker(WIDTH, HEIGHT, CH, K, mu=wl.mu, storage=storage)
+    trk.set_state(V.initial_subspace(trk.m, K, wl.video.seed))
+    seq = [frames[i % pool] for i in range(chunk)]
+    for _ in range(max(warmup // chunk, 2)):
+        trk.track_many(seq)
+    torch.cuda.synchronize()
+    calls = max(steps // chunk, 1)
+    ms, lo, hi = timed_median(lambda i: trk.track_many(seq), calls, torch.cuda.current_stream())
+    st = trk.sync()
+    info = trk.launch_info()
+    trk.close()
+    if st != 0:
+        raise RuntimeError(f"tracker error {st}")
+    n = calls * chunk
+    return dict(ms_total=ms, ms_per_frame=ms / n, fps=n / (ms / 1e3), launch=info,
+                spread_ms=[round(lo, 3), round(hi, 3)])
+
+
 def run_plain_host(steps, warmup, pool):
     """One float32 stream fed from host memory: every frame crosses PCIe
     (pageable copy into the handle's staging buffer) before its launch.
@@ -394,8 +420,9 @@ def main():
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--streams", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--forms", default="plain_f32,plain_f32_curv1,plain_f32_ordinary,plain_bf16,plain_f32_host,"
-                    "batched_bf16,batched_bf16_ordinary,batched_mixed_bf16,lpcost,quality,ingest",
+    ap.add_argument("--forms", default="plain_f32,plain_f32_curv1,plain_f32_ordinary,plain_f32_seq,plain_bf16,"
+                    "plain_bf16_seq,plain_f32_host,batched_bf16,batched_bf16_ordinary,batched_mixed_bf16,lpcost,"
+                    "quality,ingest",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -437,6 +464,14 @@ def main():
         pod = run_plain("f32", args.steps * 4, args.warmup, args.pool, cooperative=0)
         record("plain_f32_ordinary", pod, 4, 4)
         forms["plain_f32_ordinary"]["note"] = "ordinary (non-cooperative) launches of the resident grid"
+    if "plain_f32_seq" in want:
+        sq = run_plain_seq("f32", args.steps * 4, args.warmup, args.pool)
+        record("plain_f32_seq", sq, 4, 4)
+        forms["plain_f32_seq"]["note"] = "buffered sequences: 64 frames per call, U kept in registers between frames"
+    if "plain_bf16_seq" in want:
+        sq = run_plain_seq("bf16", args.steps * 4, args.warmup, args.pool)
+        record("plain_bf16_seq", sq, 2, 2)
+        forms["plain_bf16_seq"]["note"] = "buffered sequences: 64 frames per call, U kept in registers between frames"
     if "plain_bf16" in want:
         plain_bf16 = run_plain("bf16", args.steps * 4, args.warmup, args.pool)
         record("plain_bf16", plain_bf16, 2, 2)

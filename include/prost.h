@@ -174,6 +174,22 @@ PROS_API pros_status pros_get_state(pros_handle* h, double* U, double* y, uint8_
  * kernels.  Asynchronous. */
 PROS_API pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device);
 
+/* A buffered sequence: frames[0 .. count-1] (a host array of device
+ * pointers, each m entries of the storage dtype) are processed in order,
+ * exactly as count calls of pros_track_frame(h, frames[i], dtype, 1) would
+ * (same results, bit for bit), but up to 256 frames share one launch of the
+ * persistent kernel: every workgroup keeps its tile of U in registers from
+ * one frame to the next (U is still written every frame) and the next
+ * frame's weights come from the labels it has just produced, so neither the
+ * launch nor the reload of U is paid per frame.  The 3x3 masks of the
+ * intermediate frames are not formed (pros_get_mask afterwards gives the
+ * last frame's); a launch ends where a re-orthonormalisation is due.
+ * Options whose state crosses tiles between frames (weights_from_filtered,
+ * pre-processing, score output, the IRLS step or curvature schedule 1) fall
+ * back to one launch per frame.  The frames must stay unmodified until the
+ * work is done.  Asynchronous. */
+PROS_API pros_status pros_track_frames(pros_handle* h, const void* const* frames, int32_t count, int32_t dtype);
+
 /* Segmentation quality (the measures of Sec. 5 follow from these counts:
  * Recall = TP/(TP+FN), Specificity = TN/(TN+FP), FPR = FP/(FP+TN),
  * FNR = FN/(TP+FN), PWC = 100 (FN+FP)/(TP+FN+FP+TN), Precision =

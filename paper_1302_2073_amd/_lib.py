@@ -82,6 +82,7 @@ _SIGS = {
     "pros_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "pros_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]),
     "pros_track_frame": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    "pros_track_frames": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.c_int32]),
     "pros_get_mask": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
     "pros_get_stats": (C.c_int, [C.c_void_p, C.POINTER(pros_stats)]),
     "pros_sync": (C.c_int, [C.c_void_p]),

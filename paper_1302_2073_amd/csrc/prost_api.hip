@@ -167,7 +167,7 @@ pros_status pros_validate(const pros_params* p) {
 void prost_host::free_handle(pros_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->U, h->xstage, h->lab, h->mask, h->y, h->nframe, h->stats, h->part, h->sync, h->reorth_ws,
-                  h->pre_mean, h->pre_m2, h->pre_stat};
+                  h->pre_mean, h->pre_m2, h->pre_stat, (void*)h->seq};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete h;
@@ -185,6 +185,8 @@ int prost_host::tile_pixels(int storage, int NR, int channels, double scale) {
 // one-exchange curvature schedule): wide exchange slots, optional-feature
 // kernels.
 static bool wide_exchange(const pros_handle* h) { return h->prm.ysolve == 2 || h->curv == 1; }
+
+constexpr int kSeqChunk = 256;   // frames per sequence launch (device pointer table)
 
 size_t prost_host::part_bytes(const pros_handle* h, int G) {
   size_t d = (2 * (size_t)G + prost::kExtraSlots) * prost::kSlot;
@@ -317,6 +319,7 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
   INIT_TRY(hipMalloc((void**)&h->y, sizeof(double) * PROS_MAX_K));
   INIT_TRY(hipMalloc((void**)&h->nframe, sizeof(long long)));
   INIT_TRY(hipMalloc((void**)&h->stats, sizeof(pros_stats)));
+  INIT_TRY(hipMalloc((void**)&h->seq, sizeof(void*) * kSeqChunk));
   INIT_TRY(hipMalloc((void**)&h->part, prost_host::part_bytes(h, h->G)));
   INIT_TRY(hipMalloc((void**)&h->sync, 64));
   INIT_TRY(hipMemsetAsync(h->U, 0, es * (size_t)h->ldU * h->k, h->stream));
@@ -537,9 +540,31 @@ FrameArgs prost_host::make_args(pros_handle* h, const void* x) {
   a.i_init = p.i_init;
   a.score = h->score;
   a.ysolve = p.ysolve;
+  a.seq = nullptr;
+  a.nseq = 1;
   return a;
 }
 
+
+// Launch frame kernel fn for a.nseq frames (a.x, then a.seq[1 ..]) and run a
+// re-orthonormalisation when one is due after them.
+static pros_status launch_frames(pros_handle* h, FrameArgs& a, const void* fn) {
+  void* args[] = {&a};
+  hipError_t e = h->coop ? hipLaunchCooperativeKernel(fn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream)
+                         : hipLaunchKernel(fn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream);
+  if (e != hipSuccess) {
+    h->broken = true;
+    h->broken_status = PROS_EHIP;
+    return fail(PROS_EHIP, "frame kernel launch failed: %s", hipGetErrorString(e));
+  }
+  h->submitted += a.nseq;
+  h->mask_stale = true;
+  if (h->prm.reorth_every > 0 && h->submitted % h->prm.reorth_every == 0) {
+    pros_status st = prost_reorth_launch(h);
+    if (st != PROS_OK) return st;
+  }
+  return PROS_OK;
+}
 
 pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device) {
   pros_status st = check_usable(h);
@@ -585,19 +610,43 @@ pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, i
     x = h->xstage;
   }
   FrameArgs a = make_args(h, x);
-  void* args[] = {&a};
-  hipError_t e = h->coop ? hipLaunchCooperativeKernel(h->kfn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream)
-                         : hipLaunchKernel(h->kfn, dim3(h->G), dim3(prost::kBlock), args, 0, h->stream);
-  if (e != hipSuccess) {
-    h->broken = true;
-    h->broken_status = PROS_EHIP;
-    return fail(PROS_EHIP, "frame kernel launch failed: %s", hipGetErrorString(e));
+  return launch_frames(h, a, h->kfn);
+}
+
+pros_status pros_track_frames(pros_handle* h, const void* const* frames, int32_t count, int32_t dtype) {
+  pros_status st = check_usable(h);
+  if (st != PROS_OK) return st;
+  if (!frames || count < 1) return fail(PROS_EINVAL, "frames is NULL or count < 1");
+  if (dtype != h->prm.storage) return fail(PROS_EINVAL, "device frames must have the storage dtype");
+  if (!h->state_set) return fail(PROS_ESTATE, "set U with pros_set_state before the first frame");
+  for (int i = 0; i < count; ++i)
+    if (!frames[i]) return fail(PROS_EINVAL, "frame %d is NULL", i);
+  // frames that depend on more than the tile's own state between frames
+  // (filtered-mask weights, pre-processing statistics, scores, the wide
+  // exchange) run one launch each
+  const void* fseq = prost::frame_kernel_seq(h->prm.storage == PROS_BF16, h->k, h->NR);
+  const bool seq_ok = fseq && !h->prm.weights_from_filtered && h->pre_mean == nullptr && h->score == nullptr &&
+                      !wide_exchange(h);
+  if (!seq_ok) {
+    for (int i = 0; i < count; ++i) {
+      st = pros_track_frame(h, frames[i], dtype, 1);
+      if (st != PROS_OK) return st;
+    }
+    return PROS_OK;
   }
-  ++h->submitted;
-  h->mask_stale = true;
-  if (h->prm.reorth_every > 0 && h->submitted % h->prm.reorth_every == 0) {
-    st = prost_reorth_launch(h);
+  for (int i = 0; i < count;) {
+    long long len = std::min(count - i, kSeqChunk);
+    if (h->prm.reorth_every > 0)   // end the launch where a re-orthonormalisation is due
+      len = std::min<long long>(len, h->prm.reorth_every - h->submitted % h->prm.reorth_every);
+    HIP_TRY(hipMemcpyAsync(h->seq, frames + i, sizeof(void*) * (size_t)len, hipMemcpyHostToDevice, h->stream));
+    FrameArgs a = make_args(h, frames[i]);
+    a.seq = (const void* const*)h->seq;
+    a.nseq = (int)len;
+    for (long long f = 1; f < len; ++f)
+      if (((uintptr_t)frames[i + f] & 3u) != 0) a.pair_aligned = 0;
+    st = launch_frames(h, a, fseq);
     if (st != PROS_OK) return st;
+    i += (int)len;
   }
   return PROS_OK;
 }

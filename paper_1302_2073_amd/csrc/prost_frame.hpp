@@ -61,6 +61,8 @@ struct FrameArgs {
                          // 3: every workgroup reads all tagged partials
   int curv;              // curvature schedule of a CG step: 0 = d^T H d in a second pass
                          // and exchange, 1 = H reduced with the gradient (one wide exchange)
+  const void* const* seq;  // frames 1 .. nseq - 1 of a sequence launch (frame 0 is x), device array
+  int nseq;                // frames processed by this launch (1: one frame)
 };
 
 constexpr int kReplicas = 8;      // copies of a gathered result (spread the pollers)
@@ -898,6 +900,23 @@ __device__ __forceinline__ void geodesic_setup(const FrameArgs& a, KSpace<kMaxK>
   __syncthreads();
 }
 
+// Start of frame i > 0 of a sequence launch (no median: the masks of
+// intermediate frames are not observable; y and the frame index carry over
+// in the workgroup, identical in every workgroup of the gang).
+__device__ __forceinline__ void next_frame_begin(KSpace<kMaxK>& ks, TileCtx& t, bool bad) {
+  if (!bad) ++t.n;
+  __syncthreads();   // everyone is past the previous frame's use of ks.flag and s_flag
+  if (thread_index() < 4) ks.flag[thread_index()] = 0;
+  __syncthreads();
+}
+
+// Label of tile pixel pl from the per-entry flags of the last labelled frame.
+__device__ __forceinline__ bool pixel_label(const uint8_t* s_flag, int C, int npx, int pl) {
+  uint8_t f = 0;
+  for (int c = 0; c < C; ++c) f |= s_flag[c * npx + pl];
+  return f != 0;
+}
+
 // Pixel labels (Sec. 3.3, Step 3): foreground when any colour entry was
 // flagged in s_flag (entry q = c * npx + pixel).
 __device__ __forceinline__ void write_labels(const FrameArgs& a, const uint8_t* s_flag, int p0, int npx) {
@@ -943,12 +962,12 @@ __device__ __forceinline__ void tile_end(const FrameArgs& a, const int tile, KSp
 // ---------------------------------------------------------------------------
 // float32 storage: row q = tid + s * kBlock of the tile, K floats per row
 // ---------------------------------------------------------------------------
-template <int K, int NR, bool EXT, bool WIDE>
+template <int K, int NR, bool EXT, bool WIDE, bool SEQ>
 __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, FrameSmem& sm) {
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
-  const int tid = thread_index();
-  const TileCtx ctx = tile_begin<K>(a, tile, ks);
+  int tid = thread_index();
+  TileCtx ctx = tile_begin<K>(a, tile, ks);
   int nbar = 0;
 
   // ---- load the register tile: U rows, residual r = x - U y, weights ----
@@ -987,6 +1006,14 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     }
   }
 
+  for (int fi = 0;;) {   // frames of this launch; U stays in the registers between them
+  if constexpr (SEQ) {
+    // Per-row indices re-enter opaquely each frame: otherwise every address
+    // derived from them is hoisted out of the frame loop and held in registers.
+    tid = thread_index();
+#pragma unroll
+    for (int s = 0; s < NR; ++s) asm volatile("" : "+v"(eix[s]));
+  }
   // ---- Step 1: CG on y ----
   int steps = 0, restarts = 0;
   for (int it = 0; it < a.J; ++it) {
@@ -1098,8 +1125,11 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
           }
           const float coef = fmaf(cm1, uv, -sz * (cw[s] - ua));
 #pragma unroll
-          for (int j = 0; j < K; ++j)
-            if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = fmaf(coef, ks.vf[j], u[s][j]);
+          for (int j = 0; j < K; ++j) {
+            const float nv = fmaf(coef, ks.vf[j], u[s][j]);   // columns >= k stay 0 (v_j = 0)
+            if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = nv;
+            if constexpr (SEQ) u[s][j] = nv;   // the next frame of a sequence starts from it
+          }
           if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
         }
         if (pre && pupd) pre_store(a, eix[s], xg[eix[s]], pinv_n);
@@ -1112,6 +1142,24 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     trace_point(a, tile, 62);
   }
   tile_end(a, tile, ks, ctx, steps, restarts, bad, nbar);
+  if (!SEQ || ++fi >= a.nseq) break;
+
+  // ---- next frame of a sequence: weights from this frame's labels (still in
+  // s_flag; unchanged after a rejected frame), residuals of the next frame ----
+  next_frame_begin(ks, ctx, bad);
+  xg = (const float*)a.seq[fi];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    if (eix[s] < 0) continue;
+    const int q = tid + s * kBlock;
+    const int pl = q - (q / ctx.npx) * ctx.npx;
+    if (!bad) wt[s] = pixel_label(s_flag, a.C, ctx.npx, pl) ? a.omega : 1.0f;
+    float acc = xg[eix[s]];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc = fmaf(-u[s][j], ks.yf[j], acc);
+    r[s] = acc;
+  }
+  }
   return true;
 }
 
@@ -1168,7 +1216,7 @@ __device__ __forceinline__ void st_u16(uint16_t* base, unsigned boff, uint16_t v
   *(uint16_t*)((char*)base + boff) = v;
 }
 
-template <int K, int NP, bool EXT, int NL = 0>
+template <int K, int NP, bool EXT, int NL = 0, bool SEQ = false>
 __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int tile, FrameSmem& sm,
                                                   uint32_t* __restrict__ lt = nullptr) {
   constexpr int NT = NP + NL;   // row pairs per thread: NP in registers, NL in LDS
@@ -1176,8 +1224,8 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   static_assert(NL == 0 || !EXT, "the LDS pairs serve the default features only");
   KSpace<kMaxK>& ks = sm.ks;
   uint8_t* s_flag = sm.flag;
-  const int tid = thread_index();
-  const TileCtx ctx = tile_begin<K>(a, tile, ks);
+  int tid = thread_index();
+  TileCtx ctx = tile_begin<K>(a, tile, ks);
   int nbar = 0;
   const bool al = a.pair_aligned != 0;
 
@@ -1284,6 +1332,8 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
     return ((vbits >> i) & 1u) ? (((fbits >> i) & 1u) ? om : 1.0f) : 0.f;
   };
 
+  for (int fi = 0;;) {   // frames of this launch; U stays in the registers between them
+  if constexpr (SEQ) tid = thread_index();   // re-enters opaquely each frame (see the float32 tile)
   // ---- Step 1: CG on y ----
   int steps = 0, restarts = 0;
   for (int it = 0; it < a.J; ++it) {
@@ -1466,16 +1516,19 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
         const float coef1 = fmaf(cm1, uv1, -sz * (cw[2 * s + 1] - ua1));
 #pragma unroll
         for (int j = 0; j < K; ++j)
-          if (j < a.k) {
+          if (SEQ || j < a.k) {   // columns >= k stay 0 (v_j = 0)
             const uint32_t nw = pack_bf16_rne(fmaf(coef0, ks.vf[j], bf_lo(u[s][j])),
                                               fmaf(coef1, ks.vf[j], bf_hi(u[s][j])));
-            uint16_t* col = Uw + (long long)j * a.ldU;
-            if (al) {
-              st_u32(col, 2u * (unsigned)e, nw);
-            } else {
-              st_u16(col, 2u * (unsigned)e, (uint16_t)(nw & 0xFFFFu));
-              if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(nw >> 16));
+            if (j < a.k) {
+              uint16_t* col = Uw + (long long)j * a.ldU;
+              if (al) {
+                st_u32(col, 2u * (unsigned)e, nw);
+              } else {
+                st_u16(col, 2u * (unsigned)e, (uint16_t)(nw & 0xFFFFu));
+                if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(nw >> 16));
+              }
             }
+            if constexpr (SEQ) u[s][j] = nw;   // the next frame of a sequence starts from it
           }
         if (a.labels_after_update) {
           rl0 = fmaf(-coef0, nu_f, rl0);
@@ -1551,6 +1604,40 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
     trace_point(a, tile, 62);
   }
   tile_end(a, tile, ks, ctx, steps, restarts, bad, nbar);
+  if (!SEQ || NL > 0 || ++fi >= a.nseq) break;   // sequences: register tiles only
+
+  // ---- next frame of a sequence (as in the float32 tile) ----
+  next_frame_begin(ks, ctx, bad);
+  xg = (const uint16_t*)a.seq[fi];
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+    const int q0 = 2 * (tid + s * kBlock);
+    if (q0 >= ctx.nq) continue;
+    const bool has1 = (vbits >> (2 * s + 1)) & 1u;
+    const bool split = (sbits >> s) & 1u;
+    const int c = q0 / ctx.npx;
+    const int pl = q0 - c * ctx.npx;
+    const int e = c * a.P + ctx.p0 + pl;
+    const int e1 = split ? e + 1 + (a.P - ctx.npx) : e + 1;
+    if (!bad) {
+      fbits &= ~(3u << (2 * s));
+      if (pixel_label(s_flag, a.C, ctx.npx, pl)) fbits |= 1u << (2 * s);
+      if (has1 && pixel_label(s_flag, a.C, ctx.npx, split ? 0 : pl + 1)) fbits |= 2u << (2 * s);
+    }
+    const unsigned b0 = 2u * (unsigned)e, b1 = 2u * (unsigned)e1;
+    uint32_t xw;
+    if (al) xw = ld_u32(xg, b0);
+    else xw = ld_u16(xg, b0) | (has1 ? (ld_u16(xg, b1) << 16) : 0u);
+    float acc0 = bf_lo(xw), acc1 = bf_hi(xw);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      acc0 = fmaf(-bf_lo(u[s][j]), ks.yf[j], acc0);
+      acc1 = fmaf(-bf_hi(u[s][j]), ks.yf[j], acc1);
+    }
+    r[2 * s] = acc0;
+    r[2 * s + 1] = has1 ? acc1 : 0.f;
+  }
+  }
   return true;
 }
 
@@ -1563,22 +1650,25 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 // variant and the one-exchange curvature schedule of CG) are compiled in as
 // well: float32 tiles of the single-stream kernel only, as the H partials
 // would spill the packed tile and the batch kernel's registers.
-template <int K, int NR, typename TS, bool EXT, bool WIDE = false, int NL = 0>
+// SEQ: the sequence form (a.nseq frames per launch, the tile kept in
+// registers between frames), a separate instantiation so that the one-frame
+// kernels carry none of its loop.
+template <int K, int NR, typename TS, bool EXT, bool WIDE = false, int NL = 0, bool SEQ = false>
 __device__ __forceinline__ bool run_tile(const FrameArgs& a, const int tile, FrameSmem& sm,
                                          uint32_t* __restrict__ lt = nullptr) {
   if constexpr (sizeof(TS) == 2) {
     static_assert(NR % 2 == 0, "bfloat16 tiles hold row pairs");
-    return frame_tile_packed<K, NR / 2, EXT, NL>(a, tile, sm, lt);
+    return frame_tile_packed<K, NR / 2, EXT, NL, SEQ>(a, tile, sm, lt);
   } else {
     static_assert(NL == 0, "LDS row pairs: bfloat16 tiles only");
-    return frame_tile<K, NR, EXT, WIDE>(a, tile, sm);
+    return frame_tile<K, NR, EXT, WIDE, SEQ>(a, tile, sm);
   }
 }
 
-template <int K, int NR, typename TS, bool EXT>
+template <int K, int NR, typename TS, bool EXT, bool SEQ = false>
 __global__ __launch_bounds__(kBlock, 2) void frame_kernel(FrameArgs a) {
   __shared__ FrameSmem sm;
-  run_tile<K, NR, TS, EXT, EXT>(a, blockIdx.x, sm);
+  run_tile<K, NR, TS, EXT, EXT, 0, SEQ>(a, blockIdx.x, sm);
 }
 
 }  // namespace prost

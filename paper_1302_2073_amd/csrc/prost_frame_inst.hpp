@@ -8,25 +8,25 @@
 
 namespace prost {
 
-template <typename TS, int KK, bool EXT>
+template <typename TS, int KK, bool EXT, bool SEQ = false>
 const void* frame_kernel_nr(int NR) {
   constexpr int KS = (KK <= 8) ? KK : 1;   // widest tile only for small K
   if constexpr (sizeof(TS) == 2) {
     switch (NR) {
-      case 2: return (const void*)&frame_kernel<KK, 2, TS, EXT>;
-      case 4: return (const void*)&frame_kernel<KK, 4, TS, EXT>;
-      case 8: return (const void*)&frame_kernel<KK, 8, TS, EXT>;
-      case 16: return (const void*)&frame_kernel<KK, 16, TS, EXT>;
-      case 32: return (KK <= 8) ? (const void*)&frame_kernel<KS, 32, TS, EXT> : nullptr;
+      case 2: return (const void*)&frame_kernel<KK, 2, TS, EXT, SEQ>;
+      case 4: return (const void*)&frame_kernel<KK, 4, TS, EXT, SEQ>;
+      case 8: return (const void*)&frame_kernel<KK, 8, TS, EXT, SEQ>;
+      case 16: return (const void*)&frame_kernel<KK, 16, TS, EXT, SEQ>;
+      case 32: return (KK <= 8) ? (const void*)&frame_kernel<KS, 32, TS, EXT, SEQ> : nullptr;
       default: return nullptr;
     }
   } else {
     switch (NR) {
-      case 1: return (const void*)&frame_kernel<KK, 1, TS, EXT>;
-      case 2: return (const void*)&frame_kernel<KK, 2, TS, EXT>;
-      case 4: return (const void*)&frame_kernel<KK, 4, TS, EXT>;
-      case 8: return (const void*)&frame_kernel<KK, 8, TS, EXT>;
-      case 16: return (KK <= 8) ? (const void*)&frame_kernel<KS, 16, TS, EXT> : nullptr;
+      case 1: return (const void*)&frame_kernel<KK, 1, TS, EXT, SEQ>;
+      case 2: return (const void*)&frame_kernel<KK, 2, TS, EXT, SEQ>;
+      case 4: return (const void*)&frame_kernel<KK, 4, TS, EXT, SEQ>;
+      case 8: return (const void*)&frame_kernel<KK, 8, TS, EXT, SEQ>;
+      case 16: return (KK <= 8) ? (const void*)&frame_kernel<KS, 16, TS, EXT, SEQ> : nullptr;
       default: return nullptr;
     }
   }
@@ -43,4 +43,16 @@ const void* frame_kernel_nr(int NR) {
       case K0 + 3: return ext ? frame_kernel_nr<TS, K0 + 3, true>(NR) : frame_kernel_nr<TS, K0 + 3, false>(NR); \
       default: return nullptr;                                                            \
     }                                                                                     \
+  }
+
+// The sequence form (default features only): name(K, NR).
+#define PROST_FRAME_SEQ_GROUP(name, TS, K0)                         \
+  const void* name(int K, int NR) {                                 \
+    switch (K) {                                                    \
+      case K0 + 0: return frame_kernel_nr<TS, K0 + 0, false, true>(NR); \
+      case K0 + 1: return frame_kernel_nr<TS, K0 + 1, false, true>(NR); \
+      case K0 + 2: return frame_kernel_nr<TS, K0 + 2, false, true>(NR); \
+      case K0 + 3: return frame_kernel_nr<TS, K0 + 3, false, true>(NR); \
+      default: return nullptr;                                      \
+    }                                                               \
   }

@@ -28,6 +28,7 @@ struct pros_handle {
   float* pre_m2 = nullptr;      // sum of squared deviations (m)
   double* pre_stat = nullptr;   // [0] entry sum of pre_m2, [1] initialization frames accumulated
   float* score = nullptr;       // caller's buffer for per-entry label scores (m floats), or NULL
+  void** seq = nullptr;         // device table of the frames of a sequence launch
   // launch configuration
   const void* kfn = nullptr;
   int G = 0, tpw = 0, NR = 0;

@@ -9,4 +9,7 @@ namespace prost {
 // not built.
 const void* frame_kernel_f32(int K, int NR, bool ext);
 const void* frame_kernel_bf16(int K, int NR, bool ext);
+// The sequence form (several frames per launch, default features) of the
+// same tile; nullptr when not built.
+const void* frame_kernel_seq(int bf16, int K, int NR);
 }  // namespace prost

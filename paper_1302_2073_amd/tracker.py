@@ -171,6 +171,18 @@ class Tracker:
             st = L.lib().pros_track_frame(self._h, _ptr(frame), dt, 1)
         L.check(st)
 
+    def track_many(self, frames):
+        """Queue a buffered sequence of device tensors (storage dtype, each
+        contiguous) through pros_track_frames: the same results as one
+        track() per frame, with up to 256 frames per kernel launch."""
+        import torch
+        frames = list(frames)
+        dt = {torch.float32: L.PROS_F32, torch.bfloat16: L.PROS_BF16}[frames[0].dtype]
+        for f in frames:
+            assert f.is_cuda and f.is_contiguous() and f.numel() == self.m and f.dtype == frames[0].dtype
+        ptrs = (C.c_void_p * len(frames))(*[f.data_ptr() for f in frames])
+        L.check(L.lib().pros_track_frames(self._h, ptrs, len(frames), dt))
+
     def mask(self, filtered=True, out=None):
         if out is not None:       # device tensor of P uint8, queued on the stream
             L.check(L.lib().pros_get_mask(self._h, _ptr(out), int(filtered), 1))
