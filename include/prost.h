@@ -181,9 +181,10 @@ PROS_API pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t
  * persistent kernel: every workgroup keeps its tile of U in registers from
  * one frame to the next (U is still written every frame) and the next
  * frame's weights come from the labels it has just produced, so neither the
- * launch nor the reload of U is paid per frame.  The 3x3 masks of the
- * intermediate frames are not formed (pros_get_mask afterwards gives the
- * last frame's); a launch ends where a re-orthonormalisation is due.
+ * launch nor the reload of U is paid per frame.  Every frame's 3x3 mask is
+ * formed, as in single launches, when the next frame has passed its first
+ * gang exchange (the last one by pros_get_mask); a launch ends where a
+ * re-orthonormalisation is due.
  * Options whose state crosses tiles between frames (weights_from_filtered,
  * pre-processing, score output, the IRLS step or curvature schedule 1) fall
  * back to one launch per frame.  The frames must stay unmodified until the
@@ -300,6 +301,14 @@ PROS_API pros_status pros_batch_get_state(pros_batch* b, int32_t s, double* U, d
 PROS_API pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int32_t ring);
 /* One batch step: every stream processes its next frame.  Asynchronous. */
 PROS_API pros_status pros_batch_track(pros_batch* b);
+/* `steps` batch steps (1..4096) with the same results as `steps` calls of
+ * pros_batch_track, in one launch: every (stream, tile) item of the
+ * schedule advances its stream by `steps` frames of the ring with its tile
+ * of U kept in registers between them (as pros_track_frames does for one
+ * stream).  For frames buffered ahead (the ring holds them).  Register
+ * budget 128 and the default features only; otherwise one launch per
+ * step.  Asynchronous. */
+PROS_API pros_status pros_batch_track_steps(pros_batch* b, int32_t steps);
 /* 1: capture the launch into a hipGraph on first use and replay it. */
 PROS_API pros_status pros_batch_use_graph(pros_batch* b, int32_t on);
 PROS_API pros_status pros_batch_sync(pros_batch* b);

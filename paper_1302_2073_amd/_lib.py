@@ -117,6 +117,7 @@ _SIGS = {
                                        C.POINTER(C.c_int64)]),
     "pros_batch_set_frames": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32]),
     "pros_batch_track": (C.c_int, [C.c_void_p]),
+    "pros_batch_track_steps": (C.c_int, [C.c_void_p, C.c_int32]),
     "pros_batch_use_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "pros_batch_sync": (C.c_int, [C.c_void_p]),
     "pros_batch_get_mask": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32]),

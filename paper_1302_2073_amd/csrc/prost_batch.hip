@@ -23,6 +23,28 @@ const void* batch_kernel_k10(int, int, bool);
 const void* batch_kernel_k12(int, int, bool);
 const void* batch_kernel_k15(int, int, bool);
 const void* batch_kernel_k16(int, int, bool);
+const void* batch_kernel_seq_k2(int);
+const void* batch_kernel_seq_k4(int);
+const void* batch_kernel_seq_k5(int);
+const void* batch_kernel_seq_k8(int);
+const void* batch_kernel_seq_k10(int);
+const void* batch_kernel_seq_k12(int);
+const void* batch_kernel_seq_k15(int);
+const void* batch_kernel_seq_k16(int);
+
+const void* batch_kernel_seq_ptr(int bf16, int K) {
+  switch (K) {
+    case 2: return batch_kernel_seq_k2(bf16);
+    case 4: return batch_kernel_seq_k4(bf16);
+    case 5: return batch_kernel_seq_k5(bf16);
+    case 8: return batch_kernel_seq_k8(bf16);
+    case 10: return batch_kernel_seq_k10(bf16);
+    case 12: return batch_kernel_seq_k12(bf16);
+    case 15: return batch_kernel_seq_k15(bf16);
+    case 16: return batch_kernel_seq_k16(bf16);
+    default: return nullptr;
+  }
+}
 
 const void* batch_kernel_ptr(int bf16, int K, int budget, bool ext) {
   switch (K) {
@@ -79,6 +101,11 @@ struct pros_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool broken = false;
+  bool ext = false;              // a stream uses the optional features
+  // multi-step launches: descriptors with nseq = seq_steps
+  FrameArgs* d_descs_seq = nullptr;
+  int seq_steps = 0;
+  long long descs_version = 0, seq_version = -1;
 };
 
 static void drop_graph(pros_batch* b) {
@@ -94,6 +121,7 @@ static void free_batch(pros_batch* b) {
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   for (pros_handle* h : b->hs) prost_host::free_handle(h);
   if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_descs_seq) (void)hipFree(b->d_descs_seq);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_xtab) (void)hipFree((void*)b->d_xtab);
   delete b;
@@ -191,17 +219,20 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
   if (e != hipSuccess) return fail(PROS_EHIP, "schedule upload: %s", hipGetErrorString(e));
   e = hipMemcpy(b->d_descs, b->descs.data(), sizeof(FrameArgs) * b->n, hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(PROS_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+  ++b->descs_version;
+  b->ext = ext;
   drop_graph(b);
   return PROS_OK;
 }
 
-static pros_status launch(pros_batch* b, hipStream_t on) {
-  FrameArgs* d = b->d_descs;
+static pros_status launch(pros_batch* b, hipStream_t on, const void* fn = nullptr, FrameArgs* descs = nullptr) {
+  FrameArgs* d = descs ? descs : b->d_descs;
   BatchItem* it = b->d_items;
   int rounds = b->rounds;
   void* args[] = {&d, &it, &rounds};
-  hipError_t e = b->coop ? hipLaunchCooperativeKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on)
-                         : hipLaunchKernel(b->kfn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on);
+  if (!fn) fn = b->kfn;
+  hipError_t e = b->coop ? hipLaunchCooperativeKernel(fn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on)
+                         : hipLaunchKernel(fn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on);
   if (e != hipSuccess) {
     b->broken = true;
     return fail(PROS_EHIP, "batch kernel launch: %s", hipGetErrorString(e));
@@ -343,6 +374,7 @@ pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int3
   if (descs_changed) {   // descriptors are read by the kernel at run time (also from a graph)
     e = hipMemcpy(b->d_descs, b->descs.data(), sizeof(FrameArgs) * b->n, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(PROS_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+    ++b->descs_version;
   }
   e = hipMemcpy((void*)b->d_xtab, frames, sizeof(void*) * (size_t)b->n * ring, hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(PROS_EHIP, "frame table upload: %s", hipGetErrorString(e));
@@ -386,6 +418,46 @@ pros_status pros_batch_track(pros_batch* b) {
   }
   for (pros_handle* h : b->hs) {
     ++h->submitted;
+    h->mask_stale = true;
+  }
+  return PROS_OK;
+}
+
+pros_status pros_batch_track_steps(pros_batch* b, int32_t steps) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (steps < 1 || steps > 4096) return fail(PROS_EINVAL, "steps must be 1..4096");
+  if (steps == 1) return pros_batch_track(b);
+  if (!b->frames_set) return fail(PROS_ESTATE, "register frames with pros_batch_set_frames first");
+  bool filtered = false;
+  for (pros_handle* h : b->hs) {
+    if (!h->state_set) return fail(PROS_ESTATE, "set every stream's U before the first batch step");
+    filtered = filtered || h->prm.weights_from_filtered;
+  }
+  const void* fn = prost::batch_kernel_seq_ptr(b->storage == PROS_BF16, b->kclass);
+  if (!fn || b->budget != 128 || b->ext || filtered) {   // one launch per step
+    for (int i = 0; i < steps; ++i) {
+      st = pros_batch_track(b);
+      if (st != PROS_OK) return st;
+    }
+    return PROS_OK;
+  }
+  hipError_t e = hipSuccess;
+  if (!b->d_descs_seq) e = hipMalloc((void**)&b->d_descs_seq, sizeof(FrameArgs) * b->n);
+  if (e != hipSuccess) return fail(PROS_ENOMEM, "descriptors: %s", hipGetErrorString(e));
+  if (b->seq_steps != steps || b->seq_version != b->descs_version) {
+    std::vector<FrameArgs> d = b->descs;
+    for (FrameArgs& a : d) a.nseq = steps;
+    e = hipStreamSynchronize(b->stream);   // a running launch may still read the table
+    if (e == hipSuccess) e = hipMemcpy(b->d_descs_seq, d.data(), sizeof(FrameArgs) * b->n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(PROS_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+    b->seq_steps = steps;
+    b->seq_version = b->descs_version;
+  }
+  st = launch(b, b->stream, fn, b->d_descs_seq);
+  if (st != PROS_OK) return st;
+  for (pros_handle* h : b->hs) {
+    h->submitted += steps;
     h->mask_stale = true;
   }
   return PROS_OK;

@@ -73,7 +73,9 @@ __device__ __forceinline__ FrameArgs load_uniform(const FrameArgs* __restrict__ 
   return a;
 }
 
-template <typename TS, int K, int NR, bool EXT, int NL = 0>
+// SEQ: every item advances its stream by a.nseq frames of its ring with the
+// tile kept in registers (several batch steps per launch).
+template <typename TS, int K, int NR, bool EXT, int NL = 0, bool SEQ = false>
 __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __restrict__ descs,
                                                        const BatchItem* __restrict__ items, int rounds) {
   __shared__ FrameSmem sm;
@@ -82,8 +84,15 @@ __global__ __launch_bounds__(kBlock, 2) void batch_kernel(const FrameArgs* __res
     const BatchItem it = items[(size_t)r * gridDim.x + blockIdx.x];
     if (it.stream < 0) continue;
     const FrameArgs a = load_uniform(descs + it.stream);
-    if (!run_tile<K, NR, TS, EXT, false, NL>(a, it.tile, sm, lt)) return;
+    if (!run_tile<K, NR, TS, EXT, false, NL, SEQ>(a, it.tile, sm, lt)) return;
   }
+}
+
+// The multi-step form of class K at register budget 128 (default features).
+template <int K>
+const void* batch_kernel_seq(int storage_bf16) {
+  return storage_bf16 ? (const void*)&batch_kernel<uint16_t, K, batch_nr_bf16(128, K), false, 0, true>
+                      : (const void*)&batch_kernel<float, K, batch_nr(128, K), false, 0, true>;
 }
 
 // The LDS form of class K (bfloat16, default features).
@@ -98,5 +107,6 @@ const void* batch_kernel_lds() {
 // Kernel for (storage, class K, budget, optional features compiled in);
 // nullptr if not built.
 const void* batch_kernel_ptr(int storage_bf16, int K, int budget, bool ext);
+const void* batch_kernel_seq_ptr(int storage_bf16, int K);
 
 }  // namespace prost

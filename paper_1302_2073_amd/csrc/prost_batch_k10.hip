@@ -15,4 +15,5 @@ const void* batch_kernel_k10(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 10, batch_nr(64, 10), false>
                              : (const void*)&batch_kernel<float, 10, batch_nr(128, 10), false>);
 }
+const void* batch_kernel_seq_k10(int storage_bf16) { return batch_kernel_seq<10>(storage_bf16); }
 }  // namespace prost

@@ -15,4 +15,5 @@ const void* batch_kernel_k12(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 12, batch_nr(64, 12), false>
                              : (const void*)&batch_kernel<float, 12, batch_nr(128, 12), false>);
 }
+const void* batch_kernel_seq_k12(int storage_bf16) { return batch_kernel_seq<12>(storage_bf16); }
 }  // namespace prost

@@ -15,4 +15,5 @@ const void* batch_kernel_k15(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 15, batch_nr(64, 15), false>
                              : (const void*)&batch_kernel<float, 15, batch_nr(128, 15), false>);
 }
+const void* batch_kernel_seq_k15(int storage_bf16) { return batch_kernel_seq<15>(storage_bf16); }
 }  // namespace prost

@@ -15,4 +15,5 @@ const void* batch_kernel_k16(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 16, batch_nr(64, 16), false>
                              : (const void*)&batch_kernel<float, 16, batch_nr(128, 16), false>);
 }
+const void* batch_kernel_seq_k16(int storage_bf16) { return batch_kernel_seq<16>(storage_bf16); }
 }  // namespace prost

@@ -15,4 +15,5 @@ const void* batch_kernel_k2(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 2, batch_nr(64, 2), false>
                              : (const void*)&batch_kernel<float, 2, batch_nr(128, 2), false>);
 }
+const void* batch_kernel_seq_k2(int storage_bf16) { return batch_kernel_seq<2>(storage_bf16); }
 }  // namespace prost

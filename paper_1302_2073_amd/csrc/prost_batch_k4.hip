@@ -15,4 +15,5 @@ const void* batch_kernel_k4(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 4, batch_nr(64, 4), false>
                              : (const void*)&batch_kernel<float, 4, batch_nr(128, 4), false>);
 }
+const void* batch_kernel_seq_k4(int storage_bf16) { return batch_kernel_seq<4>(storage_bf16); }
 }  // namespace prost

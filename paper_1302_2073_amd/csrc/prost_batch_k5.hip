@@ -15,4 +15,5 @@ const void* batch_kernel_k5(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 5, batch_nr(64, 5), false>
                              : (const void*)&batch_kernel<float, 5, batch_nr(128, 5), false>);
 }
+const void* batch_kernel_seq_k5(int storage_bf16) { return batch_kernel_seq<5>(storage_bf16); }
 }  // namespace prost

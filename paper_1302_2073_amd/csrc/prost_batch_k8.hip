@@ -15,4 +15,5 @@ const void* batch_kernel_k8(int storage_bf16, int budget, bool ext) {
              : (budget == 64 ? (const void*)&batch_kernel<float, 8, batch_nr(64, 8), false>
                              : (const void*)&batch_kernel<float, 8, batch_nr(128, 8), false>);
 }
+const void* batch_kernel_seq_k8(int storage_bf16) { return batch_kernel_seq<8>(storage_bf16); }
 }  // namespace prost

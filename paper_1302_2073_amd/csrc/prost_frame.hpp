@@ -61,7 +61,8 @@ struct FrameArgs {
                          // 3: every workgroup reads all tagged partials
   int curv;              // curvature schedule of a CG step: 0 = d^T H d in a second pass
                          // and exchange, 1 = H reduced with the gradient (one wide exchange)
-  const void* const* seq;  // frames 1 .. nseq - 1 of a sequence launch (frame 0 is x), device array
+  const void* const* seq;  // frames 1 .. nseq - 1 of a sequence launch (frame 0 is x), device array;
+                           // with xtab (batched form) the ring is read instead
   int nseq;                // frames processed by this launch (1: one frame)
 };
 
@@ -495,6 +496,9 @@ __device__ __forceinline__ bool gang_reduce(float (&acc)[L], const FrameArgs& a,
 
 // 3x3 median of binary labels (>= 5 of the 9 neighbours, edges replicated,
 // Sec. 3.4) for pixels [p0, p0 + npx) of a W x H image.
+// COH: the labels were written in this launch by other workgroups, with
+// device-coherent stores; read them with device-coherent loads.
+template <bool COH = false>
 __device__ __forceinline__ void median3x3_range(const uint8_t* __restrict__ lab, uint8_t* __restrict__ mask, int W,
                                                 int H, int p0, int npx) {
   for (int pl = thread_index(); pl < npx; pl += blockDim.x) {
@@ -506,7 +510,10 @@ __device__ __forceinline__ void median3x3_range(const uint8_t* __restrict__ lab,
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) cnt += lab[rows[i] * W + cols[j]];
+      for (int j = 0; j < 3; ++j) {
+        const uint8_t* p = lab + rows[i] * W + cols[j];
+        cnt += COH ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+      }
     mask[pix] = (cnt >= 5) ? 1 : 0;
   }
 }
@@ -900,14 +907,28 @@ __device__ __forceinline__ void geodesic_setup(const FrameArgs& a, KSpace<kMaxK>
   __syncthreads();
 }
 
-// Start of frame i > 0 of a sequence launch (no median: the masks of
-// intermediate frames are not observable; y and the frame index carry over
-// in the workgroup, identical in every workgroup of the gang).
+// Start of frame i > 0 of a sequence launch: y and the frame index carry
+// over in the workgroup (identical in every workgroup of the gang).  The
+// finished frame's labels went out with device-coherent stores; every thread
+// waits for its stores to complete before any partial of the next frame is
+// published, so that the mask of the finished frame (its 3x3 median reads
+// neighbouring tiles' labels) can be formed after the next frame's first
+// exchange (sequence_median), which no workgroup completes before all have
+// published.  (A device-scope release / acquire fence pair would also
+// write back and invalidate the L2: measured 3x slower.)
 __device__ __forceinline__ void next_frame_begin(KSpace<kMaxK>& ks, TileCtx& t, bool bad) {
   if (!bad) ++t.n;
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's stores have completed
   __syncthreads();   // everyone is past the previous frame's use of ks.flag and s_flag
   if (thread_index() < 4) ks.flag[thread_index()] = 0;
   __syncthreads();
+}
+
+// The deferred median of a sequence frame: the previous frame's labels of
+// the whole gang are complete once this frame's first exchange is, and no
+// workgroup writes this frame's labels before the last exchange.
+__device__ __forceinline__ void sequence_median(const FrameArgs& a, const TileCtx& t) {
+  median3x3_range<true>(a.lab, a.mask, a.W, a.H, t.p0, t.npx);
 }
 
 // Label of tile pixel pl from the per-entry flags of the last labelled frame.
@@ -918,13 +939,18 @@ __device__ __forceinline__ bool pixel_label(const uint8_t* s_flag, int C, int np
 }
 
 // Pixel labels (Sec. 3.3, Step 3): foreground when any colour entry was
-// flagged in s_flag (entry q = c * npx + pixel).
+// flagged in s_flag (entry q = c * npx + pixel).  COH: device-coherent
+// stores (read by other workgroups in the same launch).
+template <bool COH = false>
 __device__ __forceinline__ void write_labels(const FrameArgs& a, const uint8_t* s_flag, int p0, int npx) {
   __syncthreads();
   for (int pl = thread_index(); pl < npx; pl += kBlock) {
     uint8_t f = 0;
     for (int c = 0; c < a.C; ++c) f |= s_flag[c * npx + pl];
-    a.lab[p0 + pl] = f;
+    if (COH)
+      __hip_atomic_store(&a.lab[p0 + pl], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      a.lab[p0 + pl] = f;
   }
 }
 
@@ -1061,6 +1087,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       continue;
     }
     if (!gang_reduce<K + 1>(acc, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    if (SEQ && fi > 0 && it == 0) sequence_median(a, ctx);
     cg_direction<K>(a, ks, it, ctx.lead, restarts);
     if (ks.flag[0]) break;
     // phase B: curvature of the majoriser along d; cw then holds u.d
@@ -1138,7 +1165,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
       }
     }
     trace_point(a, tile, 61);
-    write_labels(a, s_flag, ctx.p0, ctx.npx);
+    write_labels<SEQ>(a, s_flag, ctx.p0, ctx.npx);
     trace_point(a, tile, 62);
   }
   tile_end(a, tile, ks, ctx, steps, restarts, bad, nbar);
@@ -1147,7 +1174,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   // ---- next frame of a sequence: weights from this frame's labels (still in
   // s_flag; unchanged after a rejected frame), residuals of the next frame ----
   next_frame_begin(ks, ctx, bad);
-  xg = (const float*)a.seq[fi];
+  xg = (const float*)(a.xtab ? a.xtab[ctx.n % a.ring] : a.seq[fi]);
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     if (eix[s] < 0) continue;
@@ -1378,6 +1405,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
       }
     }
     if (!gang_reduce<K + 1>(acc, a, tile, nbar, ctx.base, ctx.ebase, sm, ks.red)) return false;
+    if (SEQ && fi > 0 && it == 0) sequence_median(a, ctx);
     cg_direction<K>(a, ks, it, ctx.lead, restarts);
     if (ks.flag[0]) break;
     float accb[1] = {0.f};
@@ -1600,7 +1628,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
       if (has1) s_flag[q0 + 1] = (fabsf(rl1) >= a.delta) ? 1 : 0;
     }
     trace_point(a, tile, 61);
-    write_labels(a, s_flag, ctx.p0, ctx.npx);
+    write_labels<SEQ>(a, s_flag, ctx.p0, ctx.npx);
     trace_point(a, tile, 62);
   }
   tile_end(a, tile, ks, ctx, steps, restarts, bad, nbar);
@@ -1608,7 +1636,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
 
   // ---- next frame of a sequence (as in the float32 tile) ----
   next_frame_begin(ks, ctx, bad);
-  xg = (const uint16_t*)a.seq[fi];
+  xg = (const uint16_t*)(a.xtab ? a.xtab[ctx.n % a.ring] : a.seq[fi]);
 #pragma unroll
   for (int s = 0; s < NP; ++s) {
     const int q0 = 2 * (tid + s * kBlock);

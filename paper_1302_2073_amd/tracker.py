@@ -318,6 +318,10 @@ class BatchTracker:
     def step(self):
         L.check(L.lib().pros_batch_track(self._b))
 
+    def steps(self, n):
+        """n batch steps in one launch (pros_batch_track_steps)."""
+        L.check(L.lib().pros_batch_track_steps(self._b, int(n)))
+
     def use_graph(self, on=True):
         L.check(L.lib().pros_batch_use_graph(self._b, int(bool(on))))
 

@@ -283,3 +283,33 @@ def test_ordinary_dispatch_is_bitwise_equal(graph):
     for sa, sb in zip(res[0], res[1]):
         for a, b in zip(sa, sb):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_multi_step_launch_is_bitwise_equal(storage):
+    """pros_batch_track_steps(b, 3) twice equals six single steps: each item
+    keeps its tile in registers over three frames of its ring."""
+    from paper_1302_2073_amd.tracker import BatchTracker
+    streams = _streams(SHAPES[:4])
+    res = []
+    for multi in (False, True):
+        with BatchTracker(_specs(streams), storage=storage) as bt:
+            bt.configure(register_budget=128, workgroups_per_cu=1)
+            bt.set_frames(_frames_tensor(streams, 4, 4, storage))
+            _load(bt, streams)
+            if multi:
+                bt.steps(3)
+                bt.steps(3)
+            else:
+                for _ in range(6):
+                    bt.step()
+            assert bt.sync() == 0
+            res.append([bt.get_state(s) for s in range(len(streams))] +
+                       [bt.mask(s) for s in range(len(streams))])
+    say(f"  {storage}: n = {[int(st[3]) for st in res[1][:len(streams)]]}")
+    for sa, sb in zip(res[0], res[1]):
+        if isinstance(sa, tuple):
+            for a, b in zip(sa, sb):
+                np.testing.assert_array_equal(a, b)
+        else:
+            np.testing.assert_array_equal(sa, sb)
