@@ -172,3 +172,13 @@ def test_upsample_and_ingest_reject_bad_arguments_without_touching_the_gpu():
     assert L.lib().pros_ingest_init(None, 64, 48, 2, 1.0 / 255, C.byref(g)) == L.PROS_EINVAL
     assert g.value is None
     assert L.lib().pros_ingest_submit(None) == L.PROS_EINVAL
+
+
+def test_new_entry_points_reject_null_handles_without_touching_the_gpu():
+    L = _lib()
+    ptrs = (C.c_void_p * 1)(C.c_void_p(16))
+    assert L.lib().pros_track_frames(None, ptrs, 1, L.PROS_F32) == L.PROS_EINVAL
+    assert L.lib().pros_batch_track_steps(None, 4) == L.PROS_EINVAL
+    assert L.lib().pros_set_dispatch(None, 0) == L.PROS_EINVAL
+    assert L.lib().pros_batch_set_dispatch(None, 0) == L.PROS_EINVAL
+    assert L.lib().pros_set_curvature(None, 1) == L.PROS_EINVAL

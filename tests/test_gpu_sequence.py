@@ -98,3 +98,11 @@ def test_sequence_with_ordinary_dispatch_and_fallback_options():
     # filtered-mask weights run one launch per frame
     _same(_run(wl, frames, "f32", False, weights_from_filtered=True),
           _run(wl, frames, "f32", True, weights_from_filtered=True))
+
+
+def test_sequence_longer_than_one_launch():
+    """300 frames: two launches (256 + 44), still equal to 300 single
+    launches."""
+    wl = V.small_gray()
+    frames = _frames(wl, 300, "f32")
+    _same(_run(wl, frames, "f32", False), _run(wl, frames, "f32", True))
