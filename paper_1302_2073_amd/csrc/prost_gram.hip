@@ -152,6 +152,11 @@ __global__ __launch_bounds__(256) void gram_apply(TS* __restrict__ U, long long 
   for (int q = threadIdx.x; q < K * K; q += 256) M[q / K][q % K] = ws[(q / K) * kMaxK + (q % K)];
   __syncthreads();
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < m; e += (long long)gridDim.x * 256) {
+    // an offset the compiler cannot see is zero: the LDS reads of M stay in
+    // the loop instead of being hoisted into (K * K * 2) registers and spilled
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    const double* Ml = &M[0][0] + z;
     double u[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) u[i] = (double)ld_elem(U, (long long)i * ldU + e);
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(256) void gram_apply(TS* __restrict__ U, long long 
     for (int j = 0; j < K; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < K; ++i) s = fma(u[i], M[i][j], s);
+      for (int i = 0; i < K; ++i) s = fma(u[i], Ml[i * K + j], s);
       st_elem(U, (long long)j * ldU + e, (float)s);
     }
   }
