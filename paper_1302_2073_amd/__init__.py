@@ -7,11 +7,15 @@ the C ABI of include/prost.h; this package only marshals arguments.
 """
 from . import _lib  # noqa: F401
 
-__all__ = ["Tracker", "make_params", "roc_counts"]
+__all__ = ["Tracker", "BatchTracker", "make_params", "roc_counts", "Ingest", "resample_rgb8", "mask_upsample"]
 
 
 def __getattr__(name):
-    if name in ("Tracker", "make_params", "bf16_bits", "bf16_to_f64", "roc_counts"):
+    if name in ("Tracker", "BatchTracker", "make_params", "bf16_bits", "bf16_to_f64", "roc_counts",
+                "quality_measures"):
         from . import tracker
         return getattr(tracker, name)
+    if name in ("Ingest", "resample_rgb8", "mask_upsample"):
+        from . import ingest
+        return getattr(ingest, name)
     raise AttributeError(name)
