@@ -428,6 +428,49 @@ def cpu_baseline(seconds=15.0):
                 sample=f"{n} frames of 640x480x3 k=15 (float64 numpy oracle, {el:.1f} s)")
 
 
+def oracle_table(seconds=8.0):
+    """The float64 oracle on every workload (bounded samples), on one host
+    thread and on all of them: frames/s (forward + backward passes/s for the
+    differentiation form).  Printed by --oracle-table as one JSON line."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import prost_oracle as O
+    from synth import video as V
+    allc = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    rows = []
+    for name in ("small_gray", "qvga_rgb", "vga_rgb"):
+        wl = getattr(V, name)()
+        v = wl.video
+        sv = V.SyntheticVideo(v)
+        prm = O.Params(v.width, v.height, v.channels, k=wl.k, mu=wl.mu, delta=wl.delta, cost=wl.cost)
+        frames = [sv.frame(n).astype(np.float32).astype(np.float64) for n in range(4)]
+        for threads in (1, allc):
+            with threadpool_limits(limits=threads):
+                st = O.initial_state(V.initial_subspace(prm.m, wl.k, v.seed), prm.P)
+                n, t0 = 0, time.perf_counter()
+                while True:
+                    st, _ = O.track_frame(st, frames[n % 4], prm)
+                    n += 1
+                    el = time.perf_counter() - t0
+                    if el >= seconds or n >= 400:
+                        break
+            rows.append(dict(workload=f"{v.width}x{v.height}x{v.channels} k={wl.k}", threads=threads,
+                             frames_per_s=round(n / el, 3), frames=n))
+    U, Y, X, w = V.lpcost_batch()
+    for threads in (1, allc):
+        with threadpool_limits(limits=threads):
+            n, t0 = 0, time.perf_counter()
+            while True:
+                O.lpcost_forward(U, Y, X, w, 0.25, 1e-3)
+                O.lpcost_backward(U, Y, X, w, 0.25, 1e-3, np.ones(Y.shape[1]))
+                n += 1
+                el = time.perf_counter() - t0
+                if el >= seconds or n >= 400:
+                    break
+        rows.append(dict(workload="lpcost fwd+bwd m=230400 k=10 B=32", threads=threads,
+                         passes_per_s=round(n / el, 3), passes=n))
+    return dict(kind="oracle", host_threads=allc, rows=rows)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +479,8 @@ def main():
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--streams", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="only time the float64 oracle on every workload (1 and all host threads)")
     # also available: plain_f32_curv1, plain_f32_ordinary, batched_bf16_ordinary
     ap.add_argument("--forms", default="plain_f32,plain_f32_seq,plain_bf16,plain_bf16_seq,plain_f32_host,"
                     "batched_bf16,batched_bf16_seq,batched_mixed_bf16,batched_mixed_bf16_seq,lpcost,"
@@ -446,6 +491,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.oracle_table:
+        print(json.dumps(oracle_table()), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
               f"shards by independent streams, see the design notes.", file=sys.stderr)
