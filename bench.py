@@ -484,7 +484,7 @@ def main():
     # also available: plain_f32_curv1, plain_f32_ordinary, batched_bf16_ordinary
     ap.add_argument("--forms", default="plain_f32,plain_f32_seq,plain_bf16,plain_bf16_seq,plain_f32_host,"
                     "batched_bf16,batched_bf16_seq,batched_mixed_bf16,batched_mixed_bf16_seq,lpcost,"
-                    "quality,ingest",
+                    "quality,ingest,stream_copy",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -633,13 +633,28 @@ def main():
                                         "frame; roc_call_ms is the host-timed sweep call (12 thresholds)")
         except Exception as exc:   # a side form must not cost the headline line
             forms["quality"] = {"error": repr(exc)[:300]}
-    if args.copy_probe_mib:
+    if args.copy_probe_mib:   # one copy of known size (counter calibration under rocprofv3)
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         forms["copy_probe"] = {"bytes_read": 4 * n, "bytes_written": 4 * n}
+    if "stream_copy" in want:   # achievable HBM bandwidth beside the published 8 TB/s
+        try:
+            n = (1 << 30) // 4
+            a = torch.ones(n, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+            ms, lo, hi = timed_median(lambda i: b.copy_(a), 10, torch.cuda.current_stream())
+            gbps = 2 * 4 * n * 10 / (ms * 1e-3) / 1e9
+            forms["stream_copy"] = {"GBps": round(gbps, 1), "frac_of_hbm_peak": round(gbps / PEAK_HBM_GBS, 4),
+                                    "note": "1 GiB device-to-device copy (read + write), torch copy kernel"}
+            del a, b
+        except Exception as exc:
+            forms["stream_copy"] = {"error": repr(exc)[:300]}
     head = bsq if bsq is not None else (batched if batched is not None else plain)
     if head is None:   # a diagnostic run of other forms only: no headline
         print(json.dumps({"metric": None, "value": None, "forms": forms}), flush=True)
