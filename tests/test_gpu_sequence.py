@@ -106,3 +106,28 @@ def test_sequence_longer_than_one_launch():
     wl = V.small_gray()
     frames = _frames(wl, 300, "f32")
     _same(_run(wl, frames, "f32", False), _run(wl, frames, "f32", True))
+
+
+def _odd_spec():
+    v = V.VideoSpec(41, 29, 3, rank=3, seed=77, noise=0.01, fg_kind="rects", fg_count=2, fg_density=0.1)
+    return V.Workload("41x29x3", v, k=6, mu=1e-3, n_frames=20)
+
+
+@pytest.mark.parametrize("unaligned", [False, True])
+def test_bf16_sequence_with_split_pairs_and_unaligned_frames(unaligned):
+    """Odd P (row pairs that continue in the next colour plane) and, with
+    `unaligned`, frames at an odd bfloat16 offset (no 32-bit pair access):
+    the sequence launch still equals one launch per frame."""
+    import torch
+    wl = _odd_spec()
+    frames = _frames(wl, 10, "bf16")
+    if unaligned:
+        m = frames[0].numel()
+        buf = torch.empty(len(frames) * m + 1, dtype=torch.bfloat16, device="cuda")
+        views = []
+        for i, f in enumerate(frames):
+            v = buf[1 + i * m:1 + (i + 1) * m]
+            v.copy_(f)
+            views.append(v)
+        frames = views
+    _same(_run(wl, frames, "bf16", False), _run(wl, frames, "bf16", True))
