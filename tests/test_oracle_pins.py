@@ -690,3 +690,47 @@ def test_mask_upsample_picks_the_pixel_under_each_centre():
             r, c = int(cy), int(cx)
             assert r <= cy < r + 1 and c <= cx < c + 1
             assert out[i, j] == m[r * w + c]
+
+
+# --------------------------------------------------------------------------
+# small helpers, each against its definition written out entry by entry
+# --------------------------------------------------------------------------
+
+def test_pixel_weights_planar_layout_by_loops():
+    """eq. (pixelweighting): entry c*P + p of the weight vector is 1 when
+    pixel p was background in the previous frame and omega otherwise, for
+    every colour plane c."""
+    rng = _rng(31)
+    P, C, omega = 37, 3, 0.125
+    lab = (rng.random(P) < 0.3).astype(np.uint8)
+    w = O.pixel_weights(lab, omega, C)
+    assert w.shape == (C * P,)
+    for c in range(C):
+        for p in range(P):
+            assert w[c * P + p] == (omega if lab[p] else 1.0)
+
+
+def test_cho_solve_lower_solves_the_normal_equations():
+    rng = _rng(32)
+    B = rng.standard_normal((6, 6))
+    A = B @ B.T + 6 * np.eye(6)
+    b = rng.standard_normal(6)
+    z = O.cho_solve_lower(np.linalg.cholesky(A), b)
+    np.testing.assert_allclose(A @ z, b, rtol=0, atol=1e-12)
+
+
+def test_band_pixels_by_loops():
+    """A pixel is in the band when its largest channel residual lies within
+    the guard of the threshold (brute force over pixels and channels)."""
+    rng = _rng(33)
+    P, C, k = 50, 3, 2
+    U = V.random_orthonormal(C * P, k, rng)
+    y = rng.standard_normal(k)
+    x = U @ y + 0.1 * rng.standard_normal(C * P)
+    thr, guard = 0.1, 0.03
+    got = O.band_pixels(U, x, y, thr, C, guard)
+    r = x - U @ y
+    for p in range(P):
+        rmax = max(abs(r[c * P + p]) for c in range(C))
+        assert bool(got[p]) == (abs(rmax - thr) <= guard)
+    assert 0 < got.sum() < P
