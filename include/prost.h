@@ -147,7 +147,11 @@ PROS_API pros_status pros_validate(const pros_params* prm);
 /* Create a tracker.  Allocates the device state on the current HIP device and
  * queues its initialisation on `hip_stream` (a hipStream_t, NULL = default):
  * U = 0 (must be set with pros_set_state before the first frame), y = 0,
- * labels = mask = 0, frame counter 0.  On error *out is NULL. */
+ * labels = mask = 0, frame counter 0.  On error *out is NULL.
+ * PROS_EUNSUPPORTED, before any allocation, when the frame needs more
+ * workgroups than the device keeps resident (every workgroup holds its tile
+ * of U in registers for the whole frame): on MI355X at k = 15, frames above
+ * 349 440 pixels x 3 channels in FP32 storage, 698 880 in BF16. */
 PROS_API pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out);
 
 /* Release all device memory of the handle (waits for its stream).  NULL is
