@@ -60,7 +60,7 @@ typedef enum pros_status {
   PROS_ESTATE = -4,        /* call not valid in the current handle state */
   PROS_EBADFRAME = -5,     /* frame had a NaN/Inf entry; state left unchanged */
   PROS_ETIMEOUT = -6,      /* a persistent kernel gave up waiting (handle unusable) */
-  PROS_EUNSUPPORTED = -7   /* size/option outside what this build supports */
+  PROS_EUNSUPPORTED = -7   /* size/option outside what the library supports */
 } pros_status;
 
 typedef enum pros_dtype { PROS_F32 = 0, PROS_BF16 = 1 } pros_dtype;
