@@ -171,19 +171,58 @@ def test_batch_bf16_matches_oracle(budget):
             assert y_rel <= 1e-4 and over == 0
 
 
+def _rne(a):
+    f = np.asarray(a, np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    return ((((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def _vga_bf16_frame(sv, n):
+    import torch
+    from paper_1302_2073_amd.tracker import bf16_bits
+    return torch.from_numpy(bf16_bits(sv.frame(n)).view(np.int16)).cuda().view(torch.bfloat16)
+
+
+def _vga_starts(bt, streams):
+    starts = {}
+    for s in streams:
+        U0, y0, l0, n0 = bt.get_state(s)
+        starts[s] = O.State(U0, y0, l0, O.median3x3(l0, 480, 640), n0)
+    return starts
+
+
+def _check_vga_bf16_step(bt, s, start, x, mu):
+    """One bfloat16 640x480x3 k=15 stream after one step against its oracle
+    step from the device's starting state: y within 1e-4, every U entry
+    within one bfloat16 ulp of the round-to-nearest oracle value plus the
+    float32 rounding bound of the update, labels exact outside the guard
+    band."""
+    prm = O.Params(640, 480, 3, k=15, mu=mu)
+    exp, _ = O.track_frame(start, x, prm)
+    U1, y1, l1, n1 = bt.get_state(s)
+    y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
+    e = _rne(exp.U)
+    ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(e), 1e-38))) - 7)
+    ulp = ulp + update_rounding_bound(start, x, prm, exp.y, y1)
+    over = int(np.sum(np.abs(U1 - e) > ulp * 1.0000001 + 1e-45))
+    if over:
+        r = (np.abs(U1 - e) / ulp).ravel()
+        worst = np.argsort(r)[-5:]
+        say("  worst entries (value, oracle, |diff|/bound):",
+            [(float(U1.ravel()[i]), float(e.ravel()[i]), float(r[i])) for i in worst])
+    band = O.band_pixels(exp.U, x, exp.y, prm.thr, 3, GUARD)
+    mism = int(np.sum((l1 != exp.labels) & ~band))
+    say(f"  vga bf16 stream {s}: y {y_rel:.1e}, U entries beyond 1 ulp: {over}, labels outside band {mism}")
+    assert n1 == exp.n and y_rel <= 1e-4 and over == 0 and mism == 0
+
+
 @pytest.mark.parametrize("nstreams,budget", [(2, 0), (3, 192)])
 def test_batch_bf16_vga_streams_share_a_round(nstreams, budget):
     """640x480x3 k=15 streams in bfloat16 (the benchmark's streams): the
     row-pair tiles halve each gang, so two frames run side by side in one
     round, and three with the LDS form; each stream matches its own oracle
     step."""
-    from paper_1302_2073_amd.tracker import BatchTracker, bf16_bits
-    import torch
-
-    def rne(a):
-        f = np.asarray(a, np.float32)
-        u = f.view(np.uint32).astype(np.uint64)
-        return ((((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)).view(np.float32).astype(np.float64)
+    from paper_1302_2073_amd.tracker import BatchTracker
 
     wls = [V.vga_rgb(stream=s) for s in range(nstreams)]
     svs = [V.SyntheticVideo(w.video) for w in wls]
@@ -194,36 +233,69 @@ def test_batch_bf16_vga_streams_share_a_round(nstreams, budget):
         cfg = bt.config()
         say("  config", cfg)
         assert cfg["rounds"] == 1
-        frames = [[torch.from_numpy(bf16_bits(sv.frame(0)).view(np.int16)).cuda().view(torch.bfloat16)]
-                  for sv in svs]
+        frames = [[_vga_bf16_frame(sv, 0)] for sv in svs]
         for s in range(nstreams):
             bt.set_state(s, V.initial_subspace(640 * 480 * 3, 15, 3, s))
         bt.set_frames(frames)
-        starts = []
-        for s, w in enumerate(wls):
-            U0, y0, l0, n0 = bt.get_state(s)
-            starts.append(O.State(U0, y0, l0, O.median3x3(l0, 480, 640), n0))
+        starts = _vga_starts(bt, range(nstreams))
         bt.step()
         assert bt.sync() == 0
         for s, w in enumerate(wls):
-            prm = O.Params(640, 480, 3, k=15, mu=w.mu)
-            x = rne(svs[s].frame(0))
-            exp, _ = O.track_frame(starts[s], x, prm)
-            U1, y1, l1, n1 = bt.get_state(s)
-            y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
-            e = rne(exp.U)
-            ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(e), 1e-38))) - 7)
-            ulp = ulp + update_rounding_bound(starts[s], x, prm, exp.y, y1)
-            over = int(np.sum(np.abs(U1 - e) > ulp * 1.0000001 + 1e-45))
-            if over:
-                r = (np.abs(U1 - e) / ulp).ravel()
-                worst = np.argsort(r)[-5:]
-                say("  worst entries (value, oracle, |diff|/bound):",
-                    [(float(U1.ravel()[i]), float(e.ravel()[i]), float(r[i])) for i in worst])
-            band = O.band_pixels(exp.U, x, exp.y, prm.thr, 3, GUARD)
-            mism = int(np.sum((l1 != exp.labels) & ~band))
-            say(f"  vga bf16 stream {s}: y {y_rel:.1e}, U entries beyond 1 ulp: {over}, labels outside band {mism}")
-            assert n1 == exp.n and y_rel <= 1e-4 and over == 0 and mism == 0
+            _check_vga_bf16_step(bt, s, starts[s], _rne(svs[s].frame(0)), w.mu)
+
+
+def test_benchmark_launch_configuration():
+    """The benchmark's headline launch: 16 bfloat16 640x480x3 k=15 streams,
+    register budget 128, one workgroup per CU, gangs in stream order (two
+    per round, eight rounds), two-hop exchange, replayed from a hipGraph,
+    8 steps per launch over a ring of 8 frames.  One step is checked
+    against the oracle on a sample of streams from six of the eight rounds;
+    then two 8-step launches must equal 16 single steps (no graph) bit for
+    bit, for every stream's state and mask."""
+    import hashlib
+    from paper_1302_2073_amd.tracker import BatchTracker
+    ns, ring = 16, 8
+    wls = [V.vga_rgb(stream=s) for s in range(ns)]
+    svs = [V.SyntheticVideo(w.video) for w in wls]
+    specs = [dict(width=640, height=480, channels=3, k=15, mu=w.mu) for w in wls]
+    frames = [[_vga_bf16_frame(sv, n) for n in range(ring)] for sv in svs]
+    sample = [0, 3, 6, 9, 12, 15]
+
+    def digest(bt):
+        out = []
+        for s in range(ns):
+            U, y, lab, n = bt.get_state(s)
+            out.append((hashlib.sha256(U.tobytes()).hexdigest(), y.tobytes(), lab.tobytes(), n,
+                        bt.mask(s).tobytes()))
+        return out
+
+    res = []
+    for multi in (True, False):
+        with BatchTracker(specs, storage="bf16") as bt:
+            bt.configure(register_budget=128, workgroups_per_cu=1, tile_scale=1.0, strategy=1, sync_mode=2)
+            cfg = bt.config()
+            say("  config", cfg)
+            assert cfg["rounds"] == 8 and cfg["workgroups"] >= 226
+            for s in range(ns):
+                bt.set_state(s, V.initial_subspace(640 * 480 * 3, 15, 3, s))
+            bt.set_frames(frames)
+            bt.use_graph(multi)
+            starts = _vga_starts(bt, sample) if multi else None
+            bt.step()
+            assert bt.sync() == 0
+            if multi:
+                for s in sample:
+                    _check_vga_bf16_step(bt, s, starts[s], _rne(svs[s].frame(0)), wls[s].mu)
+                bt.steps(8)
+                bt.steps(8)
+            else:
+                for _ in range(16):
+                    bt.step()
+            assert bt.sync() == 0
+            res.append(digest(bt))
+    assert [r[3] for r in res[0]] == [17] * ns
+    for s in range(ns):
+        assert res[0][s] == res[1][s], f"stream {s}"
 
 
 def test_mixed_streams_workload_parity_sample():
