@@ -95,8 +95,11 @@ def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
         lab_mismatch=int(np.sum(l1 != exp.labels)),
         mask_vs_median_of_gpu_labels=int(np.sum(mask != O.median3x3(l1, prm.height, prm.width))),
         f_rel=float(max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(stats["f"], info.cg.f))) if stats["f"] else 0.0,
+        f_rel0=float(max(abs(a - b) for a, b in zip(stats["f"], info.cg.f)) / max(abs(info.cg.f[0]), 1e-300))
+        if stats["f"] else 0.0,
         theta_rel=float(abs(stats["theta"] - info.theta) / max(abs(info.theta), 1e-300)),
         steps=(stats["cg_steps"], info.cg.iters),
+        cg_iters=prm.cg_iters,
         U1=U1, exp=exp, info=info, stats=stats, y1=y1, labels=l1, mask=mask, start=start,
     )
     if prm.preprocess:
@@ -108,17 +111,30 @@ def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
     return rep
 
 
-def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U):
+def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U, f_ref0=False):
+    """f_ref0: compare the costs relative to the frame's first cost f_0
+    instead of each f_j.  For frames the subspace fits exactly (k = m) the
+    log cost's f_j tends to 0, and the float32 residuals (absolute error
+    about 2^-24 |x|) then leave a large relative error on f_j alone."""
     say(f"  n={rep['n']} y_rel={rep['y_rel']:.2e} U_rel={rep['U_rel']:.2e} band={rep['band']} "
         f"lab_mism={rep['lab_mismatch']} outside={rep['lab_mismatch_outside_band']} "
         f"f_rel={rep['f_rel']:.1e} theta_rel={rep['theta_rel']:.1e} steps={rep['steps']}")
     assert rep["n"] == rep["n_exp"]
-    assert rep["steps"][0] == rep["steps"][1]
+    dev_steps, ora_steps = rep["steps"]
+    if ora_steps < rep["cg_iters"]:
+        # The oracle stopped early at an exactly zero gradient or curvature
+        # (the exact minimiser, e.g. a one-pixel frame with k = 1).  Whether
+        # g is exactly zero is a floating-point decision: the kernel's
+        # float32 residual leaves g at rounding level, so it may take further
+        # steps, which must leave y within the tolerance.
+        assert ora_steps <= dev_steps <= rep["cg_iters"]
+    else:
+        assert dev_steps == ora_steps
     assert rep["y_rel"] <= tol_y
     assert rep["U_rel"] <= tol_u
     assert rep["lab_mismatch_outside_band"] == 0
     assert rep["mask_vs_median_of_gpu_labels"] == 0
-    assert rep["f_rel"] <= TOL_F
+    assert (rep["f_rel0"] if f_ref0 else rep["f_rel"]) <= TOL_F
     if "pre" in rep:   # float32 running statistics against float64
         say(f"  pre-processing: count {rep['pre']['count']} mean {rep['pre']['mean_err']:.1e} "
             f"m2 {rep['pre']['m2_rel']:.1e}")
