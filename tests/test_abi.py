@@ -182,3 +182,32 @@ def test_new_entry_points_reject_null_handles_without_touching_the_gpu():
     assert L.lib().pros_set_dispatch(None, 0) == L.PROS_EINVAL
     assert L.lib().pros_batch_set_dispatch(None, 0) == L.PROS_EINVAL
     assert L.lib().pros_set_curvature(None, 1) == L.PROS_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libprost.so the binding raises; there is no fallback path."""
+    from paper_1302_2073_amd import _lib as L
+    from paper_1302_2073_amd import Tracker, make_params
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "absent" / "libprost.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(ImportError, match="missing"):
+        L.lib()
+    with pytest.raises(ImportError):
+        make_params(16, 8, 1, 2)      # parameter set-up already goes through the library
+    # no GPU here: the tracker refuses before loading; with a GPU the load raises
+    with pytest.raises((ImportError, RuntimeError)):
+        Tracker(16, 8, 1, 2)
+
+
+def test_package_never_touches_the_oracle():
+    """The product package (binding and kernels' sources) neither imports
+    nor names the CPU oracle."""
+    import glob
+    import re
+    pkg = os.path.join(ROOT, "paper_1302_2073_amd")
+    files = glob.glob(os.path.join(pkg, "**", "*.py"), recursive=True)
+    files += glob.glob(os.path.join(pkg, "csrc", "*"))
+    assert files
+    for f in files:
+        text = open(f, errors="replace").read()
+        assert not re.search(r"\boracle\b|prost_oracle", text), f
