@@ -50,7 +50,11 @@ def _bf16_check(trk, prm, st, x, label=""):
         f"(> 1 ulp: {over}) of {diff.size}; label mismatches outside band {rep['lab_mismatch_outside_band']} "
         f"band {rep['band']}")
     assert rep["n"] == rep["n_exp"]
-    assert rep["steps"][0] == rep["steps"][1]
+    dev_steps, ora_steps = rep["steps"]
+    if ora_steps < rep["cg_iters"]:   # the oracle met an exactly zero gradient (as in assert_parity)
+        assert ora_steps <= dev_steps <= rep["cg_iters"]
+    else:
+        assert dev_steps == ora_steps
     assert rep["y_rel"] <= 1e-4
     assert over == 0
     # round-to-nearest-even storage: entries off by one ulp are rare (a
@@ -89,11 +93,13 @@ def test_bf16_row_pair_tiles(nr):
 
 @pytest.mark.parametrize("cost", ["lp", "log"])
 @pytest.mark.parametrize("shape,nr", [((7, 5, 3, 4), 2), ((33, 17, 1, 1), 0), ((123, 77, 3, 9), 0),
-                                      ((123, 77, 3, 9), 4), ((41, 30, 2, 16), 0), ((45, 31, 3, 5), 32)])
+                                      ((123, 77, 3, 9), 4), ((41, 30, 2, 16), 0), ((45, 31, 3, 5), 32),
+                                      ((1, 1, 1, 1), 0), ((1, 9, 3, 2), 0), ((9, 1, 2, 3), 0), ((2, 2, 1, 4), 0)])
 def test_bf16_random_shapes(shape, nr, cost):
     """Odd pixel counts (row pairs that continue in the next colour plane,
     element-wise pair access), even ones (aligned 32-bit pair access),
-    k = 1 .. 16, 1-3 channels."""
+    k = 1 .. 16, 1-3 channels; the degenerate frames of the float32 test
+    (one pixel, one column, one row, k = m)."""
     W, H, Cc, k = shape
     spec = V.VideoSpec(W, H, Cc, rank=min(k, 3), seed=60 + W, noise=0.01, fg_kind="rects",
                        fg_count=2, fg_density=0.1)
