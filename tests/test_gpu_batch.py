@@ -357,16 +357,17 @@ def test_ordinary_dispatch_is_bitwise_equal(graph):
             np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_multi_step_launch_is_bitwise_equal(storage):
+@pytest.mark.parametrize("storage,budget", [("f32", 128), ("bf16", 128), ("bf16", 64)])
+def test_multi_step_launch_is_bitwise_equal(storage, budget):
     """pros_batch_track_steps(b, 3) twice equals six single steps: each item
-    keeps its tile in registers over three frames of its ring."""
+    keeps its tile in registers over three frames of its ring (register
+    budget 128; at budget 64 the call falls back to one launch per step)."""
     from paper_1302_2073_amd.tracker import BatchTracker
     streams = _streams(SHAPES[:4])
     res = []
     for multi in (False, True):
         with BatchTracker(_specs(streams), storage=storage) as bt:
-            bt.configure(register_budget=128, workgroups_per_cu=1)
+            bt.configure(register_budget=budget, workgroups_per_cu=1)
             bt.set_frames(_frames_tensor(streams, 4, 4, storage))
             _load(bt, streams)
             if multi:
