@@ -95,9 +95,10 @@ def test_sequence_with_ordinary_dispatch_and_fallback_options():
     wl = V.qvga_rgb()
     frames = _frames(wl, 6, "f32")
     _same(_run(wl, frames, "f32", False), _run(wl, frames, "f32", True, coop=0))
-    # filtered-mask weights run one launch per frame
+    # filtered-mask weights and pre-processing run one launch per frame
     _same(_run(wl, frames, "f32", False, weights_from_filtered=True),
           _run(wl, frames, "f32", True, weights_from_filtered=True))
+    _same(_run(wl, frames, "f32", False, preprocess=True), _run(wl, frames, "f32", True, preprocess=True))
 
 
 def test_sequence_longer_than_one_launch():
