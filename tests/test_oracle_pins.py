@@ -734,3 +734,80 @@ def test_band_pixels_by_loops():
         rmax = max(abs(r[c * P + p]) for c in range(C))
         assert bool(got[p]) == (abs(rmax - thr) <= guard)
     assert 0 < got.sum() < P
+
+
+# --------------------------------------------------------------------------
+# diagnostics: orthonormality error and principal angles (Sec. 2.1,
+# eq. stiefeldef); they are the checkers of the trajectory pins above
+# --------------------------------------------------------------------------
+
+def _plane_pair(m, thetas, seed):
+    """Orthonormal A, B (m x len(thetas)) whose principal angles are exactly
+    thetas: A_i = cos(t_i) e_i + sin(t_i) f_i, B_i = e_i, with e, f the
+    columns of one orthonormal basis."""
+    a = len(thetas)
+    E, _ = np.linalg.qr(_rng(seed).standard_normal((m, 2 * a)))
+    B = E[:, :a]
+    A = np.cos(thetas)[None, :] * B + np.sin(thetas)[None, :] * E[:, a:]
+    return A, B
+
+
+def test_principal_angles_known_rotation_including_tiny():
+    """Planes rotated by known angles, down to 1e-7 rad (where an arccos
+    form loses all digits), come back as those angles."""
+    thetas = np.array([1e-7, 3e-4, 0.25, 1.1, np.pi / 2])
+    A, B = _plane_pair(40, thetas, 31)
+    got = np.sort(O.principal_angles(A, B))
+    np.testing.assert_allclose(got, np.sort(thetas), rtol=1e-8, atol=1e-15)
+    assert got[0] > 0.5e-7   # not lost to cancellation
+
+
+def test_principal_angles_against_scipy_subspace_angles():
+    """Random subspaces of unequal dimension: the same angles as
+    scipy.linalg.subspace_angles."""
+    rng = _rng(32)
+    A, _ = np.linalg.qr(rng.standard_normal((30, 3)))
+    B, _ = np.linalg.qr(rng.standard_normal((30, 5)))
+    got = np.sort(O.principal_angles(A, B))
+    ref = np.sort(scipy.linalg.subspace_angles(A, B))
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-13)
+
+
+def test_principal_angles_contained_and_orthogonal():
+    """A vector inside span(B) makes angle 0; one orthogonal to it pi/2;
+    a basis change of the same span does not move the angles."""
+    rng = _rng(33)
+    B, _ = np.linalg.qr(rng.standard_normal((25, 4)))
+    inside = B @ rng.standard_normal(4)
+    inside /= np.linalg.norm(inside)
+    assert O.principal_angles(inside[:, None], B)[0] < 1e-14
+    out = rng.standard_normal(25)
+    out -= B @ (B.T @ out)
+    out /= np.linalg.norm(out)
+    assert abs(O.principal_angles(out[:, None], B)[0] - np.pi / 2) < 1e-7
+    Qr, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    assert O.principal_angles(B @ Qr, B).max() < 1e-7
+
+
+def test_orthonormality_error_by_loops_and_planted_scaling():
+    """||U^T U - I||_F against an explicit double loop over column pairs,
+    and a planted column scaling diag(1 + eps) of an orthonormal U, whose
+    error is sqrt(sum((1 + eps_i)^2 - 1)^2) in closed form."""
+    rng = _rng(34)
+    U = rng.standard_normal((20, 4)) * 0.5
+    tot = 0.0
+    for i in range(4):
+        for j in range(4):
+            dot = sum(U[e, i] * U[e, j] for e in range(20))
+            tot += (dot - (1.0 if i == j else 0.0)) ** 2
+    assert abs(O.orthonormality_error(U) - math.sqrt(tot)) < 1e-13 * max(1.0, math.sqrt(tot))
+    Q, _ = np.linalg.qr(rng.standard_normal((50, 5)))
+    eps = np.array([1e-3, -2e-4, 0.0, 5e-6, 0.3])
+    want = math.sqrt(float(np.sum(((1 + eps) ** 2 - 1) ** 2)))
+    assert abs(O.orthonormality_error(Q * (1 + eps)[None, :]) - want) < 1e-12
+    assert O.orthonormality_error(Q) < 1e-14
+    # a planted off-diagonal: rotate column 1 towards column 0 without renormalising
+    V_ = Q.copy()
+    V_[:, 1] = Q[:, 1] + 1e-4 * Q[:, 0]
+    want = math.sqrt(2 * 1e-4 ** 2 + (1e-4 ** 2) ** 2)
+    assert abs(O.orthonormality_error(V_) - want) < 1e-12
