@@ -20,6 +20,7 @@ PROS_ESTATE = -4
 PROS_EBADFRAME = -5
 PROS_ETIMEOUT = -6
 PROS_EUNSUPPORTED = -7
+PROS_LPCOST_SCRATCH_BYTES = 8 << 20   # fixed scratch of pros_lpcost_bwd_noalloc (include/prost.h)
 
 PROS_F32 = 0
 PROS_BF16 = 1
@@ -131,6 +132,8 @@ _SIGS = {
                         + [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "pros_lpcost_bwd": (C.c_int, [C.c_void_p] * 5 + [C.c_int32] * 4 + [C.c_float]
                         + [C.c_void_p] * 5 + [C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pros_lpcost_bwd_noalloc": (C.c_int, [C.c_void_p] * 5 + [C.c_int32] * 4 + [C.c_float]
+                                + [C.c_void_p] * 5 + [C.c_void_p]),
     "pros_strerror": (C.c_char_p, [C.c_int]),
     "pros_last_error": (C.c_char_p, []),
 }
@@ -142,6 +145,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1302_2073_amd.build`")
+        # torch first: its libraries bring their own HIP runtime under the
+        # same soname as the system one, and the library must bind to the
+        # runtime that owns torch's device memory and streams (loaded the
+        # other way round, the first launch finds no device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
