@@ -363,6 +363,29 @@ PROS_API pros_status pros_lpcost_bwd(const float* U, const float* Y, const float
                             float* dX, float* dU, float* dY, float* dmu,
                             void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Bytes of the fixed device scratch behind pros_lpcost_bwd_noalloc (8 MiB). */
+#define PROS_LPCOST_SCRATCH_BYTES (8u << 20)
+
+/* pros_lpcost_bwd without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as
+ * pros_lpcost_bwd, bit for bit; the partial sums go to a fixed scratch array
+ * inside the library instead: one per GPU, PROS_LPCOST_SCRATCH_BYTES bytes,
+ * held until the process ends.  No call allocates: the array's device
+ * address is looked up once per device (the first call made with that
+ * device current) and kept.  Every call on one GPU uses the same array, and
+ * its contents after a call are that call's partials (nothing in it has to
+ * start at zero); calls that overlap on one GPU (two host threads, or two
+ * streams without ordering between them) race and give wrong results.
+ * Errors: PROS_EINVAL when pros_lpcost_workspace_size(m, k, B) exceeds
+ * PROS_LPCOST_SCRATCH_BYTES (m = 230400, k = 10, B = 32 needs 2.5 MB) or for
+ * the argument errors of pros_lpcost_bwd; PROS_EHIP when the array's address
+ * cannot be looked up. */
+PROS_API pros_status pros_lpcost_bwd_noalloc(const float* U, const float* Y, const float* X, const float* w,
+                                             const float* mu, int32_t m, int32_t k, int32_t B, int32_t cost, float p,
+                                             const float* gout, float* dX, float* dU, float* dY, float* dmu,
+                                             void* hip_stream);
+
 /* Launch tuning of a single-stream handle.  pros_init chooses automatically:
  * one workgroup if the frame fits one, else the smallest tile reaching a
  * gang of <= 32 workgroups, else the smallest tile whose gang fits one

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 
 #include "../../include/prost.h"
 #include "prost_device.hpp"
@@ -240,6 +241,33 @@ __global__ __launch_bounds__(256) void lpcost_finish(const double* __restrict__ 
 
 static int lp_blocks(int m) { return (m + kLpBlock - 1) / kLpBlock; }
 
+// Partial sums of pros_lpcost_bwd_noalloc: a file-scope device array, one
+// copy per GPU.  Calls on one GPU share it (they must not overlap).
+static __device__ __align__(256) unsigned char scratch[PROS_LPCOST_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];   // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current.
+static pros_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return prost_host::set_error(PROS_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return prost_host::set_error(PROS_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return prost_host::set_error(PROS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PROS_OK;
+}
+
 }  // namespace prost
 
 using namespace prost;
@@ -293,16 +321,10 @@ pros_status pros_lpcost_fwd(const float* U, const float* Y, const float* X, cons
   return PROS_OK;
 }
 
-pros_status pros_lpcost_bwd(const float* U, const float* Y, const float* X, const float* w, const float* mu,
-                            int32_t m, int32_t k, int32_t B, int32_t cost, float p, const float* gout, float* dX,
-                            float* dU, float* dY, float* dmu, void* workspace, size_t workspace_bytes,
-                            void* hip_stream) {
-  pros_status st = lp_check(U, Y, X, mu, m, k, B, cost, p, workspace, workspace_bytes);
-  if (st != PROS_OK) return st;
-  if (!gout) return prost_host::set_error(PROS_EINVAL, "gout is NULL");
-  hipStream_t s = (hipStream_t)hip_stream;
+static pros_status lp_bwd_launch(const float* U, const float* Y, const float* X, const float* w, const float* mu,
+                                 int32_t m, int32_t k, int32_t B, int32_t cost, float p, const float* gout,
+                                 float* dX, float* dU, float* dY, float* dmu, double* part, hipStream_t s) {
   const int nblk = lp_blocks(m);
-  double* part = (double*)workspace;
   const int form = (cost == PROS_COST_LOG) ? 1 : 0;
   PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_bwd_kernel<KK>), dim3(nblk), dim3(kLpBlock), 0, s, U, Y, X, w, m, B,
                                        form, p, mu, gout, dX, dU, part));
@@ -313,6 +335,42 @@ pros_status pros_lpcost_bwd(const float* U, const float* Y, const float* X, cons
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return prost_host::set_error(PROS_EHIP, "lpcost backward launch: %s", hipGetErrorString(e));
   return PROS_OK;
+}
+
+pros_status pros_lpcost_bwd(const float* U, const float* Y, const float* X, const float* w, const float* mu,
+                            int32_t m, int32_t k, int32_t B, int32_t cost, float p, const float* gout, float* dX,
+                            float* dU, float* dY, float* dmu, void* workspace, size_t workspace_bytes,
+                            void* hip_stream) {
+  pros_status st = lp_check(U, Y, X, mu, m, k, B, cost, p, workspace, workspace_bytes);
+  if (st != PROS_OK) return st;
+  if (!gout) return prost_host::set_error(PROS_EINVAL, "gout is NULL");
+  return lp_bwd_launch(U, Y, X, w, mu, m, k, B, cost, p, gout, dX, dU, dY, dmu, (double*)workspace,
+                       (hipStream_t)hip_stream);
+}
+
+// The backward without a workspace argument: its partial sums live in
+// `scratch`, a fixed device array of the library (one per GPU, held until
+// the process ends).  Host code never passes the array's name to a kernel
+// (in host code it is a stand-in, not a device address): the device address
+// is taken once per device with hipGetSymbolAddress and kept here.
+pros_status pros_lpcost_bwd_noalloc(const float* U, const float* Y, const float* X, const float* w, const float* mu,
+                                    int32_t m, int32_t k, int32_t B, int32_t cost, float p, const float* gout,
+                                    float* dX, float* dU, float* dY, float* dmu, void* hip_stream) {
+  const size_t need = pros_lpcost_workspace_size(m, k, B);
+  if (need == 0) return prost_host::set_error(PROS_EINVAL, "bad sizes m=%d k=%d B=%d", m, k, B);
+  if (need > (size_t)PROS_LPCOST_SCRATCH_BYTES)
+    return prost_host::set_error(PROS_EINVAL,
+                                 "m=%d k=%d B=%d needs %zu bytes of partial sums; the fixed scratch holds %zu "
+                                 "(use pros_lpcost_bwd with a workspace)",
+                                 m, k, B, need, (size_t)PROS_LPCOST_SCRATCH_BYTES);
+  void* part = nullptr;
+  pros_status st = scratch_address(&part);
+  if (st != PROS_OK) return st;
+  st = lp_check(U, Y, X, mu, m, k, B, cost, p, part, (size_t)PROS_LPCOST_SCRATCH_BYTES);
+  if (st != PROS_OK) return st;
+  if (!gout) return prost_host::set_error(PROS_EINVAL, "gout is NULL");
+  return lp_bwd_launch(U, Y, X, w, mu, m, k, B, cost, p, gout, dX, dU, dY, dmu, (double*)part,
+                       (hipStream_t)hip_stream);
 }
 
 }  // extern "C"
