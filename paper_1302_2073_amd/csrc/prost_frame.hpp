@@ -117,6 +117,45 @@ __device__ __forceinline__ void trace_point(const FrameArgs& a, int tile, int id
   if (a.trace && thread_index() == 0 && idx < 64) a.trace[(size_t)tile * 64 + idx] = wall_clock64();
 }
 
+// Waits for component `comp` of the tagged slots q = row0, row0 + rs, ...
+// (q < n, slot q at base + q * qstride) to carry epoch ep and returns their
+// sum in slot order.  Each thread spins on its own values with no barrier
+// inside the wait (a barrier per poll round made every round cost a memory
+// round trip plus two workgroup barriers); `bad` is set on time-out or when
+// another workgroup has raised the time-out bit.
+__device__ __forceinline__ double spin_sum(const double* base, int n, int rs, size_t qstride, int comp, int row0,
+                                           unsigned ep, const FrameArgs& a, int& bad) {
+  double v = 0.0;
+  const long long t0 = now_ticks();
+  for (int q = row0; q < n; q += rs) {
+    const double* p = base + (size_t)q * qstride + comp;
+    double x = ld_tagged(p);
+    unsigned spins = 0;
+    while (tag_of(x) != ep) {
+      x = ld_tagged(p);
+      if ((++spins & 63u) == 0 &&
+          (now_ticks() - t0 > a.timeout ||
+           (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout))) {
+        bad = 1;
+        return v;
+      }
+    }
+    v += untag(x);
+  }
+  return v;
+}
+
+// Uniform end of a spin wait: false in every thread (and the gang's
+// time-out bit raised) if any thread gave up.  The barrier also publishes
+// the threads' s_big entries.
+__device__ __forceinline__ bool spin_end(int bad, const FrameArgs& a) {
+  if (__syncthreads_or(bad)) {
+    if (thread_index() == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+  return true;
+}
+
 // Workgroup + gang reduction of L float partials held by every thread.
 // Result (float64, identical in every workgroup) lands in s_out[0..L).
 // Tagged gather/broadcast: every workgroup publishes its tagged partial
@@ -139,30 +178,12 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
   if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (tid < L) st_tagged(&slots[(size_t)tile * kSlot + tid], tag_value(wg_sum[tid], ep));
   if (tile == 0) {
-    const long long t0 = now_ticks();
     constexpr int kRows = kBlock / 32;
     const int comp = tid & 31, row0 = tid >> 5;
-    double v = 0.0;
-    while (true) {
-      int ok = 1;
-      v = 0.0;
-      if (comp < L)
-        for (int w = row0; w < a.G; w += kRows) {
-          const double x = ld_tagged(&slots[(size_t)w * kSlot + comp]);
-          ok &= (tag_of(x) == ep) ? 1 : 0;
-          v += untag(x);
-        }
-      if (__syncthreads_and(ok)) break;
-      const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
-                                      (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
-      if (__syncthreads_or(late)) {
-        if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
+    int bad = 0;
+    const double v = (comp < L) ? spin_sum(slots, a.G, kRows, kSlot, comp, row0, ep, a, bad) : 0.0;
     s_big[tid] = v;
-    __syncthreads();
+    if (!spin_end(bad, a)) return false;
     if (tid < L) {
       double tot = 0.0;
 #pragma unroll
@@ -207,37 +228,20 @@ __device__ __forceinline__ bool gang_reduce_tagged(const double* wg_sum, const F
   return s_ctl[1] == 0;
 }
 
-// Tagged all-read helpers: poll n tagged slots (stride kSlot) until every
-// component carries the epoch, summing component c in slot order.  Thread
-// layout: component tid % 32, slots tid / 32, tid / 32 + kRows, ...; the kRows
-// partial sums are then added in order.  Uniform exit; false on timeout.
+// Tagged all-read helper: waits for n tagged slots (stride kSlot) to carry
+// the epoch, summing component c in slot order.  Thread layout: component
+// tid % 32, slots tid / 32, tid / 32 + kRows, ...; the kRows partial sums are
+// then added in order.  Uniform exit; false on time-out.
 template <int L>
 __device__ __forceinline__ bool poll_sum_slots(const double* slots, int nslots, unsigned ep, const FrameArgs& a,
                                                double* s_big, double* out) {
   const int tid = thread_index();
   constexpr int kRows = kBlock / 32;
   const int comp = tid & 31, row0 = tid >> 5;
-  const long long t0 = now_ticks();
-  double v = 0.0;
-  while (true) {
-    int ok = 1;
-    v = 0.0;
-    if (comp < L)
-      for (int q = row0; q < nslots; q += kRows) {
-        const double val = ld_tagged(&slots[(size_t)q * kSlot + comp]);
-        ok &= (tag_of(val) == ep) ? 1 : 0;
-        v += untag(val);
-      }
-    if (__syncthreads_and(ok)) break;
-    const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
-                                    (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
-    if (__syncthreads_or(late)) {
-      if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-  }
+  int bad = 0;
+  const double v = (comp < L) ? spin_sum(slots, nslots, kRows, kSlot, comp, row0, ep, a, bad) : 0.0;
   s_big[tid] = v;
-  __syncthreads();
+  if (!spin_end(bad, a)) return false;
   if (tid < L) {
     double tot = 0.0;
 #pragma unroll
@@ -270,27 +274,11 @@ __device__ __forceinline__ bool gang_reduce_2level(const double* wg_sum, const F
     const int n = (a.G - x + 7) >> 3;
     const int comp = tid & 31, row0 = tid >> 5;
     constexpr int kRows = kBlock / 32;
-    const long long t0 = now_ticks();
-    double v = 0.0;
-    while (true) {
-      int ok = 1;
-      v = 0.0;
-      if (comp < L)
-        for (int q = row0; q < n; q += kRows) {
-          const double val = ld_tagged(&slots[(size_t)(q * 8 + x) * kSlot + comp]);
-          ok &= (tag_of(val) == ep) ? 1 : 0;
-          v += untag(val);
-        }
-      if (__syncthreads_and(ok)) break;
-      const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
-                                      (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
-      if (__syncthreads_or(late)) {
-        if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
+    int bad = 0;
+    const double v = (comp < L) ? spin_sum(slots + (size_t)x * kSlot, n, kRows, (size_t)8 * kSlot, comp, row0, ep, a, bad)
+                                : 0.0;
     s_big[tid] = v;
-    __syncthreads();
+    if (!spin_end(bad, a)) return false;
     if (tid < L) {
       double g = 0.0;
       for (int r = 0; r < kRows; ++r) g += s_big[r * 32 + tid];
@@ -330,27 +318,10 @@ __device__ __forceinline__ bool poll_sum_wide(const double* base, int n, int qst
   constexpr int kRowsW = kBlock / kWideMax;
   const int v = tid % kWideMax, row = tid / kWideMax;
   const bool act = row < kRowsW && v < LT;
-  const long long t0 = now_ticks();
-  double acc = 0.0;
-  while (true) {
-    int ok = 1;
-    acc = 0.0;
-    if (act)
-      for (int q = row; q < n; q += kRowsW) {
-        const double val = ld_tagged(&base[(size_t)q * qstride + v]);
-        ok &= (tag_of(val) == ep) ? 1 : 0;
-        acc += untag(val);
-      }
-    if (__syncthreads_and(ok)) break;
-    const int late = (tid == 0) && (now_ticks() - t0 > a.timeout ||
-                                    (__hip_atomic_load(&a.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout));
-    if (__syncthreads_or(late)) {
-      if (tid == 0) __hip_atomic_fetch_or(&a.sync[2], kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-  }
+  int bad = 0;
+  const double acc = act ? spin_sum(base, n, kRowsW, (size_t)qstride, v, row, ep, a, bad) : 0.0;
   s_big[tid] = acc;
-  __syncthreads();
+  if (!spin_end(bad, a)) return false;
   if (tid < LT) {
     double t = 0.0;
 #pragma unroll
