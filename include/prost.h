@@ -112,6 +112,10 @@ typedef struct pros_params {
                                       refuses it).
                                       A singular H ends the solve with the
                                       current y. */
+  uint64_t seed;                   /* U0 = orthonormal factor of the reduced QR
+                                      of a random m x k matrix drawn from this
+                                      seed (Sec. 3.4, Initialization; see
+                                      pros_random_subspace); default 0 */
 } pros_params;
 
 typedef struct pros_stats {
@@ -134,6 +138,26 @@ typedef struct pros_stats {
 
 typedef struct pros_handle pros_handle;
 
+/* Initialization of U (Sec. 3.4): U = the orthonormal factor Q (diag(R) > 0)
+ * of the reduced QR decomposition of an m x k matrix A of independent
+ * standard normal entries.  A is drawn from a counter-based generator, so it
+ * is the same for every launch and device: entry e = j m + i of A (column j,
+ * row i) belongs to pair q = e / 2, one Philox4x32-10 call (Salmon, Moraes,
+ * Dror, Shaw, SC'11) with counter (q mod 2^32, q div 2^32, stream_index, 0)
+ * and key (seed mod 2^32, seed div 2^32); its words (w0, w1, w2, w3) give the
+ * uniforms u_a = ((w0 2^32 + w1) div 2^11 + 1/2) 2^-53 and u_b likewise from
+ * (w2, w3), and Box-Muller gives sqrt(-2 ln u_a) cos(2 pi u_b) for even e and
+ * sqrt(-2 ln u_a) sin(2 pi u_b) for odd e.  Q is formed in float64 on the GPU
+ * by CholeskyQR2.  U: caller-owned device memory, m x k float64,
+ * column-major with leading dimension m.  Work runs on `hip_stream`;
+ * synchronises (temporary device scratch is allocated and freed).  Errors:
+ * PROS_EINVAL for NULL U or sizes outside 1 <= k <= min(m, PROS_MAX_K), or a
+ * rank-deficient draw; PROS_ENOMEM; PROS_EHIP.  pros_init and
+ * pros_batch_init (stream index = the stream's position in the batch) set
+ * each tracker's U from it. */
+PROS_API pros_status pros_random_subspace(uint64_t seed, uint32_t stream_index, int64_t m, int32_t k, double* U,
+                                          void* hip_stream);
+
 /* Fill *out with the Sec. 5.1 benchmark parameters for a width x height x
  * channels video (k=15, 5 CG steps, p=0.25, omega=5e-5, t_init=5e-3,
  * t_min=1e-4, i_init=100, mu=1e-3, FP32 storage).  Returns PROS_EINVAL on a
@@ -145,9 +169,11 @@ PROS_API pros_status pros_params_default(pros_params* out, int32_t width, int32_
 PROS_API pros_status pros_validate(const pros_params* prm);
 
 /* Create a tracker.  Allocates the device state on the current HIP device and
- * queues its initialisation on `hip_stream` (a hipStream_t, NULL = default):
- * U = 0 (must be set with pros_set_state before the first frame), y = 0,
- * labels = mask = 0, frame counter 0.  On error *out is NULL.
+ * initialises it on `hip_stream` (a hipStream_t, NULL = default), then
+ * synchronises: U = U0 of Sec. 3.4 drawn from prm->seed (stream index 0 of
+ * pros_random_subspace, rounded to the storage type), y = 0, labels = mask
+ * = 0, frame counter 0, so frames can be tracked right away;
+ * pros_set_state replaces any of it.  On error *out is NULL.
  * PROS_EUNSUPPORTED, before any allocation, when the frame needs more
  * workgroups than the device keeps resident (every workgroup holds its tile
  * of U in registers for the whole frame): on MI355X at k = 15, frames above
@@ -292,7 +318,10 @@ typedef struct pros_batch_config {
 } pros_batch_config;
 
 /* Create a batch of n streams (per_stream[0..n-1]; reorth_every must be 0,
- * use pros_batch_reorthonormalize).  Work is queued on hip_stream. */
+ * use pros_batch_reorthonormalize).  Stream s starts from U0 of Sec. 3.4
+ * drawn from per_stream[s].seed with stream index s (pros_random_subspace),
+ * so equal seeds still give distinct subspaces.  Work runs on hip_stream;
+ * synchronises. */
 PROS_API pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_stream, pros_batch** out);
 PROS_API void pros_batch_destroy(pros_batch* b);
 /* Same contract as pros_set_state / pros_get_state for stream s. */

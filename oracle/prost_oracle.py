@@ -598,3 +598,71 @@ def principal_angles(A, B):
     R = A - B @ (B.T @ A)
     sv = np.linalg.svd(R, compute_uv=False)
     return np.arcsin(np.clip(sv, 0.0, 1.0))
+
+
+# ---------------------------------------------------------------------------
+# Initialization of U, Sec. 3.4 ("Initialization"): the orthonormal factor of
+# the reduced QR decomposition of a random m x k matrix.  The random matrix is
+# drawn from a counter-based generator so that the HIP library, which draws
+# it on the device, can be compared entry by entry: each side implements the
+# generator from its published definition and nothing else is shared.
+# ---------------------------------------------------------------------------
+
+_PHILOX_M0, _PHILOX_M1 = 0xD2511F53, 0xCD9E8D57   # round multipliers
+_PHILOX_W0, _PHILOX_W1 = 0x9E3779B9, 0xBB67AE85   # key schedule (Weyl) increments
+_MASK32 = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random
+    numbers: as easy as 1, 2, 3", SC'11).  ctr: (..., 4) uint32 counters,
+    key: (2,) uint32.  Each round multiplies words 0 and 2 by the two
+    constants (64-bit products), and the new words are
+    (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0));
+    the key is bumped by the Weyl increments between rounds."""
+    c = np.array(ctr, dtype=np.uint64) & _MASK32
+    k0, k1 = int(key[0]) & _MASK32, int(key[1]) & _MASK32
+    c0, c1, c2, c3 = c[..., 0], c[..., 1], c[..., 2], c[..., 3]
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + _PHILOX_W0) & _MASK32
+            k1 = (k1 + _PHILOX_W1) & _MASK32
+        p0 = c0 * np.uint64(_PHILOX_M0)          # exact: both factors < 2^32
+        p1 = c2 * np.uint64(_PHILOX_M1)
+        hi0, lo0 = p0 >> np.uint64(32), p0 & np.uint64(_MASK32)
+        hi1, lo1 = p1 >> np.uint64(32), p1 & np.uint64(_MASK32)
+        c0, c1, c2, c3 = (hi1 ^ c1 ^ np.uint64(k0), lo1, hi0 ^ c3 ^ np.uint64(k1), lo0)
+    return np.stack([c0, c1, c2, c3], axis=-1).astype(np.uint32)
+
+
+def gaussian_matrix(m, k, seed, stream=0):
+    """The m x k standard normal matrix behind U0.  Entry (i, j) has linear
+    index e = j m + i (column-major).  Pair q = e // 2 is one Philox4x32-10
+    call with counter (q mod 2^32, q div 2^32, stream, 0) and key
+    (seed mod 2^32, seed div 2^32); its words give two uniforms in (0, 1),
+    u = ((w0 2^32 + w1) div 2^11 + 1/2) 2^-53 and likewise from (w2, w3), and
+    Box-Muller turns them into sqrt(-2 ln u_a) cos(2 pi u_b) (even e) and
+    sqrt(-2 ln u_a) sin(2 pi u_b) (odd e)."""
+    n = m * k
+    q = np.arange((n + 1) // 2, dtype=np.uint64)
+    ctr = np.stack([q & np.uint64(_MASK32), q >> np.uint64(32),
+                    np.full_like(q, stream & _MASK32), np.zeros_like(q)], axis=-1)
+    w = philox4x32_10(ctr, (seed & _MASK32, (seed >> 32) & _MASK32)).astype(np.uint64)
+    za = ((w[:, 0] << np.uint64(32)) | w[:, 1]) >> np.uint64(11)
+    zb = ((w[:, 2] << np.uint64(32)) | w[:, 3]) >> np.uint64(11)
+    ua = (za.astype(np.float64) + 0.5) * 2.0 ** -53
+    ub = (zb.astype(np.float64) + 0.5) * 2.0 ** -53
+    rad = np.sqrt(-2.0 * np.log(ua))
+    g = np.empty(2 * len(q))
+    g[0::2] = rad * np.cos(2.0 * np.pi * ub)
+    g[1::2] = rad * np.sin(2.0 * np.pi * ub)
+    return g[:n].reshape(k, m).T.copy()
+
+
+def initial_subspace(m, k, seed, stream=0):
+    """U0 of Sec. 3.4: the Q factor of the reduced QR decomposition of the
+    random matrix, signs fixed so that diag(R) > 0 (the factorisation is then
+    unique)."""
+    A = gaussian_matrix(m, k, seed, stream)
+    Q, R = np.linalg.qr(A, mode="reduced")
+    return Q * np.sign(np.diag(R))

@@ -40,6 +40,7 @@ class pros_params(C.Structure):
         ("labels_after_update", C.c_int32), ("weights_from_filtered", C.c_int32),
         ("preprocess", C.c_int32),
         ("ysolve", C.c_int32),
+        ("seed", C.c_uint64),
     ]
 
 
@@ -134,6 +135,7 @@ _SIGS = {
                         + [C.c_void_p] * 5 + [C.c_void_p, C.c_size_t, C.c_void_p]),
     "pros_lpcost_bwd_noalloc": (C.c_int, [C.c_void_p] * 5 + [C.c_int32] * 4 + [C.c_float]
                                 + [C.c_void_p] * 5 + [C.c_void_p]),
+    "pros_random_subspace": (C.c_int, [C.c_uint64, C.c_uint32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
     "pros_strerror": (C.c_char_p, [C.c_int]),
     "pros_last_error": (C.c_char_p, []),
 }

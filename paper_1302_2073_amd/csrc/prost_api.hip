@@ -348,7 +348,23 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
 
 pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out) {
   if (!out) return fail(PROS_EINVAL, "out is NULL");
-  return prost_host::create_handle(prm, (hipStream_t)hip_stream, 0, 0, 0, out);
+  pros_status st = prost_host::create_handle(prm, (hipStream_t)hip_stream, 0, 0, 0, out);
+  if (st != PROS_OK) return st;
+  st = prost_init_subspace(*out, prm->seed, 0);   // U0 of Sec. 3.4
+  if (st != PROS_OK) {
+    free_handle(*out);
+    *out = nullptr;
+    return st;
+  }
+  (*out)->state_set = true;
+  return PROS_OK;
+}
+
+pros_status pros_random_subspace(uint64_t seed, uint32_t stream_index, int64_t m, int32_t k, double* U,
+                                 void* hip_stream) {
+  if (!U) return fail(PROS_EINVAL, "U is NULL");
+  if (m < 1 || k < 1 || k > PROS_MAX_K || m < k) return fail(PROS_EINVAL, "bad sizes m=%lld k=%d", (long long)m, k);
+  return prost_random_subspace(seed, stream_index, m, k, U, (hipStream_t)hip_stream);
 }
 
 void pros_destroy(pros_handle* h) {

@@ -304,6 +304,12 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
       return st;
     }
     b->hs.push_back(h);
+    st = prost_init_subspace(h, per_stream[s].seed, (uint32_t)s);   // U0 of Sec. 3.4, stream s
+    if (st != PROS_OK) {
+      free_batch(b);
+      return st;
+    }
+    h->state_set = true;
   }
   e = hipMalloc((void**)&b->d_descs, sizeof(FrameArgs) * n);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_xtab, sizeof(void*) * n);

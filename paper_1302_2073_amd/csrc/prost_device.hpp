@@ -36,6 +36,7 @@ __device__ __forceinline__ int thread_index() {
 // storage
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float ld_elem(const float* p, long long i) { return p[i]; }
+__device__ __forceinline__ double ld_elem(const double* p, long long i) { return p[i]; }
 __device__ __forceinline__ float ld_elem(const uint16_t* p, long long i) {
   return __uint_as_float(((uint32_t)p[i]) << 16);
 }

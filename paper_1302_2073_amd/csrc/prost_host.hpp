@@ -78,3 +78,8 @@ pros_status set_error(pros_status s, const char* fmt, ...);
 }  // namespace prost_host
 
 pros_status prost_reorth_launch(pros_handle* h);
+// Seeded orthonormal m x k float64 matrix (Sec. 3.4 initialization) into a
+// device buffer; and a handle's U set from it (rounded to the storage type).
+pros_status prost_random_subspace(unsigned long long seed, uint32_t stream_index, long long m, int k, double* A,
+                                  hipStream_t st);
+pros_status prost_init_subspace(pros_handle* h, unsigned long long seed, uint32_t stream_index);

@@ -17,8 +17,9 @@ from . import _lib as L
 def make_params(width, height, channels=1, k=15, cg_iters=5, cost="lp", p=0.25, mu=1e-3,
                 delta=None, omega=5e-5, t_init=5e-3, t_min=1e-4, i_init=100, storage="f32",
                 reorth_every=0, labels_after_update=True, weights_from_filtered=False, preprocess=False,
-                ysolve="cg"):
-    """pros_params from keyword arguments (Sec. 5.1 defaults)."""
+                ysolve="cg", seed=0):
+    """pros_params from keyword arguments (Sec. 5.1 defaults).  seed: the
+    draw behind the initial subspace U0 (Sec. 3.4)."""
     prm = L.pros_params()
     L.check(L.lib().pros_params_default(C.byref(prm), width, height, channels))
     prm.k = k
@@ -37,6 +38,7 @@ def make_params(width, height, channels=1, k=15, cg_iters=5, cost="lp", p=0.25, 
     prm.weights_from_filtered = int(bool(weights_from_filtered))
     prm.preprocess = int(bool(preprocess))
     prm.ysolve = {"cg": 0, "gd": 1, "irls": 2}[ysolve]
+    prm.seed = int(seed)
     return prm
 
 

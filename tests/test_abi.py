@@ -50,8 +50,8 @@ def test_binding_covers_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     L = _lib()
-    # pros_params: 6 int32 + 6 double + 7 int32, padded to 8 bytes
-    assert C.sizeof(L.pros_params) == 6 * 4 + 6 * 8 + 8 * 4
+    # pros_params: 6 int32 + 6 double + 7 int32 (padded to 8 bytes) + uint64 seed
+    assert C.sizeof(L.pros_params) == 6 * 4 + 6 * 8 + 8 * 4 + 8
     assert C.sizeof(L.pros_stats) == 8 + 4 * 4 + 8 * (17 + 16 + 16 + 5) + 8
 
 

@@ -119,5 +119,5 @@ def test_pipeline_refusals():
         with Ingest(t, 32, 24) as ing:
             with pytest.raises(ProstError):     # no slot filled yet
                 ing.submit()
-            with pytest.raises(ProstError):     # no subspace set yet
-                ing.push(np.zeros((24, 32, 3), np.uint8))
+            ing.push(np.zeros((24, 32, 3), np.uint8))   # tracks from the seeded U0 of pros_init (Sec. 3.4)
+            assert t.get_state()[3] == 1

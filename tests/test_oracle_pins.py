@@ -811,3 +811,62 @@ def test_orthonormality_error_by_loops_and_planted_scaling():
     V_[:, 1] = Q[:, 1] + 1e-4 * Q[:, 0]
     want = math.sqrt(2 * 1e-4 ** 2 + (1e-4 ** 2) ** 2)
     assert abs(O.orthonormality_error(V_) - want) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Initialization of U (Sec. 3.4): Q of the reduced QR of a random matrix,
+# drawn from Philox4x32-10 + Box-Muller
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    import json
+    kat = json.load(open(os.path.join(GOLD, "philox4x32_10_kat.json")))
+    for v in kat["vectors"]:
+        ctr = np.array([int(w, 16) for w in v["ctr"]], dtype=np.uint64)
+        key = [int(w, 16) for w in v["key"]]
+        out = O.philox4x32_10(ctr, key)
+        assert [int(w) for w in out] == [int(w, 16) for w in v["out"]]
+
+
+def test_philox_is_counter_based():
+    """Vectorised calls equal one call per counter; a changed key or counter
+    word changes every output word."""
+    ctr = np.array([[q, 7, 3, 0] for q in range(50)], dtype=np.uint64)
+    many = O.philox4x32_10(ctr, (11, 12))
+    for q in range(50):
+        assert np.array_equal(many[q], O.philox4x32_10(ctr[q], (11, 12)))
+    a = O.philox4x32_10(np.array([1, 2, 3, 4]), (5, 6))
+    for alt in (O.philox4x32_10(np.array([1, 2, 3, 5]), (5, 6)), O.philox4x32_10(np.array([1, 2, 3, 4]), (5, 7))):
+        assert np.all(a != alt)
+
+
+def test_gaussian_matrix_is_standard_normal():
+    """Moments and a Kolmogorov-Smirnov test against N(0, 1) on 200 000
+    draws; the cosine and sine variates of a pair are uncorrelated; the
+    column-major layout is the linear draw order."""
+    from scipy import stats
+    A = O.gaussian_matrix(40000, 5, seed=2024)
+    g = A.T.ravel()                     # draw order e = j m + i
+    assert abs(g.mean()) < 0.01 and abs(g.var() - 1.0) < 0.01
+    assert abs(np.mean(g ** 4) - 3.0) < 0.05
+    assert stats.kstest(g, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(g[0::2], g[1::2])[0, 1]) < 0.01
+    B = O.gaussian_matrix(40000, 5, seed=2024, stream=1)
+    assert abs(np.corrcoef(A.ravel(), B.ravel())[0, 1]) < 0.01
+    # a smaller matrix is a prefix of the same draw order
+    assert np.array_equal(O.gaussian_matrix(10, 3, seed=9).T.ravel(), O.gaussian_matrix(15, 2, seed=9).T.ravel()[:30])
+
+
+def test_initial_subspace_is_the_reduced_qr_factor():
+    """U0 has orthonormal columns, spans the random matrix's column space,
+    and R = U0^T A is upper triangular with a positive diagonal (the unique
+    reduced QR); odd m k (the last draw pair half used) included."""
+    for (m, k, seed) in ((4801, 5, 1), (300, 16, 2), (7, 7, 3), (1000, 1, 4)):
+        A = O.gaussian_matrix(m, k, seed)
+        U = O.initial_subspace(m, k, seed)
+        assert O.orthonormality_error(U) < 1e-13
+        R = U.T @ A
+        assert np.all(np.diag(R) > 0)
+        assert np.max(np.abs(np.tril(R, -1))) < 1e-12 * np.max(np.abs(R))
+        assert np.max(np.abs(U @ R - A)) < 1e-12 * np.max(np.abs(A))
+    assert not np.allclose(O.initial_subspace(100, 3, 1), O.initial_subspace(100, 3, 1, stream=1))
