@@ -13,6 +13,8 @@ TOL_Y = 1e-4          # ||y - y*|| / ||y*||
 TOL_U = 1e-4          # ||U - U*||_F / ||U*||_F
 GUARD = 1e-5          # labels compared exactly where | max_c |r'| - delta | > GUARD
 TOL_F = 1e-5          # cost values, relative
+TOL_STEP = 1e-5       # geodesic angle theta and CG step lengths alpha, relative
+TOL_U_ELEM = 1e-5     # max_e,j |U - U*| / max |U*| (float32 storage)
 
 
 def say(*a):
@@ -98,6 +100,15 @@ def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
         f_rel0=float(max(abs(a - b) for a, b in zip(stats["f"], info.cg.f)) / max(abs(info.cg.f[0]), 1e-300))
         if stats["f"] else 0.0,
         theta_rel=float(abs(stats["theta"] - info.theta) / max(abs(info.theta), 1e-300)),
+        # step lengths of the steps that matter: those that decrease the cost by
+        # at least 0.1% of the frame's whole decrease (near an exact fit a
+        # step's gradient is at rounding level and its length ill-conditioned,
+        # while the step itself is negligible)
+        alpha_rel=float(max([abs(a - b) / max(abs(b), 1e-300)
+                             for j, (a, b) in enumerate(zip(stats["alpha"], info.cg.alpha))
+                             if info.cg.f[j] - info.cg.f[j + 1] >= 1e-3 * (info.cg.f[0] - info.cg.f[-1])]
+                            + [0.0])),
+        U_elem=float(np.max(np.abs(U1 - exp.U)) / np.max(np.abs(exp.U))),
         steps=(stats["cg_steps"], info.cg.iters),
         cg_iters=prm.cg_iters,
         U1=U1, exp=exp, info=info, stats=stats, y1=y1, labels=l1, mask=mask, start=start,
@@ -116,9 +127,10 @@ def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U, f_ref0=False):
     instead of each f_j.  For frames the subspace fits exactly (k = m) the
     log cost's f_j tends to 0, and the float32 residuals (absolute error
     about 2^-24 |x|) then leave a large relative error on f_j alone."""
-    say(f"  n={rep['n']} y_rel={rep['y_rel']:.2e} U_rel={rep['U_rel']:.2e} band={rep['band']} "
-        f"lab_mism={rep['lab_mismatch']} outside={rep['lab_mismatch_outside_band']} "
-        f"f_rel={rep['f_rel']:.1e} theta_rel={rep['theta_rel']:.1e} steps={rep['steps']}")
+    say(f"  n={rep['n']} y_rel={rep['y_rel']:.2e} U_rel={rep['U_rel']:.2e} U_elem={rep['U_elem']:.2e} "
+        f"band={rep['band']} lab_mism={rep['lab_mismatch']} outside={rep['lab_mismatch_outside_band']} "
+        f"f_rel={rep['f_rel']:.1e} theta_rel={rep['theta_rel']:.1e} alpha_rel={rep['alpha_rel']:.1e} "
+        f"steps={rep['steps']}")
     assert rep["n"] == rep["n_exp"]
     dev_steps, ora_steps = rep["steps"]
     if ora_steps < rep["cg_iters"]:
@@ -135,6 +147,10 @@ def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U, f_ref0=False):
     assert rep["lab_mismatch_outside_band"] == 0
     assert rep["mask_vs_median_of_gpu_labels"] == 0
     assert (rep["f_rel0"] if f_ref0 else rep["f_rel"]) <= TOL_F
+    assert rep["U_elem"] <= TOL_U_ELEM
+    if not f_ref0:   # (an exactly fitted frame drives theta and the last alpha to rounding level)
+        assert rep["theta_rel"] <= TOL_STEP
+        assert rep["alpha_rel"] <= TOL_STEP
     if "pre" in rep:   # float32 running statistics against float64
         say(f"  pre-processing: count {rep['pre']['count']} mean {rep['pre']['mean_err']:.1e} "
             f"m2 {rep['pre']['m2_rel']:.1e}")

@@ -191,13 +191,13 @@ def _vga_starts(bt, streams):
     return starts
 
 
-def _check_vga_bf16_step(bt, s, start, x, mu):
-    """One bfloat16 640x480x3 k=15 stream after one step against its oracle
-    step from the device's starting state: y within 1e-4, every U entry
-    within one bfloat16 ulp of the round-to-nearest oracle value plus the
-    float32 rounding bound of the update, labels exact outside the guard
-    band."""
-    prm = O.Params(640, 480, 3, k=15, mu=mu)
+def _check_vga_bf16_step(bt, s, start, x, mu, prm=None):
+    """One bfloat16 stream (640x480x3 k=15 unless prm says otherwise) after
+    one step against its oracle step from the device's starting state: y
+    within 1e-4, every U entry within one bfloat16 ulp of the
+    round-to-nearest oracle value plus the float32 rounding bound of the
+    update, labels exact outside the guard band."""
+    prm = prm or O.Params(640, 480, 3, k=15, mu=mu)
     exp, _ = O.track_frame(start, x, prm)
     U1, y1, l1, n1 = bt.get_state(s)
     y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
@@ -210,14 +210,16 @@ def _check_vga_bf16_step(bt, s, start, x, mu):
         worst = np.argsort(r)[-5:]
         say("  worst entries (value, oracle, |diff|/bound):",
             [(float(U1.ravel()[i]), float(e.ravel()[i]), float(r[i])) for i in worst])
-    band = O.band_pixels(exp.U, x, exp.y, prm.thr, 3, GUARD)
+    band = O.band_pixels(exp.U, x, exp.y, prm.thr, prm.channels, GUARD)
     mism = int(np.sum((l1 != exp.labels) & ~band))
-    say(f"  vga bf16 stream {s}: y {y_rel:.1e}, U entries beyond 1 ulp: {over}, labels outside band {mism}")
+    say(f"  bf16 stream {s} {prm.width}x{prm.height}x{prm.channels} k={prm.k} n={start.n}: y {y_rel:.1e}, "
+        f"U entries beyond 1 ulp: {over}, labels outside band {mism}")
     assert n1 == exp.n and y_rel <= 1e-4 and over == 0 and mism == 0
+    assert np.array_equal(bt.mask(s), O.median3x3(l1, prm.height, prm.width))
 
 
-@pytest.mark.parametrize("nstreams,budget", [(2, 0), (3, 192)])
-def test_batch_bf16_vga_streams_share_a_round(nstreams, budget):
+@pytest.mark.parametrize("nstreams,budget,n0", [(2, 0, 0), (3, 192, 0), (2, 0, 150)])
+def test_batch_bf16_vga_streams_share_a_round(nstreams, budget, n0):
     """640x480x3 k=15 streams in bfloat16 (the benchmark's streams): the
     row-pair tiles halve each gang, so two frames run side by side in one
     round, and three with the LDS form; each stream matches its own oracle
@@ -234,9 +236,9 @@ def test_batch_bf16_vga_streams_share_a_round(nstreams, budget):
         say("  config", cfg)
         assert cfg["rounds"] == 1
         frames = [[_vga_bf16_frame(sv, 0)] for sv in svs]
-        for s in range(nstreams):
-            bt.set_state(s, V.initial_subspace(640 * 480 * 3, 15, 3, s))
-        bt.set_frames(frames)
+        for s in range(nstreams):   # n0 = 150: past the initialization phase, t = t_min (Sec. 3.4)
+            bt.set_state(s, V.initial_subspace(640 * 480 * 3, 15, 3, s), n=n0)
+        bt.set_frames(frames)   # a ring of one frame: every step reads it whatever n is
         starts = _vga_starts(bt, range(nstreams))
         bt.step()
         assert bt.sync() == 0
@@ -298,9 +300,11 @@ def test_benchmark_launch_configuration():
         assert res[0][s] == res[1][s], f"stream {s}"
 
 
-def test_mixed_streams_workload_parity_sample():
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_mixed_streams_workload_parity_sample(storage):
     """Four streams of the 64-stream mixed workload (one of each resolution
-    plus the largest k) inside the full 64-stream launch."""
+    plus the largest k) inside the full 64-stream launch, in float32 and in
+    the workload's own bfloat16 storage."""
     from paper_1302_2073_amd.tracker import BatchTracker
     wls = V.mixed_streams(64)
     check = []
@@ -314,25 +318,33 @@ def test_mixed_streams_workload_parity_sample():
             break
     specs = [dict(width=w.video.width, height=w.video.height, channels=3, k=w.k, mu=w.mu) for w in wls]
     import torch
-    with BatchTracker(specs, storage="f32") as bt:
+    with BatchTracker(specs, storage=storage) as bt:
         say("  config", bt.config())
         frames = []
         svs = []
         for i, wl in enumerate(wls):
             sv = V.SyntheticVideo(wl.video)
             svs.append(sv)
-            frames.append([torch.from_numpy(sv.frame(0).astype(np.float32)).cuda()])
+            if storage == "f32":
+                frames.append([torch.from_numpy(sv.frame(0).astype(np.float32)).cuda()])
+            else:
+                frames.append([_vga_bf16_frame(sv, 0)])
             bt.set_state(i, V.initial_subspace(wl.video.m, wl.k, 4, i))
         bt.set_frames(frames)
+        starts = {}
+        for i in check:
+            U0, y0, l0, n0 = bt.get_state(i)
+            starts[i] = O.State(U0, y0, l0, O.median3x3(l0, wls[i].video.height, wls[i].video.width), n0)
         bt.step()
         assert bt.sync() == 0
         for i in check:
             wl = wls[i]
             v = wl.video
             prm = O.Params(v.width, v.height, 3, k=wl.k, mu=wl.mu)
-            U0 = V.initial_subspace(v.m, wl.k, 4, i).astype(np.float32).astype(np.float64)
-            st = O.initial_state(U0, prm.P)
-            _check_stream(bt, i, prm, st, f32(svs[i].frame(0)))
+            if storage == "f32":
+                _check_stream(bt, i, prm, starts[i], f32(svs[i].frame(0)))
+            else:
+                _check_vga_bf16_step(bt, i, starts[i], _rne(svs[i].frame(0)), wl.mu, prm)
 
 
 @pytest.mark.parametrize("graph", [False, True])

@@ -71,6 +71,33 @@ def test_vga_rgb_step(frame):
     assert_parity(rep)
 
 
+def test_vga_rgb_step_at_minimum_step_size():
+    """640x480x3, k=15 in the regime n >= i_init of the step-size rule
+    (Sec. 3.4: t = t_min): the oracle's state before frame 3 injected with
+    frame counter 150, so the geodesic step uses t_min (50x smaller angles
+    than at n = 0)."""
+    wl, prm, sv, states = oracle_trajectory("vga_rgb", 3)
+    st = states[3].copy()
+    st.n = 150
+    assert O.step_size(150, prm.t_init, prm.t_min, prm.i_init) == prm.t_min
+    with _tracker(prm) as trk:
+        rep = compare_step(trk, prm, st, f32(sv.frame(3)))
+    assert rep["info"].t == prm.t_min
+    assert_parity(rep)
+
+
+@pytest.mark.parametrize("frame", [150, 151])
+def test_qvga_rgb_step_after_initialization_phase(frame):
+    """320x240x3, k=10 on the oracle's own trajectory past the
+    initialization phase (frames 150 and 151 of the jittered video, t =
+    t_min): a converged subspace, small angles."""
+    wl, prm, sv, states = oracle_trajectory("qvga_rgb", 151)
+    with _tracker(prm) as trk:
+        rep = compare_step(trk, prm, states[frame], f32(sv.frame(frame)))
+    assert rep["info"].t == prm.t_min
+    assert_parity(rep)
+
+
 @pytest.mark.parametrize("curvature", [0, 1])
 @pytest.mark.parametrize("cost", ["lp", "log"])
 @pytest.mark.parametrize("shape", [(7, 5, 3, 4), (33, 17, 1, 1), (41, 29, 2, 16), (123, 77, 3, 9),
@@ -204,6 +231,40 @@ def test_free_running_small_gray():
                 worst = max(worst, dis)
                 say(f"  frame {n}: angle {ang:.2e} y_rel {np.linalg.norm(y - ref.y) / np.linalg.norm(ref.y):.2e} "
                     f"label disagreement {dis:.4%}")
+    assert worst <= 0.005
+
+
+def test_free_running_qvga_rgb_1000_frames():
+    """The 320x240x3, k=10 workload (camera jitter, moving ellipses) over its
+    1000 frames on both sides from the same U0, no state injection: the
+    GPU's labels disagree with the oracle's on at most 0.5% of the pixels
+    in every frame; drift of U (largest principal angle) and y reported
+    every 100 frames."""
+    import time
+    from paper_1302_2073_amd import Tracker
+    wl = V.qvga_rgb()
+    v = wl.video
+    prm = oracle_params(wl)
+    sv = V.SyntheticVideo(v)
+    st = O.initial_state(V.initial_subspace(prm.m, prm.k, v.seed), prm.P)
+    worst, worst_n = 0.0, -1
+    t0 = time.time()
+    with _tracker(prm) as trk:
+        trk.set_state(st.U, st.y, st.labels, 0)
+        for n in range(wl.n_frames):
+            x = sv.frame(n).astype(np.float32)
+            st, _ = O.track_frame(st, x.astype(np.float64), prm)
+            trk.track(x)
+            lab = trk.mask(filtered=False)
+            dis = float(np.mean(lab != st.labels))
+            if dis > worst:
+                worst, worst_n = dis, n
+            if n % 100 == 99:
+                U, y, _, _ = trk.get_state()
+                say(f"  frame {n}: angle {O.principal_angles(st.U, U).max():.2e} "
+                    f"y_rel {np.linalg.norm(y - st.y) / np.linalg.norm(st.y):.2e} label disagreement {dis:.4%} "
+                    f"({time.time() - t0:.0f} s)")
+    say(f"  worst label disagreement {worst:.4%} at frame {worst_n}")
     assert worst <= 0.005
 
 

@@ -45,6 +45,10 @@ def _bf16_check(trk, prm, st, x, label=""):
         say("  worst entries (value, oracle, |diff|/bound):",
             [(float(rep["U1"].ravel()[i]), float(exp.ravel()[i]), float((diff / ulp).ravel()[i])) for i in worst])
     n1ulp = int(np.sum(diff > 0))
+    # entries that pass only through the float32 rounding terms of the bound
+    beyond = int(np.sum(diff > np.maximum(bf16_ulp(exp), bf16_ulp(rep["U1"])) * (1 + 1e-12)))
+    rep["beyond_ulp"] = beyond
+    say(f"  bf16 {label}: entries beyond one plain bfloat16 ulp (inside the rounding bound): {beyond}")
     say(f"  bf16 {label}: launch {trk.launch_info()['rows_per_thread']} rows/thread, "
         f"y_rel={rep['y_rel']:.2e} U entries off by 1 ulp: {n1ulp} "
         f"(> 1 ulp: {over}) of {diff.size}; label mismatches outside band {rep['lab_mismatch_outside_band']} "
@@ -60,6 +64,9 @@ def _bf16_check(trk, prm, st, x, label=""):
     # round-to-nearest-even storage: entries off by one ulp are rare (a
     # truncating conversion would move a large share of them)
     assert n1ulp <= 1e-3 * diff.size + 2
+    # entries beyond one plain ulp, admitted only by the float32 rounding terms
+    # of the bound, stay rare (measured: at most 56 of 13.8 million)
+    assert beyond <= 1e-5 * diff.size + 2
     assert rep["lab_mismatch_outside_band"] == 0
     assert rep["mask_vs_median_of_gpu_labels"] == 0
     return rep
@@ -83,6 +90,20 @@ def test_bf16_small_gray(frame):
 @pytest.mark.parametrize("frame", [0, 2])
 def test_bf16_vga_rgb(frame):
     _bf16_step("vga_rgb", frame, 2)
+
+
+def test_bf16_vga_rgb_at_minimum_step_size():
+    """The benchmark's bfloat16 640x480x3 k=15 frame with frame counter 150
+    (t = t_min, Sec. 3.4): the small-angle regime, where round-to-nearest
+    storage leaves most updates below half an ulp."""
+    from gpu_common import oracle_trajectory
+    wl, prm, sv, states = oracle_trajectory("vga_rgb", 2)
+    st = states[2].copy()
+    st.n = 150
+    x = rne_bf16(sv.frame(2))
+    with _tracker(prm, "bf16") as trk:
+        rep = _bf16_check(trk, prm, st, x, "vga_rgb frame 2 at n = 150")
+    assert rep["info"].t == prm.t_min
 
 
 @pytest.mark.parametrize("nr", [2, 4, 8, 16])
@@ -194,3 +215,79 @@ def test_bf16_free_running_with_reorth_reports_drift():
                 if n % 50 == 49:
                     assert O.orthonormality_error(U) < 5e-3
     assert worst <= 0.005
+
+
+def test_precision_workload_report():
+    """The precision workload (640x480x3, k=15): the bfloat16 tracker with
+    float64 re-orthonormalisation every 50 frames and the float32 tracker,
+    free-running from the same U0, each beside the float64 oracle on the
+    same inputs (bfloat16-rounded frames and U0 for the bfloat16 tracker).
+    Every 50 frames: largest principal angle between the GPU's and the
+    oracle's U, y relative error, ||U^T U - I||_F of the GPU's U, label
+    disagreement and (bfloat16) the share of U entries the frame left
+    unchanged.  120 frames by default (two re-orthonormalisations, the
+    step size still decaying); PROST_C3_FRAMES=1000 runs the whole video
+    and PROST_C3_JSON names a file for the table.  Gate: label
+    disagreement at most 0.5% in every frame, for both storage types."""
+    import concurrent.futures as cf
+    import json
+    import os
+    import time
+    import torch
+    from paper_1302_2073_amd import Tracker
+    from paper_1302_2073_amd.tracker import bf16_bits
+    frames = int(os.environ.get("PROST_C3_FRAMES", "120"))
+    wl = V.vga_rgb()
+    v = wl.video
+    sv = V.SyntheticVideo(v)
+    prm32 = oracle_params(wl)
+    prmbf = oracle_params(wl)
+    U0 = V.initial_subspace(prm32.m, prm32.k, v.seed)
+    st = {"f32": O.initial_state(U0.astype(np.float32).astype(np.float64), prm32.P),
+          "bf16": O.initial_state(rne_bf16(U0), prm32.P)}
+    trk = {"f32": Tracker(640, 480, 3, 15, **tracker_kwargs(prm32, "f32")),
+           "bf16": Tracker(640, 480, 3, 15, reorth_every=50, **tracker_kwargs(prmbf, "bf16"))}
+    rows, worst = [], {"f32": 0.0, "bf16": 0.0}
+    t0 = time.time()
+    pool = cf.ThreadPoolExecutor(2)
+    try:
+        for key in trk:
+            trk[key].set_state(U0)
+        for n in range(frames):
+            x64 = sv.frame(n)
+            xin = {"f32": x64.astype(np.float32).astype(np.float64), "bf16": rne_bf16(x64)}
+            futs = {key: pool.submit(O.track_frame, st[key], xin[key], prm32) for key in st}
+            check = (n + 1) % 50 == 0 or n + 1 == frames
+            before = trk["bf16"].get_state()[0] if check else None
+            trk["f32"].track(torch.from_numpy(xin["f32"].astype(np.float32)).cuda())
+            trk["bf16"].track(torch.from_numpy(bf16_bits(x64).view(np.int16)).cuda().view(torch.bfloat16))
+            for key in st:
+                st[key] = futs[key].result()[0]
+                lab = trk[key].mask(filtered=False)
+                worst[key] = max(worst[key], float(np.mean(lab != st[key].labels)))
+            if check:
+                row = {"frame": n}
+                for key in ("f32", "bf16"):
+                    U, y, lab, _ = trk[key].get_state()
+                    ref = st[key]
+                    row[key] = dict(angle=float(O.principal_angles(ref.U, U).max()),
+                                    y_rel=float(np.linalg.norm(y - ref.y) / np.linalg.norm(ref.y)),
+                                    orth=float(O.orthonormality_error(U)),
+                                    labels=float(np.mean(lab != ref.labels)))
+                    if key == "bf16":
+                        row[key]["unchanged"] = float(np.mean(U == before))
+                rows.append(row)
+                say(f"  frame {n}: " + "; ".join(
+                    f"{k} angle {r['angle']:.2e} y {r['y_rel']:.2e} orth {r['orth']:.2e} labels {r['labels']:.4%}"
+                    + (f" unchanged {r['unchanged']:.1%}" if "unchanged" in r else "")
+                    for k, r in ((k, row[k]) for k in ("f32", "bf16"))) + f" ({time.time() - t0:.0f} s)")
+    finally:
+        pool.shutdown()
+        for t in trk.values():
+            t.close()
+    say(f"  worst label disagreement over {frames} frames: f32 {worst['f32']:.4%}, bf16 {worst['bf16']:.4%}")
+    out = os.environ.get("PROST_C3_JSON")
+    if out:
+        with open(out, "w") as fh:
+            json.dump({"frames": frames, "rows": rows, "worst_labels": worst}, fh)
+    assert worst["f32"] <= 0.005 and worst["bf16"] <= 0.005
