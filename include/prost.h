@@ -328,6 +328,12 @@ PROS_API void pros_batch_destroy(pros_batch* b);
 PROS_API pros_status pros_batch_set_state(pros_batch* b, int32_t s, const double* U, const double* y,
                                  const uint8_t* labels, int64_t n);
 PROS_API pros_status pros_batch_get_state(pros_batch* b, int32_t s, double* U, double* y, uint8_t* labels, int64_t* n);
+/* Same contract as pros_set_preprocess / pros_get_preprocess for stream s
+ * (a stream created with preprocess = 1; PROS_ESTATE otherwise). */
+PROS_API pros_status pros_batch_set_preprocess(pros_batch* b, int32_t s, const double* mean, const double* m2,
+                                               int64_t count);
+PROS_API pros_status pros_batch_get_preprocess(pros_batch* b, int32_t s, double* mean, double* m2, int64_t* count,
+                                               double* scale);
 /* Register the frame ring: n * ring device pointers (host array; stream s,
  * slot i at frames[s * ring + i]), each m_s entries of the storage type.
  * The pointed-to frames must stay valid while batch steps run.  Synchronous. */
@@ -342,7 +348,10 @@ PROS_API pros_status pros_batch_track(pros_batch* b);
  * budget 128 and the default features only; otherwise one launch per
  * step.  Asynchronous. */
 PROS_API pros_status pros_batch_track_steps(pros_batch* b, int32_t steps);
-/* 1: capture the launch into a hipGraph on first use and replay it. */
+/* 1: capture the launch into a hipGraph on first use and replay it; the
+ * multi-step launch of pros_batch_track_steps gets a graph of its own (per
+ * step count), recaptured when the step count, the frame ring or the launch
+ * configuration changes. */
 PROS_API pros_status pros_batch_use_graph(pros_batch* b, int32_t on);
 PROS_API pros_status pros_batch_sync(pros_batch* b);
 PROS_API pros_status pros_batch_get_mask(pros_batch* b, int32_t s, uint8_t* out, int32_t filtered, int32_t on_device);

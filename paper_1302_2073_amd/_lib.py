@@ -117,6 +117,9 @@ _SIGS = {
     "pros_batch_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "pros_batch_get_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.POINTER(C.c_int64)]),
+    "pros_batch_set_preprocess": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64]),
+    "pros_batch_get_preprocess": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
     "pros_batch_set_frames": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32]),
     "pros_batch_track": (C.c_int, [C.c_void_p]),
     "pros_batch_track_steps": (C.c_int, [C.c_void_p, C.c_int32]),

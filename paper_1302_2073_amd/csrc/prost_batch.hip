@@ -100,6 +100,8 @@ struct pros_batch {
   bool coop = true;              // cooperative launch, or an ordinary dispatch of the resident grid
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph_seq = nullptr;       // the multi-step launch (seq_steps steps), captured likewise
+  hipGraphExec_t gexec_seq = nullptr;
   bool broken = false;
   bool ext = false;              // a stream uses the optional features
   // multi-step launches: descriptors with nseq = seq_steps
@@ -111,9 +113,18 @@ struct pros_batch {
 static void drop_graph(pros_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->gexec_seq) (void)hipGraphExecDestroy(b->gexec_seq);
+  if (b->graph_seq) (void)hipGraphDestroy(b->graph_seq);
   b->gexec = nullptr;
   b->graph = nullptr;
+  b->gexec_seq = nullptr;
+  b->graph_seq = nullptr;
 }
+
+// Capture one launch of `fn` over `descs` on the private capture stream and
+// instantiate it.
+static pros_status capture_launch(pros_batch* b, const void* fn, FrameArgs* descs, hipGraph_t* g_out,
+                                  hipGraphExec_t* x_out);
 
 static void free_batch(pros_batch* b) {
   if (!b) return;
@@ -240,6 +251,27 @@ static pros_status launch(pros_batch* b, hipStream_t on, const void* fn = nullpt
   return PROS_OK;
 }
 
+static pros_status capture_launch(pros_batch* b, const void* fn, FrameArgs* descs, hipGraph_t* g_out,
+                                  hipGraphExec_t* x_out) {
+  hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail(PROS_EHIP, "begin capture: %s", hipGetErrorString(e));
+  pros_status ls = launch(b, b->capture_stream, fn, descs);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->capture_stream, &g);
+  if (ls != PROS_OK) return ls;
+  if (e != hipSuccess) {
+    b->broken = true;
+    return fail(PROS_EHIP, "end capture: %s", hipGetErrorString(e));
+  }
+  *g_out = g;
+  e = hipGraphInstantiate(x_out, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    b->broken = true;
+    return fail(PROS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  return PROS_OK;
+}
+
 static pros_status check_batch(pros_batch* b) {
   if (!b) return fail(PROS_EINVAL, "batch is NULL");
   if (b->broken) return fail(PROS_EHIP, "batch unusable after an earlier error");
@@ -345,6 +377,20 @@ pros_status pros_batch_get_state(pros_batch* b, int32_t s, double* U, double* y,
   return pros_get_state(b->hs[s], U, y, labels, n);
 }
 
+pros_status pros_batch_set_preprocess(pros_batch* b, int32_t s, const double* mean, const double* m2,
+                                      int64_t count) {
+  pros_status st = check_stream(b, s);
+  if (st != PROS_OK) return st;
+  return pros_set_preprocess(b->hs[s], mean, m2, count);
+}
+
+pros_status pros_batch_get_preprocess(pros_batch* b, int32_t s, double* mean, double* m2, int64_t* count,
+                                      double* scale) {
+  pros_status st = check_stream(b, s);
+  if (st != PROS_OK) return st;
+  return pros_get_preprocess(b->hs[s], mean, m2, count, scale);
+}
+
 pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int32_t ring) {
   pros_status st = check_batch(b);
   if (st != PROS_OK) return st;
@@ -396,22 +442,8 @@ pros_status pros_batch_track(pros_batch* b) {
     if (!h->state_set) return fail(PROS_ESTATE, "set every stream's U before the first batch step");
   if (b->use_graph) {
     if (!b->gexec) {
-      hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return fail(PROS_EHIP, "begin capture: %s", hipGetErrorString(e));
-      pros_status ls = launch(b, b->capture_stream);
-      hipGraph_t g = nullptr;
-      e = hipStreamEndCapture(b->capture_stream, &g);
-      if (ls != PROS_OK) return ls;
-      if (e != hipSuccess) {
-        b->broken = true;
-        return fail(PROS_EHIP, "end capture: %s", hipGetErrorString(e));
-      }
-      b->graph = g;
-      e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        b->broken = true;
-        return fail(PROS_EHIP, "graph instantiate: %s", hipGetErrorString(e));
-      }
+      st = capture_launch(b, b->kfn, b->d_descs, &b->graph, &b->gexec);
+      if (st != PROS_OK) return st;
     }
     hipError_t e = hipGraphLaunch(b->gexec, b->stream);
     if (e != hipSuccess) {
@@ -459,9 +491,25 @@ pros_status pros_batch_track_steps(pros_batch* b, int32_t steps) {
     if (e != hipSuccess) return fail(PROS_EHIP, "descriptor upload: %s", hipGetErrorString(e));
     b->seq_steps = steps;
     b->seq_version = b->descs_version;
+    if (b->gexec_seq) (void)hipGraphExecDestroy(b->gexec_seq);
+    if (b->graph_seq) (void)hipGraphDestroy(b->graph_seq);
+    b->gexec_seq = nullptr;
+    b->graph_seq = nullptr;
   }
-  st = launch(b, b->stream, fn, b->d_descs_seq);
-  if (st != PROS_OK) return st;
+  if (b->use_graph) {   // the multi-step launch replayed from its own graph
+    if (!b->gexec_seq) {
+      st = capture_launch(b, fn, b->d_descs_seq, &b->graph_seq, &b->gexec_seq);
+      if (st != PROS_OK) return st;
+    }
+    e = hipGraphLaunch(b->gexec_seq, b->stream);
+    if (e != hipSuccess) {
+      b->broken = true;
+      return fail(PROS_EHIP, "graph launch: %s", hipGetErrorString(e));
+    }
+  } else {
+    st = launch(b, b->stream, fn, b->d_descs_seq);
+    if (st != PROS_OK) return st;
+  }
   for (pros_handle* h : b->hs) {
     h->submitted += steps;
     h->mask_stale = true;

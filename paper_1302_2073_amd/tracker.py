@@ -295,6 +295,16 @@ class BatchTracker:
         L.check(L.lib().pros_batch_set_state(self._b, s, _ptr(Ucm), None if yv is None else _ptr(yv),
                                              None if lab is None else _ptr(lab), int(n)))
 
+    def get_preprocess(self, s):
+        """Stream s's pre-processing statistics (mean, m2, count, scale)."""
+        P, m, k = self._dims(s)
+        mv = np.empty(m, np.float64)
+        vv = np.empty(m, np.float64)
+        cnt = C.c_int64()
+        sc = C.c_double()
+        L.check(L.lib().pros_batch_get_preprocess(self._b, s, _ptr(mv), _ptr(vv), C.byref(cnt), C.byref(sc)))
+        return mv, vv, int(cnt.value), float(sc.value)
+
     def get_state(self, s):
         P, m, k = self._dims(s)
         Ucm = np.empty((k, m), np.float64)
