@@ -176,7 +176,12 @@ def run_plain_host(steps, warmup, pool):
 
 def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1, per_launch=1):
     """nstreams independent 640x480x3 k=15 streams, each with its own seeded
-    video, one persistent launch per batch step (hipGraph replay)."""
+    video, one persistent launch per batch step (hipGraph replay).
+    per_launch > 1: launches of that many steps each (also replayed from a
+    hipGraph); per_launch = 0: the steps per launch are chosen from
+    {4, 8, 16, 32} by timing each on the real frames (part of tuning).
+    Exactly `steps` steps are timed: whole launches plus one shorter launch
+    for the remainder."""
     import torch
     from paper_1302_2073_amd.tracker import BatchTracker, bf16_bits
     from synth import video as V
@@ -202,13 +207,32 @@ def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1
     tuned = bt.tune(steps=3) if tune else None
     bt.use_graph(True)
     stream = torch.cuda.current_stream()
+    spl_times = None
+    if per_launch == 0:   # steps per launch tuned on the real frames
+        spl_times = {}
+        for cand in (4, 8, 16, 32):
+            for _ in range(2):
+                bt.steps(cand)
+            torch.cuda.synchronize()
+            n_calls = max(64 // cand, 2)
+            t, _, _ = timed_median(lambda i: bt.steps(cand), n_calls, stream)
+            spl_times[cand] = round(t / (n_calls * cand), 5)
+        per_launch = min(spl_times, key=spl_times.get)
     if per_launch > 1:   # several steps per launch, tiles kept in registers
         for _ in range(max(warmup // per_launch, 2)):
             bt.steps(per_launch)
+        if steps % per_launch:
+            bt.steps(steps % per_launch)   # the remainder launch's graph, captured before timing
         torch.cuda.synchronize()
-        calls = max(steps // per_launch, 1)
-        ms, lo, hi = timed_median(lambda i: bt.steps(per_launch), calls, stream)
-        steps = calls * per_launch
+        calls = steps // per_launch
+        rem = steps % per_launch
+
+        def run(i):
+            if i < calls:
+                bt.steps(per_launch)
+            else:
+                bt.steps(rem)
+        ms, lo, hi = timed_median(run, calls + (1 if rem else 0), stream)
     else:
         for _ in range(warmup):
             bt.step()
@@ -220,7 +244,8 @@ def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1
     cfg = bt.config()
     bt.close()
     return dict(ms_total=ms, ms_per_step=ms / steps, fps=steps * nstreams / (ms / 1e3), config=cfg, tuned=tuned,
-                spread_ms=[round(lo, 3), round(hi, 3)], steps_per_launch=per_launch)
+                spread_ms=[round(lo, 3), round(hi, 3)], steps_per_launch=per_launch, steps_timed=steps,
+                steps_per_launch_ms_per_step=spl_times)
 
 
 def run_batched_mixed(nstreams, steps, warmup, pool, per_launch=1):
@@ -488,6 +513,8 @@ def main():
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
+    ap.add_argument("--steps-per-launch", type=int, default=8,
+                    help="headline form with --no-tune: batch steps per launch (tuned otherwise)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -570,12 +597,15 @@ def main():
     bsq = None
     if "batched_bf16_seq" in want:
         bsq = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune,
-                          per_launch=8)
+                          per_launch=0 if not args.no_tune else args.steps_per_launch)
         achieved = record("batched_bf16_seq", bsq, 2, 2, args.streams)
         if batched:
             forms["batched_bf16_seq"]["vs_one_step_per_launch"] = round(bsq["fps"] / batched["fps"], 3)
-        forms["batched_bf16_seq"]["note"] = ("8 batch steps per launch (frames buffered in each stream's ring), "
-                                             "tiles kept in registers between a stream's frames")
+        forms["batched_bf16_seq"]["steps_per_launch"] = bsq["steps_per_launch"]
+        if bsq["steps_per_launch_ms_per_step"]:
+            forms["batched_bf16_seq"]["steps_per_launch_ms_per_step"] = bsq["steps_per_launch_ms_per_step"]
+        forms["batched_bf16_seq"]["note"] = ("several batch steps per launch (frames buffered in each stream's ring), "
+                                             "tiles kept in registers between a stream's frames; hipGraph replay")
     if "batched_bf16_ordinary" in want:
         try:
             bod = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune,
@@ -658,21 +688,27 @@ def main():
     head = bsq if bsq is not None else (batched if batched is not None else plain)
     if head is None:   # a diagnostic run of other forms only: no headline
         print(json.dumps({"metric": None, "value": None, "forms": forms}), flush=True)
+        release_device()
         return
 
+    steps_timed = head.get("steps_timed", args.steps)
     if bsq is not None:
-        traffic = measured_traffic("batch_kernel_seq<bf16>", f"{args.streams}x640x480x3 k=15 bf16 8 steps")
-        launch_desc = ("8 batch steps per persistent launch (frames resident in each stream's ring; every frame's "
-                       "labels and 3x3 mask formed), launched directly")
+        spl = bsq["steps_per_launch"]
+        traffic = measured_traffic("batch_kernel_seq<bf16>", f"{args.streams}x640x480x3 k=15 bf16 {spl} steps")
+        launch_desc = (f"{spl} batch steps per persistent cooperative launch, replayed from a hipGraph (frames "
+                       f"resident in each stream's ring; every frame's labels and 3x3 mask formed)")
+        per_launch_ms = head["ms_per_step"] * spl
     else:
+        spl = 1
         traffic = measured_traffic("batch_kernel<bf16>", f"{args.streams}x640x480x3 k=15 bf16")
-        launch_desc = "one persistent launch per step (hipGraph)"
+        launch_desc = "one persistent cooperative launch per step, replayed from a hipGraph"
+        per_launch_ms = head.get("ms_per_step", head.get("ms_per_frame"))
     out = {
         "metric": "frames/sec at 640x480x3, k=15 (plain vs batched BF16); HBM GB/s vs peak",
         "value": round(head["fps"], 1),
         "unit": "frames/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps_timed,
         "warmup": args.warmup,
         "ms_per_step": round(head.get("ms_per_step", head.get("ms_per_frame")), 5),
         "higher_is_better": True,
@@ -684,12 +720,30 @@ def main():
                                f"5 CG steps, {launch_desc}",
                    "streams": args.streams, "plain_f32_fps": round(plain["fps"], 1) if plain else None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "traffic_GBps": (round(traffic / (per_launch_ms * 1e-3) / 1e9, 1) if traffic else None),
+                     "per_launch": f"{spl} steps x {args.streams} streams"},
         "forms": forms,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+    release_device()
+
+
+def release_device():
+    """Return every device allocation before the interpreter exits: the
+    trackers are closed by their forms; frames and workspaces that went back
+    to torch's caching allocator are freed here, while the HIP runtime (and
+    a profiler attached to it) is still fully up, instead of during the
+    process's exit handlers."""
+    import gc
+    import torch
+    gc.collect()
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

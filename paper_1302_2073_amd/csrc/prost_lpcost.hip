@@ -60,33 +60,45 @@ __device__ __forceinline__ void stage_frames(const float* __restrict__ Y, int b0
   for (int q = thread_index(); q < nb * K; q += kLpBlock) ys[q / K][q % K] = Y[(long long)b0 * K + q];
 }
 
+// Frame entries of this thread's row for frames b .. b + kLpSub - 1 (0 past
+// the last frame or row): one coalesced load per frame across the workgroup.
+constexpr int kLpSub = 8;   // frames per prefetch step
+__device__ __forceinline__ void fetch_frames(float (&buf)[kLpSub], const float* __restrict__ X, long long m,
+                                             long long e, bool valid, int b, int B) {
+#pragma unroll
+  for (int i = 0; i < kLpSub; ++i) buf[i] = (valid && b + i < B) ? X[(long long)(b + i) * m + e] : 0.f;
+}
+
 // Forward: each thread owns one row e (u_e in registers) and walks the
-// frames; the chunk's frame entries are requested before U and Y are staged,
-// so their latency overlaps.  Per frame the workgroup's sum of w phi(r) is
-// formed with one in-place reduce-scatter per chunk and float64 across
-// wavefronts.
+// frames in passes of kLpChunkF, eight at a time, with the next eight
+// frames' entries requested before the current ones are used (the loads of
+// the first eight are in flight while U and Y are staged), so memory and
+// arithmetic overlap within every workgroup.  Per frame the workgroup's sum
+// of w phi(r) is formed with one in-place reduce-scatter per pass and float64
+// across wavefronts.  Partials: part[b * nblk + workgroup].
 template <int K>
 __global__ __launch_bounds__(kLpBlock) void lpcost_fwd_kernel(const float* __restrict__ U, const float* __restrict__ Y,
                                                               const float* __restrict__ X, const float* __restrict__ w,
                                                               int m, int B, int form, float p, const float* __restrict__ mu_p,
                                                               double* __restrict__ part) {
   constexpr int CH = kLpChunkF;
+  constexpr int NS = CH / kLpSub;
   __shared__ __align__(16) float uT[K][kLpPad];
   __shared__ float ys[CH][K];
   __shared__ double red[kLpWaves][CH];
   const CostParams cp = make_cp(form, p, *mu_p);
   const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
+  const int nblk = gridDim.x;
   const long long e0 = (long long)blockIdx.x * kLpBlock;
   const int nrow = (int)((long long)m - e0 < kLpBlock ? (long long)m - e0 : kLpBlock);
   const bool valid = tid < nrow;
   const long long e = e0 + tid;
   const float wt = valid ? (w ? w[e] : 1.0f) : 0.f;
+  float xb[2][kLpSub];
+  fetch_frames(xb[0], X, m, e, valid, 0, B);
   float u[K];
   for (int b0 = 0; b0 < B; b0 += CH) {
     const int nb = min(CH, B - b0);
-    float xv[CH];
-#pragma unroll
-    for (int bl = 0; bl < CH; ++bl) xv[bl] = (bl < nb && valid) ? X[(long long)(b0 + bl) * m + e] : 0.f;
     __syncthreads();
     if (b0 == 0) stage_rows<K>(U, e0, nrow, uT);
     stage_frames<K, CH>(Y, b0, nb, ys);
@@ -97,13 +109,18 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_fwd_kernel(const float* __res
     }
     float acc[CH];
 #pragma unroll
-    for (int bl = 0; bl < CH; ++bl) {
-      float r = xv[bl];
+    for (int st = 0; st < NS; ++st) {
+      fetch_frames(xb[(st + 1) & 1], X, m, e, valid, b0 + (st + 1) * kLpSub, B);   // the next eight
 #pragma unroll
-      for (int j = 0; j < K; ++j) r = fmaf(-u[j], ys[bl][j], r);
-      float phi, c;
-      cost_eval(r, cp, phi, c);
-      acc[bl] = (bl < nb) ? wt * phi : 0.f;
+      for (int i = 0; i < kLpSub; ++i) {
+        const int bl = st * kLpSub + i;
+        float r = xb[st & 1][i];
+#pragma unroll
+        for (int j = 0; j < K; ++j) r = fmaf(-u[j], ys[bl][j], r);
+        float phi, c;
+        cost_eval(r, cp, phi, c);
+        acc[bl] = (bl < nb) ? wt * phi : 0.f;
+      }
     }
     int comp;
     const float v = wave_reduce_scatter<CH>(acc, comp);
@@ -113,16 +130,17 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_fwd_kernel(const float* __res
       double sum = 0.0;
 #pragma unroll
       for (int q = 0; q < kLpWaves; ++q) sum += red[q][tid];
-      part[(size_t)blockIdx.x * B + b0 + tid] = sum;
+      part[(size_t)(b0 + tid) * nblk + blockIdx.x] = sum;
     }
   }
 }
 
 // Backward: per frame each thread forms s = g w phi'(r) for its row, writes
 // dX, accumulates its dU row and dmu in registers, and leaves s in LDS; after
-// each chunk the workgroup's share of dY (chunk x K) is formed from LDS, one
-// output per thread, rows in order.  Partials: nb x K of dY per chunk, then
-// dmu last (n = B K + 1 per workgroup).
+// each pass of kLpChunkB frames the workgroup's share of dY (pass x K) is
+// formed from LDS, one output per thread, rows in order.  Frame entries are
+// prefetched eight frames ahead as in the forward kernel.  Partials
+// (output q = b K + j of dY, then dmu at q = B K): part[q * nblk + workgroup].
 template <int K>
 __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __restrict__ U, const float* __restrict__ Y,
                                                               const float* __restrict__ X, const float* __restrict__ w,
@@ -130,6 +148,7 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
                                                               const float* __restrict__ gout, float* __restrict__ dX,
                                                               float* __restrict__ dU, double* __restrict__ part) {
   constexpr int CH = kLpChunkB;
+  constexpr int NS = CH / kLpSub;
   __shared__ __align__(16) float uT[K][kLpPad];
   __shared__ __align__(16) float sdl[CH][kLpPad];
   __shared__ float ys[CH][K];
@@ -137,21 +156,20 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
   __shared__ double redm[kLpWaves];
   const CostParams cp = make_cp(form, p, *mu_p);
   const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
+  const int nblk = gridDim.x;
   const long long e0 = (long long)blockIdx.x * kLpBlock;
   const int nrow = (int)((long long)m - e0 < kLpBlock ? (long long)m - e0 : kLpBlock);
   const bool valid = tid < nrow;
   const long long e = e0 + tid;
   const float wt = valid ? (w ? w[e] : 1.0f) : 0.f;
-  const size_t np = (size_t)B * K + 1;
   float u[K], du[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) du[j] = 0.f;
   float dmu = 0.f;
+  float xb[2][kLpSub];
+  fetch_frames(xb[0], X, m, e, valid, 0, B);
   for (int b0 = 0; b0 < B; b0 += CH) {
     const int nb = min(CH, B - b0);
-    float xv[CH];
-#pragma unroll
-    for (int bl = 0; bl < CH; ++bl) xv[bl] = (bl < nb && valid) ? X[(long long)(b0 + bl) * m + e] : 0.f;
     __syncthreads();
     if (b0 == 0) stage_rows<K>(U, e0, nrow, uT);
     stage_frames<K, CH>(Y, b0, nb, ys);
@@ -162,22 +180,27 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
       for (int j = 0; j < K; ++j) u[j] = uT[j][tid];
     }
 #pragma unroll
-    for (int bl = 0; bl < CH; ++bl) {
-      float sd = 0.f;
-      if (bl < nb && valid) {
-        float r = xv[bl];
+    for (int st = 0; st < NS; ++st) {
+      fetch_frames(xb[(st + 1) & 1], X, m, e, valid, b0 + (st + 1) * kLpSub, B);   // the next eight
 #pragma unroll
-        for (int j = 0; j < K; ++j) r = fmaf(-u[j], ys[bl][j], r);
-        float phi, c;
-        cost_eval(r, cp, phi, c);
-        const float gw = gs[bl] * wt;
-        sd = gw * c * r;                         // g w phi'(r)
-        if (dX) dX[(long long)(b0 + bl) * m + e] = sd;
-        dmu = fmaf(gw, dphi_dmu(r, c, cp), dmu);
+      for (int i = 0; i < kLpSub; ++i) {
+        const int bl = st * kLpSub + i;
+        float sd = 0.f;
+        if (bl < nb && valid) {
+          float r = xb[st & 1][i];
 #pragma unroll
-        for (int j = 0; j < K; ++j) du[j] = fmaf(-sd, ys[bl][j], du[j]);
+          for (int j = 0; j < K; ++j) r = fmaf(-u[j], ys[bl][j], r);
+          float phi, c;
+          cost_eval(r, cp, phi, c);
+          const float gw = gs[bl] * wt;
+          sd = gw * c * r;                         // g w phi'(r)
+          if (dX) dX[(long long)(b0 + bl) * m + e] = sd;
+          dmu = fmaf(gw, dphi_dmu(r, c, cp), dmu);
+#pragma unroll
+          for (int j = 0; j < K; ++j) du[j] = fmaf(-sd, ys[bl][j], du[j]);
+        }
+        if (bl < nb) sdl[bl][tid] = sd;
       }
-      if (bl < nb) sdl[bl][tid] = sd;
     }
     __syncthreads();
     // dY share of this workgroup: -sum_rows s[b][row] u[row][j], rows in order
@@ -194,7 +217,7 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
         a2 = fmaf(sv.z, uv.z, a2);
         a3 = fmaf(sv.w, uv.w, a3);
       }
-      part[(size_t)blockIdx.x * np + (size_t)b0 * K + q] = -(((double)a0 + (double)a1) + ((double)a2 + (double)a3));
+      part[(size_t)((size_t)b0 * K + q) * nblk + blockIdx.x] = -(((double)a0 + (double)a1) + ((double)a2 + (double)a3));
     }
   }
   if (dU) {   // coalesced store of the workgroup's dU rows through LDS
@@ -212,20 +235,22 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
   if (tid == 0) {
     double v = 0.0;
     for (int q = 0; q < kLpWaves; ++q) v += redm[q];
-    part[(size_t)blockIdx.x * np + (size_t)B * K] = v;
+    part[(size_t)B * K * nblk + blockIdx.x] = v;
   }
 }
 
-// out[q] = sum over workgroups b of part[b * n + q] (q < n0 to out0, the
+// out[q] = sum over workgroups b of part[q * nblk + b] (q < n0 to out0, the
 // rest to out1), one workgroup per output: thread t adds partials t, t + 256,
-// ... in order, then fixed-order wavefront and workgroup sums.
+// ... in order (contiguous, coalesced), then fixed-order wavefront and
+// workgroup sums.
 __global__ __launch_bounds__(256) void lpcost_finish(const double* __restrict__ part, int nblk, int n, int n0,
                                                      float* __restrict__ out0, float* __restrict__ out1) {
   __shared__ double red[4];
   const int q = blockIdx.x;
   const int t = threadIdx.x;
+  const double* row = part + (size_t)q * nblk;
   double s = 0.0;
-  for (int b = t; b < nblk; b += 256) s += part[(size_t)b * n + q];
+  for (int b = t; b < nblk; b += 256) s += row[b];
   s = wave_sum(s);
   if ((t & 63) == 0) red[t >> 6] = s;
   __syncthreads();
