@@ -25,6 +25,7 @@
 #include "../../include/prost.h"
 
 namespace prost {
+inline namespace PROST_BLOCK_NS {
 
 struct FrameArgs {
   void* U;               // K planes of ldU entries (storage type)
@@ -974,6 +975,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   float u[NR][K];
   float r[NR], wt[NR], cw[NR];
   int eix[NR];
+  bool u_pending = false;   // sequence: the registers hold an update not yet stored
   const bool pre = EXT && a.pre_mean != nullptr;   // compiled out without EXT
   const bool pupd = EXT && ks.pre_upd != 0;
   const float pinv_n = ks.pre_inv_n, pinv_s = ks.pre_inv_s;
@@ -1109,6 +1111,9 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     float* __restrict__ Uw = (float*)a.U;
     const float cm1 = ks.scal[0], sz = ks.scal[1], nu_f = ks.scal[2];
     const bool upd = ks.flag[2] != 0;
+    // a sequence keeps U in the registers: it is stored after its last frame only
+    const bool store_u = !SEQ || fi + 1 >= a.nseq;
+    if (SEQ && upd) u_pending = !store_u;
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       const int q = tid + s * kBlock;
@@ -1125,7 +1130,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             const float nv = fmaf(coef, ks.vf[j], u[s][j]);   // columns >= k stay 0 (v_j = 0)
-            if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = nv;
+            if (j < a.k && store_u) Uw[(long long)j * a.ldU + eix[s]] = nv;
             if constexpr (SEQ) u[s][j] = nv;   // the next frame of a sequence starts from it
           }
           if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
@@ -1157,6 +1162,18 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     for (int j = 0; j < K; ++j) acc = fmaf(-u[s][j], ks.yf[j], acc);
     r[s] = acc;
   }
+  }
+  if constexpr (SEQ) {   // the last frame stored nothing (rejected, or no step): store the updated tile
+    if (u_pending) {
+      float* __restrict__ Uw = (float*)a.U;
+#pragma unroll
+      for (int s = 0; s < NR; ++s)
+        if (eix[s] >= 0) {
+#pragma unroll
+          for (int j = 0; j < K; ++j)
+            if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = u[s][j];
+        }
+    }
   }
   return true;
 }
@@ -1329,6 +1346,8 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   auto weight = [&](int i) -> float {
     return ((vbits >> i) & 1u) ? (((fbits >> i) & 1u) ? om : 1.0f) : 0.f;
   };
+  static_assert(!(SEQ && NL > 0), "sequences keep register tiles only");
+  bool u_pending = false;   // sequence: the registers hold an update not yet stored
 
   for (int fi = 0;;) {   // frames of this launch; U stays in the registers between them
   if constexpr (SEQ) tid = thread_index();   // re-enters opaquely each frame (see the float32 tile)
@@ -1491,6 +1510,9 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
     uint16_t* __restrict__ Uw = (uint16_t*)a.U;
     const float cm1 = ks.scal[0], sz = ks.scal[1], nu_f = ks.scal[2];
     const bool upd = ks.flag[2] != 0;
+    // a sequence keeps U in the registers: it is stored after its last frame only
+    const bool store_u = !SEQ || fi + 1 >= a.nseq;
+    if (SEQ && upd) u_pending = !store_u;
     pin_tile(u);
 #pragma unroll
     for (int s = 0; s < NP; ++s) {
@@ -1518,7 +1540,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
           if (SEQ || j < a.k) {   // columns >= k stay 0 (v_j = 0)
             const uint32_t nw = pack_bf16_rne(fmaf(coef0, ks.vf[j], bf_lo(u[s][j])),
                                               fmaf(coef1, ks.vf[j], bf_hi(u[s][j])));
-            if (j < a.k) {
+            if (j < a.k && store_u) {
               uint16_t* col = Uw + (long long)j * a.ldU;
               if (al) {
                 st_u32(col, 2u * (unsigned)e, nw);
@@ -1637,6 +1659,31 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
     r[2 * s + 1] = has1 ? acc1 : 0.f;
   }
   }
+  if constexpr (SEQ) {   // the last frame stored nothing (rejected, or no step): store the updated tile
+    if (u_pending) {
+      uint16_t* __restrict__ Uw = (uint16_t*)a.U;
+#pragma unroll
+      for (int s = 0; s < NP; ++s) {
+        const int q0 = 2 * (tid + s * kBlock);
+        if (q0 >= ctx.nq) continue;
+        const bool has1 = (vbits >> (2 * s + 1)) & 1u;
+        const int c = q0 / ctx.npx;
+        const int e = c * a.P + ctx.p0 + (q0 - c * ctx.npx);
+        const int e1 = ((sbits >> s) & 1u) ? e + 1 + (a.P - ctx.npx) : e + 1;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+          if (j < a.k) {
+            uint16_t* col = Uw + (long long)j * a.ldU;
+            if (al) {
+              st_u32(col, 2u * (unsigned)e, u[s][j]);
+            } else {
+              st_u16(col, 2u * (unsigned)e, (uint16_t)(u[s][j] & 0xFFFFu));
+              if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(u[s][j] >> 16));
+            }
+          }
+      }
+    }
+  }
   return true;
 }
 
@@ -1670,4 +1717,5 @@ __global__ __launch_bounds__(kBlock, 2) void frame_kernel(FrameArgs a) {
   run_tile<K, NR, TS, EXT, EXT, 0, SEQ>(a, blockIdx.x, sm);
 }
 
+}  // inline namespace PROST_BLOCK_NS
 }  // namespace prost
