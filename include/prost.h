@@ -315,6 +315,11 @@ typedef struct pros_batch_config {
   int32_t sync_mode;         /* gang exchange, as in pros_set_launch */
   int32_t workgroups;        /* out: resident workgroups of the launch */
   int32_t rounds;            /* out: rounds of the schedule */
+  int32_t threads;           /* threads per workgroup: 512 (0 selects it), or 256 with
+                                register budget 128 and workgroups_per_cu 2 (two
+                                workgroups of different streams share a CU, so one
+                                computes while the other waits on an exchange;
+                                k class 15, default features) */
 } pros_batch_config;
 
 /* Create a batch of n streams (per_stream[0..n-1]; reorth_every must be 0,

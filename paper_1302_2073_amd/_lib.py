@@ -64,7 +64,7 @@ class pros_launch_info(C.Structure):
 class pros_batch_config(C.Structure):
     _fields_ = [("register_budget", C.c_int32), ("workgroups_per_cu", C.c_int32), ("tile_scale", C.c_double),
                 ("strategy", C.c_int32), ("sync_mode", C.c_int32), ("workgroups", C.c_int32),
-                ("rounds", C.c_int32)]
+                ("rounds", C.c_int32), ("threads", C.c_int32)]
 
 
 class ProstError(RuntimeError):

@@ -173,9 +173,9 @@ void prost_host::free_handle(pros_handle* h) {
   delete h;
 }
 
-int prost_host::tile_pixels(int storage, int NR, int channels, double scale) {
-  const int full = prost::kBlock * NR / channels;
-  int tpw = (int)std::floor(prost::kBlock * NR * scale / channels);
+int prost_host::tile_pixels(int storage, int NR, int channels, double scale, int threads) {
+  const int full = threads * NR / channels;
+  int tpw = (int)std::floor(threads * NR * scale / channels);
   tpw = std::max(1, std::min(tpw, full));
   if (storage == PROS_BF16 && tpw > 1) tpw &= ~1;
   return tpw;

@@ -32,6 +32,12 @@ const void* batch_kernel_seq_k12(int);
 const void* batch_kernel_seq_k15(int);
 const void* batch_kernel_seq_k16(int);
 
+const void* batch256_kernel_k15(int);
+const void* batch256_kernel_seq_k15(int);
+
+const void* batch256_kernel_ptr(int bf16, int K) { return K == 15 ? batch256_kernel_k15(bf16) : nullptr; }
+const void* batch256_kernel_seq_ptr(int bf16, int K) { return K == 15 ? batch256_kernel_seq_k15(bf16) : nullptr; }
+
 const void* batch_kernel_seq_ptr(int bf16, int K) {
   switch (K) {
     case 2: return batch_kernel_seq_k2(bf16);
@@ -81,6 +87,7 @@ struct pros_batch {
   // launch
   int budget = 128;
   int wg_per_cu = 2;
+  int threads = prost::kBlock;   // threads per workgroup of the launch (512, or the 256-thread build)
   int nwg = 0;
   int rounds = 0;
   int strategy = 0;
@@ -173,22 +180,31 @@ static pros_status build_schedule(pros_batch* b) {
 }
 
 // (Re)create the per-stream tile configuration, descriptors and schedule.
-static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy, int sync_mode) {
+static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double tile_scale, int strategy, int sync_mode,
+                             int threads) {
   bool ext = false;
   for (pros_handle* h : b->hs) {
     ext = ext || (h->pre_mean != nullptr);
   }
-  const void* f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget, ext);
-  if (!f) return fail(PROS_EUNSUPPORTED, "no batch kernel for k class %d", b->kclass);
+  if (threads != prost::kBlock && threads != 256) return fail(PROS_EINVAL, "threads must be 256 or %d", prost::kBlock);
+  const void* f = nullptr;
+  if (threads == 256) {
+    if (budget != 128 || ext || wg_per_cu != 2)
+      return fail(PROS_EUNSUPPORTED, "256-thread workgroups: register budget 128, two per CU, default features");
+    f = prost::batch256_kernel_ptr(b->storage == PROS_BF16, b->kclass);
+  } else {
+    f = prost::batch_kernel_ptr(b->storage == PROS_BF16, b->kclass, budget, ext);
+  }
+  if (!f) return fail(PROS_EUNSUPPORTED, "no batch kernel for k class %d (%d threads)", b->kclass, threads);
   int occ = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, prost::kBlock, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, threads, 0);
   if (e != hipSuccess) return fail(PROS_EHIP, "occupancy query: %s", hipGetErrorString(e));
   if (occ < 1) return fail(PROS_EUNSUPPORTED, "batch kernel cannot be resident");
   const int wpc = std::min(occ, wg_per_cu);
   const int nwg = wpc * b->num_cu;
   for (pros_handle* h : b->hs) {
     const int NR = prost::batch_rows(b->storage == PROS_BF16, budget, b->kclass);
-    const int tpw = prost_host::tile_pixels(b->storage, NR, h->C, tile_scale);
+    const int tpw = prost_host::tile_pixels(b->storage, NR, h->C, tile_scale, threads);
     const int G = (h->P + tpw - 1) / tpw;
     if (G > nwg) return fail(PROS_EUNSUPPORTED, "a %dx%dx%d stream at k=%d needs %d workgroups (> %d)",
                              h->prm.width, h->prm.height, h->C, h->k, G, nwg);
@@ -206,6 +222,7 @@ static pros_status configure(pros_batch* b, int budget, int wg_per_cu, double ti
     if (rs != PROS_OK) return rs;
   }
   b->budget = budget;
+  b->threads = threads;
   b->wg_per_cu = wpc;
   b->nwg = nwg;
   b->kfn = f;
@@ -242,8 +259,8 @@ static pros_status launch(pros_batch* b, hipStream_t on, const void* fn = nullpt
   int rounds = b->rounds;
   void* args[] = {&d, &it, &rounds};
   if (!fn) fn = b->kfn;
-  hipError_t e = b->coop ? hipLaunchCooperativeKernel(fn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on)
-                         : hipLaunchKernel(fn, dim3(b->nwg), dim3(prost::kBlock), args, 0, on);
+  hipError_t e = b->coop ? hipLaunchCooperativeKernel(fn, dim3(b->nwg), dim3(b->threads), args, 0, on)
+                         : hipLaunchKernel(fn, dim3(b->nwg), dim3(b->threads), args, 0, on);
   if (e != hipSuccess) {
     b->broken = true;
     return fail(PROS_EHIP, "batch kernel launch: %s", hipGetErrorString(e));
@@ -349,7 +366,7 @@ pros_status pros_batch_init(const pros_params* per_stream, int32_t n, void* hip_
     free_batch(b);
     return fail(PROS_ENOMEM, "batch tables: %s", hipGetErrorString(e));
   }
-  pros_status st = configure(b, 128, 2, 1.0, 0, 2);   // sync mode 2 suits every stream
+  pros_status st = configure(b, 128, 2, 1.0, 0, 2, prost::kBlock);   // sync mode 2 suits every stream
   if (st != PROS_OK) {
     free_batch(b);
     return st;
@@ -472,7 +489,8 @@ pros_status pros_batch_track_steps(pros_batch* b, int32_t steps) {
     if (!h->state_set) return fail(PROS_ESTATE, "set every stream's U before the first batch step");
     filtered = filtered || h->prm.weights_from_filtered;
   }
-  const void* fn = prost::batch_kernel_seq_ptr(b->storage == PROS_BF16, b->kclass);
+  const void* fn = (b->threads == 256) ? prost::batch256_kernel_seq_ptr(b->storage == PROS_BF16, b->kclass)
+                                       : prost::batch_kernel_seq_ptr(b->storage == PROS_BF16, b->kclass);
   if (!fn || b->budget != 128 || b->ext || filtered) {   // one launch per step
     for (int i = 0; i < steps; ++i) {
       st = pros_batch_track(b);
@@ -580,6 +598,7 @@ pros_status pros_batch_get_config(pros_batch* b, pros_batch_config* out) {
   out->sync_mode = b->sync_mode;
   out->workgroups = b->nwg;
   out->rounds = b->rounds;
+  out->threads = b->threads;
   return PROS_OK;
 }
 
@@ -595,7 +614,8 @@ pros_status pros_batch_configure(pros_batch* b, const pros_batch_config* cfg) {
   if (cfg->sync_mode < 0 || cfg->sync_mode > 3) return fail(PROS_EINVAL, "sync_mode must be 0..3");
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return fail(PROS_EHIP, "sync: %s", hipGetErrorString(e));
-  return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy, cfg->sync_mode);
+  return configure(b, cfg->register_budget, cfg->workgroups_per_cu, cfg->tile_scale, cfg->strategy, cfg->sync_mode,
+                   cfg->threads == 0 ? prost::kBlock : cfg->threads);
 }
 
 // Device-side copy of every stream's state, so that tuning leaves the
@@ -674,12 +694,14 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
   pros_batch_config bc{};
   const double scales[] = {1.0, 0.75, 0.5};
   const int wpcs[] = {1, 2};
+  const int thr[] = {prost::kBlock, 256};
   for (int sm = 0; sm < 4; ++sm)
+  for (int threads : thr)
   for (int budget : kBudgets)
     for (int wpc : wpcs)
       for (double sc : scales)
         for (int strat = 0; strat < 2; ++strat) {
-          if (configure(b, budget, wpc, sc, strat, sm) != PROS_OK) continue;   // does not fit
+          if (configure(b, budget, wpc, sc, strat, sm, threads) != PROS_OK) continue;   // does not fit
           if (b->wg_per_cu != wpc) continue;                               // duplicate of a smaller grid
           st = launch(b, b->stream);                                        // warm-up
           for (int i = 0; i < steps && st == PROS_OK; ++i) {
@@ -709,6 +731,7 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
             bc.tile_scale = sc;
             bc.strategy = strat;
             bc.sync_mode = sm;
+            bc.threads = threads;
           }
           st = snapshot(b, sn, true);
           if (st != PROS_OK) break;
@@ -718,7 +741,7 @@ extern "C" pros_status pros_batch_tune(pros_batch* b, int32_t steps, pros_batch_
   b->use_graph = graph;
   if (st != PROS_OK) return st;
   if (bestt >= 1e300) return fail(PROS_EUNSUPPORTED, "no candidate configuration fits");
-  st = configure(b, bc.register_budget, bc.workgroups_per_cu, bc.tile_scale, bc.strategy, bc.sync_mode);
+  st = configure(b, bc.register_budget, bc.workgroups_per_cu, bc.tile_scale, bc.strategy, bc.sync_mode, bc.threads);
   if (st != PROS_OK) return st;
   if (best) pros_batch_get_config(b, best);
   if (best_ms) *best_ms = bestt;

@@ -17,6 +17,7 @@
 #include "prost_frame.hpp"
 
 namespace prost {
+inline namespace PROST_BLOCK_NS {
 
 struct BatchItem {
   int stream;   // -1: idle slot
@@ -104,9 +105,16 @@ const void* batch_kernel_lds() {
   return (const void*)&batch_kernel<uint16_t, K, 2 * batch_lds_np(K), false, NL>;
 }
 
+}  // inline namespace PROST_BLOCK_NS
+
 // Kernel for (storage, class K, budget, optional features compiled in);
 // nullptr if not built.
 const void* batch_kernel_ptr(int storage_bf16, int K, int budget, bool ext);
 const void* batch_kernel_seq_ptr(int storage_bf16, int K);
+// The 256-thread build (two workgroups per CU) at register budget 128 with
+// the default features: one step per launch, and the multi-step form;
+// nullptr if not built for (storage, class K).
+const void* batch256_kernel_ptr(int storage_bf16, int K);
+const void* batch256_kernel_seq_ptr(int storage_bf16, int K);
 
 }  // namespace prost

@@ -11,9 +11,27 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace prost {
+// Threads per workgroup of the persistent kernels: 512 (8 wavefronts, one
+// workgroup per CU) by default; a translation unit that defines PROST_BLOCK
+// as 256 before including this header builds its kernels for 256-thread
+// workgroups (4 wavefronts, two workgroups of different streams per CU).
+// Everything below lives in a namespace named after the block size, so the
+// two builds never share a definition.
+#ifndef PROST_BLOCK
+#define PROST_BLOCK 512
+#endif
+#if PROST_BLOCK == 512
+#define PROST_BLOCK_NS b512
+#elif PROST_BLOCK == 256
+#define PROST_BLOCK_NS b256
+#else
+#error "PROST_BLOCK must be 256 or 512"
+#endif
 
-constexpr int kBlock = 512;            // threads per workgroup (8 wavefronts, one workgroup per CU)
+namespace prost {
+inline namespace PROST_BLOCK_NS {
+
+constexpr int kBlock = PROST_BLOCK;    // threads per workgroup
 constexpr int kWaves = kBlock / 64;    // wavefronts per workgroup
 constexpr int kMaxK = 16;
 constexpr int kSlot = 32;              // doubles per workgroup partial slot
@@ -189,4 +207,5 @@ __device__ __forceinline__ bool gang_barrier(unsigned* sync, unsigned target, lo
   return s_ctl[0] != 0;
 }
 
+}  // inline namespace PROST_BLOCK_NS
 }  // namespace prost

@@ -7,6 +7,7 @@
 #include "prost_frame.hpp"
 
 namespace prost {
+inline namespace PROST_BLOCK_NS {
 
 template <typename TS, int KK, bool EXT, bool SEQ = false>
 const void* frame_kernel_nr(int NR) {
@@ -32,6 +33,7 @@ const void* frame_kernel_nr(int NR) {
   }
 }
 
+}  // inline namespace PROST_BLOCK_NS
 }  // namespace prost
 
 #define PROST_FRAME_GROUP(name, TS, K0)                                                   \

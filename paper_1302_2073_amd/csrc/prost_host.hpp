@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/prost.h"
+#include "prost_device.hpp"
 
 struct pros_handle {
   pros_params prm;
@@ -45,7 +46,11 @@ struct pros_handle {
   pros_status broken_status = PROS_OK;
 };
 
-namespace prost { struct FrameArgs; }
+namespace prost {
+inline namespace PROST_BLOCK_NS {
+struct FrameArgs;
+}
+}  // namespace prost
 
 namespace prost_host {
 double effective_delta(const pros_params& p);
@@ -64,7 +69,7 @@ pros_status refresh_mask(pros_handle* h);
 // Pixels per workgroup tile for NR register rows per thread (a fraction
 // `scale` of the full tile); even for bfloat16 storage so that row pairs
 // stay inside one colour plane.
-int tile_pixels(int storage, int NR, int channels, double scale);
+int tile_pixels(int storage, int NR, int channels, double scale, int threads = prost::kBlock);
 // bfloat16 row pairs can be accessed as aligned 32-bit words in U (frame
 // alignment is checked separately).
 bool pair_layout(const pros_handle* h);

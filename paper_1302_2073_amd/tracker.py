@@ -362,10 +362,11 @@ class BatchTracker:
         L.check(L.lib().pros_batch_get_config(self._b, C.byref(c)))
         return dict(register_budget=c.register_budget, workgroups_per_cu=c.workgroups_per_cu,
                     tile_scale=c.tile_scale, strategy=c.strategy, sync_mode=c.sync_mode,
-                    workgroups=c.workgroups, rounds=c.rounds)
+                    workgroups=c.workgroups, rounds=c.rounds, threads=c.threads)
 
-    def configure(self, register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0, sync_mode=2):
-        c = L.pros_batch_config(register_budget, workgroups_per_cu, tile_scale, strategy, sync_mode, 0, 0)
+    def configure(self, register_budget=128, workgroups_per_cu=2, tile_scale=1.0, strategy=0, sync_mode=2,
+                  threads=512):
+        c = L.pros_batch_config(register_budget, workgroups_per_cu, tile_scale, strategy, sync_mode, 0, 0, threads)
         L.check(L.lib().pros_batch_configure(self._b, C.byref(c)))
 
     def tune(self, steps=5, cache=None):
@@ -390,7 +391,8 @@ class BatchTracker:
         ms = C.c_double()
         L.check(L.lib().pros_batch_tune(self._b, int(steps), C.byref(best), C.byref(ms)))
         rec = dict(config=dict(register_budget=best.register_budget, workgroups_per_cu=best.workgroups_per_cu,
-                               tile_scale=best.tile_scale, strategy=best.strategy, sync_mode=best.sync_mode),
+                               tile_scale=best.tile_scale, strategy=best.strategy, sync_mode=best.sync_mode,
+                               threads=best.threads),
                    ms_per_step=ms.value, workgroups=best.workgroups, rounds=best.rounds)
         if path:
             db = {}

@@ -218,8 +218,9 @@ def _check_vga_bf16_step(bt, s, start, x, mu, prm=None):
     assert np.array_equal(bt.mask(s), O.median3x3(l1, prm.height, prm.width))
 
 
-@pytest.mark.parametrize("nstreams,budget,n0", [(2, 0, 0), (3, 192, 0), (2, 0, 150)])
-def test_batch_bf16_vga_streams_share_a_round(nstreams, budget, n0):
+@pytest.mark.parametrize("nstreams,budget,n0,threads", [(2, 0, 0, 512), (3, 192, 0, 512), (2, 0, 150, 512),
+                                                         (2, 128, 0, 256), (2, 128, 150, 256)])
+def test_batch_bf16_vga_streams_share_a_round(nstreams, budget, n0, threads):
     """640x480x3 k=15 streams in bfloat16 (the benchmark's streams): the
     row-pair tiles halve each gang, so two frames run side by side in one
     round, and three with the LDS form; each stream matches its own oracle
@@ -230,9 +231,12 @@ def test_batch_bf16_vga_streams_share_a_round(nstreams, budget, n0):
     svs = [V.SyntheticVideo(w.video) for w in wls]
     specs = [dict(width=640, height=480, channels=3, k=15, mu=w.mu) for w in wls]
     with BatchTracker(specs, storage="bf16") as bt:
-        if budget:
+        if threads == 256:   # two 256-thread workgroups per CU, one of each stream
+            bt.configure(register_budget=budget, workgroups_per_cu=2, threads=256)
+        elif budget:
             bt.configure(register_budget=budget, workgroups_per_cu=1)
         cfg = bt.config()
+        assert cfg["threads"] == threads
         say("  config", cfg)
         assert cfg["rounds"] == 1
         frames = [[_vga_bf16_frame(sv, 0)] for sv in svs]
@@ -392,6 +396,45 @@ def test_multi_step_launch_is_bitwise_equal(storage, budget):
             res.append([bt.get_state(s) for s in range(len(streams))] +
                        [bt.mask(s) for s in range(len(streams))])
     say(f"  {storage}: n = {[int(st[3]) for st in res[1][:len(streams)]]}")
+    for sa, sb in zip(res[0], res[1]):
+        if isinstance(sa, tuple):
+            for a, b in zip(sa, sb):
+                np.testing.assert_array_equal(a, b)
+        else:
+            np.testing.assert_array_equal(sa, sb)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_256_thread_workgroups(storage):
+    """Two 256-thread workgroups per CU (register budget 128, k class 15):
+    every stream of an uneven batch matches its oracle step, and one 4-step
+    launch equals four single steps bit for bit."""
+    from paper_1302_2073_amd.tracker import BatchTracker
+    streams = _streams(SHAPES[:3])
+    res = []
+    for multi in (False, True):
+        with BatchTracker(_specs(streams), storage=storage) as bt:
+            bt.configure(register_budget=128, workgroups_per_cu=2, threads=256)
+            cfg = bt.config()
+            say("  config", cfg)
+            assert cfg["threads"] == 256 and cfg["workgroups"] >= 2 * 256 - 16
+            bt.set_frames(_frames_tensor(streams, 4, 4, storage))
+            starts = _load(bt, streams)
+            if multi:
+                bt.steps(4)
+            else:
+                bt.step()
+                assert bt.sync() == 0
+                for s, (sv, prm, st) in enumerate(streams):
+                    if storage == "f32":
+                        _check_stream(bt, s, prm, starts[s], f32(sv.frame(4)))
+                    else:
+                        _check_vga_bf16_step(bt, s, starts[s], _rne(sv.frame(4)), prm.mu, prm)
+                for _ in range(3):
+                    bt.step()
+            assert bt.sync() == 0
+            res.append([bt.get_state(s) for s in range(len(streams))] +
+                       [bt.mask(s) for s in range(len(streams))])
     for sa, sb in zip(res[0], res[1]):
         if isinstance(sa, tuple):
             for a, b in zip(sa, sb):
