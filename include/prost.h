@@ -174,10 +174,16 @@ PROS_API pros_status pros_validate(const pros_params* prm);
  * pros_random_subspace, rounded to the storage type), y = 0, labels = mask
  * = 0, frame counter 0, so frames can be tracked right away;
  * pros_set_state replaces any of it.  On error *out is NULL.
- * PROS_EUNSUPPORTED, before any allocation, when the frame needs more
- * workgroups than the device keeps resident (every workgroup holds its tile
- * of U in registers for the whole frame): on MI355X at k = 15, frames above
- * 349 440 pixels x 3 channels in FP32 storage, 698 880 in BF16. */
+ * Frames whose tiles of U fit the resident workgroups' registers (on
+ * MI355X at k = 15: up to 349 440 pixels x 3 channels in FP32 storage,
+ * 698 880 in BF16) run the persistent frame kernel, U kept on chip for the
+ * whole frame.  Larger frames run the streamed form: the same arithmetic,
+ * one launch per dependent pass, U and the frame read from HBM in every
+ * pass (pros_get_launch_info reports sync_mode -1); it has the default
+ * features only, so pre-processing (preprocess = 1) or the IRLS step
+ * (ysolve = 2) with such a frame gives PROS_EUNSUPPORTED, before any
+ * allocation, as do pros_set_launch, pros_set_curvature and
+ * pros_set_score_output on a streamed handle. */
 PROS_API pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out);
 
 /* Release all device memory of the handle (waits for its stream).  NULL is
@@ -443,7 +449,9 @@ PROS_API pros_status pros_lpcost_bwd_noalloc(const float* U, const float* Y, con
  * workgroup and broadcast back, 2 = the same in two levels (groups of
  * tiles t = x mod 8; every workgroup reads the 8 group sums),
  * 3 = every workgroup reads all tagged partials (one hop, G^2 reads).
- * Results agree to float64 rounding.
+ * Results agree to float64 rounding.  rows_per_thread = -1 selects the
+ * streamed form (one launch per pass, U read from HBM every pass; see
+ * pros_init) for any frame size; sync_mode is then ignored.
  * Synchronises. */
 PROS_API pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode);
 

@@ -167,7 +167,7 @@ pros_status pros_validate(const pros_params* p) {
 void prost_host::free_handle(pros_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->U, h->xstage, h->lab, h->mask, h->y, h->nframe, h->stats, h->part, h->sync, h->reorth_ws,
-                  h->pre_mean, h->pre_m2, h->pre_stat, (void*)h->seq};
+                  h->pre_mean, h->pre_m2, h->pre_stat, (void*)h->seq, h->stream_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete h;
@@ -214,6 +214,7 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
   const void* best = nullptr;
   int bestNR = 0, bestG = 0, bestT = 0;
   const bool ext = h->prm.preprocess != 0 || h->score != nullptr || wide_exchange(h);
+  h->streamed = false;
   if (force_nr == 0) {
     for (int NR : nrs) {
       const void* f = (h->prm.storage == PROS_BF16) ? prost::frame_kernel_bf16(h->k, NR, ext)
@@ -261,9 +262,21 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
     best = f; bestNR = NR; bestG = (int)G; bestT = tpw;
     if (G <= h->num_cu) break;                      // smallest tile at one workgroup per CU
   }
-  if (!best)
-    return fail(PROS_EUNSUPPORTED, "frame of %d pixels x %d channels at k=%d does not fit the device's resident workgroups",
-                h->P, h->C, h->k);
+  if (!best) {
+    // no resident gang holds the frame's register tiles: stream every pass
+    // (default features only; the optional features need the tile kernels)
+    if (force_nr > 0 || ext)
+      return fail(PROS_EUNSUPPORTED,
+                  "frame of %d pixels x %d channels at k=%d does not fit the device's resident workgroups%s", h->P,
+                  h->C, h->k, ext ? " (its streamed form has no pre-processing, scores, IRLS or curvature schedule 1)" : "");
+    h->streamed = true;
+    h->kfn = nullptr;
+    h->NR = 0;
+    h->G = 1;
+    h->tpw = h->P;
+    return PROS_OK;
+  }
+  h->streamed = false;
   h->kfn = best;
   h->NR = bestNR;
   h->G = bestG;
@@ -340,6 +353,10 @@ pros_status prost_host::create_handle(const pros_params* prm, hipStream_t stream
   // epoch-tagged exchange slots must start with tag 0 (the first exchange uses 1)
   INIT_TRY(hipMemsetAsync(h->part, 0, prost_host::part_bytes(h, h->G),
                           h->stream));
+  if (h->streamed) {
+    st = prost_stream_alloc(h);
+    if (st != PROS_OK) return bail(st);
+  }
   INIT_TRY(hipStreamSynchronize(h->stream));
 #undef INIT_TRY
   *out = h;
@@ -582,6 +599,21 @@ static pros_status launch_frames(pros_handle* h, FrameArgs& a, const void* fn) {
   return PROS_OK;
 }
 
+// One frame of the streamed path (weights from the filtered mask need the
+// previous frame's median first), then a re-orthonormalisation when due.
+static pros_status stream_frame(pros_handle* h, const FrameArgs& a) {
+  if (h->prm.weights_from_filtered) {
+    pros_status st = prost_host::refresh_mask(h);
+    if (st != PROS_OK) return st;
+  }
+  pros_status st = prost_stream_frame(h, a);
+  if (st != PROS_OK) return st;
+  h->submitted += 1;
+  h->mask_stale = true;
+  if (h->prm.reorth_every > 0 && h->submitted % h->prm.reorth_every == 0) return prost_reorth_launch(h);
+  return PROS_OK;
+}
+
 pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, int32_t on_device) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
@@ -626,6 +658,7 @@ pros_status pros_track_frame(pros_handle* h, const void* frame, int32_t dtype, i
     x = h->xstage;
   }
   FrameArgs a = make_args(h, x);
+  if (h->streamed) return stream_frame(h, a);
   return launch_frames(h, a, h->kfn);
 }
 
@@ -640,7 +673,7 @@ pros_status pros_track_frames(pros_handle* h, const void* const* frames, int32_t
   // frames that depend on more than the tile's own state between frames
   // (filtered-mask weights, pre-processing statistics, scores, the wide
   // exchange) run one launch each
-  const void* fseq = prost::frame_kernel_seq(h->prm.storage == PROS_BF16, h->k, h->NR);
+  const void* fseq = h->streamed ? nullptr : prost::frame_kernel_seq(h->prm.storage == PROS_BF16, h->k, h->NR);
   const bool seq_ok = fseq && !h->prm.weights_from_filtered && h->pre_mean == nullptr && h->score == nullptr &&
                       !wide_exchange(h);
   if (!seq_ok) {
@@ -700,6 +733,16 @@ pros_status pros_get_stats(pros_handle* h, pros_stats* out) {
 
 pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
   if (!h || !out) return fail(PROS_EINVAL, "NULL argument");
+  if (h->streamed) {   // one launch per pass: no register tile, no gang exchange
+    out->workgroups = h->stream_blocks;
+    out->threads = 256;
+    out->rows_per_thread = 0;
+    out->pixels_per_wg = 256;
+    out->barriers_per_frame = 0;
+    out->sync_mode = -1;
+    out->curvature = 0;
+    return PROS_OK;
+  }
   out->workgroups = h->G;
   out->threads = prost::kBlock;
   out->rows_per_thread = h->NR;
@@ -722,6 +765,17 @@ pros_status prost_host::reset_exchange(pros_handle* h) {
 pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t sync_mode) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
+  if (rows_per_thread == -1) {   // the streamed form, whatever the frame's size
+    if (h->prm.preprocess || h->score || wide_exchange(h))
+      return fail(PROS_EUNSUPPORTED, "the streamed form has no pre-processing, scores, IRLS or curvature schedule 1");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (!h->stream_ws) {
+      st = prost_stream_alloc(h);
+      if (st != PROS_OK) return st;
+    }
+    h->streamed = true;
+    return PROS_OK;
+  }
   if (sync_mode < 0 || sync_mode > 3) return fail(PROS_EINVAL, "sync_mode must be 0..3");
   if (sync_mode == 0 && wide_exchange(h))
     return fail(PROS_EINVAL, "the wide exchange (IRLS, curvature schedule 1) needs a tagged exchange (sync_mode 1..3)");
@@ -757,6 +811,7 @@ pros_status pros_set_dispatch(pros_handle* h, int32_t cooperative) {
 pros_status pros_set_curvature(pros_handle* h, int32_t schedule) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
+  if (h->streamed) return fail(PROS_EUNSUPPORTED, "the frame is streamed (it does not fit resident register tiles)");
   if (schedule != 0 && schedule != 1) return fail(PROS_EINVAL, "curvature schedule must be 0 or 1");
   if (schedule == 1 && h->prm.storage != PROS_F32)
     return fail(PROS_EUNSUPPORTED, "curvature schedule 1 needs float32 storage");
@@ -784,6 +839,7 @@ pros_status pros_set_curvature(pros_handle* h, int32_t schedule) {
 pros_status pros_set_score_output(pros_handle* h, float* device_scores) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
+  if (h->streamed) return fail(PROS_EUNSUPPORTED, "the frame is streamed (it does not fit resident register tiles)");
   HIP_TRY(hipStreamSynchronize(h->stream));
   float* old = h->score;
   h->score = device_scores;

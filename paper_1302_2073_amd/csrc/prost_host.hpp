@@ -39,6 +39,10 @@ struct pros_handle {
   long long* trace = nullptr;   // optional per-tile timestamps (diagnostics)
   bool mask_stale = true;       // mask not yet computed from the latest labels
   long long timeout_ticks = 0;
+  // frames too large for a resident gang: every pass streams U (prost_stream.hip)
+  bool streamed = false;
+  void* stream_ws = nullptr;    // k-space state, per-entry w c and eta, per-workgroup partials
+  int stream_blocks = 0;        // workgroups of a streamed pass
   // host bookkeeping
   long long submitted = 0;
   bool state_set = false;
@@ -88,3 +92,6 @@ pros_status prost_reorth_launch(pros_handle* h);
 pros_status prost_random_subspace(unsigned long long seed, uint32_t stream_index, long long m, int k, double* A,
                                   hipStream_t st);
 pros_status prost_init_subspace(pros_handle* h, unsigned long long seed, uint32_t stream_index);
+// The streamed path for frames whose register tiles do not fit the device.
+pros_status prost_stream_alloc(pros_handle* h);
+pros_status prost_stream_frame(pros_handle* h, const prost::FrameArgs& a);

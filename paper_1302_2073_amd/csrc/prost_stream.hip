@@ -1,0 +1,478 @@
+// Frames too large for a resident gang of register tiles (Sec. 3.3, Steps
+// 1-3, with the step-size rule of Sec. 3.4): the same per-frame arithmetic as
+// the frame kernel, but every dependent pass streams U and the frame from
+// HBM, one launch per pass, with the k-space work between passes in one
+// small workgroup.  Per frame and CG step (Step 1):
+//   grad pass:   r = x - U y, phi, c; w c stored per entry; partials of
+//                U^T (w phi'(r)) and sum w phi(r)
+//   direction:   fixed-order sum of the partials, PR+ direction d
+//   curvature:   partials of sum w c (u . d)^2 (the majoriser's d^T H d)
+//   advance:     alpha = -g.d / d^T H d, y += alpha d
+// then (Step 2) the eta pass (eta = -w phi'(r) stored per entry, partials of
+// U^T eta, ||eta||^2 and the final cost), the geodesic scalars, and one pass
+// that updates U and labels every pixel (Step 3).  Reductions: float32 per
+// thread, float64 per workgroup and across workgroups in a fixed order, so
+// results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "../../include/prost.h"
+#include "prost_frame.hpp"
+#include "prost_host.hpp"
+
+namespace prost {
+
+constexpr int kStBlock = 256;           // pixels per workgroup of a pass: one thread per pixel, all channels
+constexpr int kStWaves = kStBlock / 64;
+constexpr int kStRed = 1024;            // threads of the reducing (k-space) kernels
+constexpr int kStL = kMaxK + 2;         // partials per workgroup: up to K values and two scalars
+
+// k-space state of the frame being streamed (device memory, one per handle).
+struct StreamKS {
+  double y[kMaxK], g[kMaxK], gp[kMaxK], d[kMaxK], dp[kMaxK], a[kMaxK];
+  double gd;
+  float yf[kMaxK], yl[kMaxK];   // y as float32 plus its float32 remainder: r = x - U yf - U yl
+  float df[kMaxK], vf[kMaxK], af[kMaxK];
+  float cm1, sz, nu;
+  int stop, bad, upd, steps, restarts;
+};
+
+// Workgroup sum of L float partials per thread into part[blk * kStL + q]
+// (float64; fixed order: wavefront reduce-scatter, then wavefronts in order).
+template <int L>
+__device__ __forceinline__ void st_block_partials(float (&acc)[L], double (*red)[kStL], double* __restrict__ part) {
+  const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
+  int comp;
+  const float v = wave_reduce_scatter<L>(acc, comp);
+  constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
+  if ((lane & kLowMask) == 0 && comp < L) red[wv][comp] = (double)v;
+  __syncthreads();
+  if (tid < L) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kStWaves; ++w) s += red[w][tid];
+    part[(size_t)blockIdx.x * kStL + tid] = s;
+  }
+}
+
+// Sum over the nblk workgroups' partials of the first L values, into out[]
+// (shared): thread t adds value t % 32 of workgroups t / 32, t / 32 + 32, ...
+// in order, then the 32 group sums of each value are added in order.
+template <int L>
+__device__ __forceinline__ void st_sum_partials(const double* __restrict__ part, int nblk, double (*grp)[32],
+                                                double* out) {
+  const int t = threadIdx.x, q = t & 31, g = t >> 5;
+  double s = 0.0;
+  if (q < L)
+    for (int b = g; b < nblk; b += kStRed / 32) s += part[(size_t)b * kStL + q];
+  grp[g][q] = s;
+  __syncthreads();
+  if (t < L) {
+    double v = 0.0;
+    for (int r = 0; r < kStRed / 32; ++r) v += grp[r][t];
+    out[t] = v;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ float st_weight(const FrameArgs& a, int p) {
+  const uint8_t* src = a.weights_from_filtered ? a.mask : a.lab;
+  return src[p] ? a.omega : 1.0f;
+}
+
+// y (float64) as the float32 pair the passes use: every pass recomputes
+// r = x - U y from the frame, and the remainder keeps that residual as
+// accurate as the float64 y (near a fit the gradient is small and a
+// float32-rounded y would dominate its error).
+__device__ __forceinline__ void st_set_y(StreamKS* ks, int j, double yv) {
+  ks->y[j] = yv;
+  const float hi = (float)yv;
+  ks->yf[j] = hi;
+  ks->yl[j] = (float)(yv - (double)hi);
+}
+
+// Frame start: y from the handle, flags cleared.
+__global__ void st_begin(FrameArgs a, StreamKS* ks) {
+  const int t = threadIdx.x;
+  if (t < kMaxK) st_set_y(ks, t, (t < a.k) ? a.y[t] : 0.0);
+  if (t == 0) {
+    ks->stop = ks->bad = ks->upd = ks->steps = ks->restarts = 0;
+    a.stats->frame = *a.nframe;
+  }
+}
+
+// Step 1 gradient pass at the current y (float32 per thread, as the frame kernel).
+template <int KC, typename TS>
+__global__ __launch_bounds__(kStBlock) void st_grad(FrameArgs a, const StreamKS* __restrict__ ks, float* __restrict__ wc,
+                                                    double* __restrict__ part) {
+  if (ks->stop || ks->bad) return;
+  __shared__ float ys[KC], yl[KC];
+  __shared__ double red[kStWaves][kStL];
+  const int tid = thread_index();
+  if (tid < KC) {
+    ys[tid] = ks->yf[tid];
+    yl[tid] = ks->yl[tid];
+  }
+  __syncthreads();
+  const int p = blockIdx.x * kStBlock + tid;
+  const bool valid = p < a.P;
+  const float wt = valid ? st_weight(a, p) : 0.f;
+  const TS* __restrict__ U = (const TS*)a.U;
+  const TS* __restrict__ X = (const TS*)a.x;
+  float acc[KC + 1];
+#pragma unroll
+  for (int j = 0; j <= KC; ++j) acc[j] = 0.f;
+  if (valid)
+    for (int c = 0; c < a.C; ++c) {
+      const long long e = (long long)c * a.P + p;
+      float u[KC];
+      float r = ld_elem(X, e), rl = 0.f;
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        u[j] = (j < a.k) ? ld_elem(U, (long long)j * a.ldU + e) : 0.f;
+        r = fmaf(-u[j], ys[j], r);
+        rl = fmaf(-u[j], yl[j], rl);
+      }
+      r += rl;
+      float phi, cc;
+      cost_eval(r, a.cp, phi, cc);
+      const float w_c = wt * cc;
+      wc[e] = w_c;
+      const float wd = w_c * r;                 // w phi'(r)
+      acc[KC] = fmaf(wt, phi, acc[KC]);
+#pragma unroll
+      for (int j = 0; j < KC; ++j) acc[j] = fmaf(wd, u[j], acc[j]);
+    }
+  st_block_partials<KC + 1>(acc, red, part);
+}
+
+// Reduced gradient and cost -> PR+ direction (the frame kernel's k-space step).
+template <int KC>
+__global__ __launch_bounds__(kStRed) void st_direction(FrameArgs a, StreamKS* ks, const double* __restrict__ part,
+                                                       int nblk, int it) {
+  if (ks->stop || ks->bad) return;
+  __shared__ double grp[kStRed / 32][32];
+  __shared__ double tot[32];
+  st_sum_partials<KC + 1>(part, nblk, grp, tot);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const double g = (lane < a.k) ? -tot[lane] : 0.0;
+    const double f = tot[KC];
+    const double gg = row16_sum(g * g);
+    int stop = 0, bad = 0;
+    if (it == 0 && !(isfinite(f) && isfinite(gg))) stop = bad = 1;
+    if (gg == 0.0) stop = 1;
+    double beta = 0.0, dj = -g;
+    if (!stop && it > 0 && a.ysolve == 0) {
+      const double gpv = (lane < a.k) ? ks->gp[lane] : 0.0;
+      const double num = row16_sum(g * (g - gpv));
+      const double den = row16_sum(gpv * gpv);
+      beta = fmax(0.0, num / den);
+      const double dpv = (lane < a.k) ? ks->dp[lane] : 0.0;
+      dj = -g + beta * dpv;
+      if (row16_sum(g * dj) >= 0.0) {
+        dj = -g;
+        if (lane == 0) ++ks->restarts;
+      }
+    }
+    const double gd = row16_sum(g * dj);
+    if (lane < kMaxK) {
+      ks->d[lane] = (lane < a.k) ? dj : 0.0;
+      ks->df[lane] = (lane < a.k) ? (float)dj : 0.f;
+      ks->gp[lane] = (lane < a.k) ? g : 0.0;
+    }
+    if (lane == 0) {
+      a.stats->f[it] = f;
+      a.stats->beta[it] = beta;
+      ks->gd = gd;
+      ks->stop = stop;
+      if (bad) {
+        ks->bad = 1;
+        __hip_atomic_fetch_or(&a.sync[2], kErrBadFrame, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+// Curvature of the majoriser along d: sum w c (u . d)^2.
+template <int KC, typename TS>
+__global__ __launch_bounds__(kStBlock) void st_curv(FrameArgs a, const StreamKS* __restrict__ ks,
+                                                    const float* __restrict__ wc, double* __restrict__ part) {
+  if (ks->stop || ks->bad) return;
+  __shared__ float ds[KC];
+  __shared__ double red[kStWaves][kStL];
+  const int tid = thread_index();
+  if (tid < KC) ds[tid] = ks->df[tid];
+  __syncthreads();
+  const int p = blockIdx.x * kStBlock + tid;
+  const TS* __restrict__ U = (const TS*)a.U;
+  float acc[1] = {0.f};
+  if (p < a.P)
+    for (int c = 0; c < a.C; ++c) {
+      const long long e = (long long)c * a.P + p;
+      float t = 0.f;
+#pragma unroll
+      for (int j = 0; j < KC; ++j)
+        if (j < a.k) t = fmaf(ld_elem(U, (long long)j * a.ldU + e), ds[j], t);
+      acc[0] = fmaf(wc[e] * t, t, acc[0]);
+    }
+  st_block_partials<1>(acc, red, part);
+}
+
+// Majoriser step: alpha = -g.d / d^T H d, y += alpha d.
+__global__ __launch_bounds__(kStRed) void st_advance(FrameArgs a, StreamKS* ks, const double* __restrict__ part,
+                                                     int nblk, int it) {
+  if (ks->stop || ks->bad) return;
+  __shared__ double grp[kStRed / 32][32];
+  __shared__ double tot[32];
+  st_sum_partials<1>(part, nblk, grp, tot);
+  const double dHd = tot[0];
+  if (!(dHd > 0.0)) {
+    if (threadIdx.x == 0) ks->stop = 1;
+    return;
+  }
+  const double alpha = -ks->gd / dHd;
+  const int t = threadIdx.x;
+  if (t < kMaxK) {
+    st_set_y(ks, t, ks->y[t] + alpha * ks->d[t]);
+    ks->dp[t] = ks->d[t];
+  }
+  if (t == 0) {
+    a.stats->alpha[it] = alpha;
+    ks->steps = it + 1;
+  }
+}
+
+// Step 2 eta pass at the final y: eta = -w phi'(r) stored per entry;
+// partials of U^T eta, ||eta||^2 and the final cost.
+template <int KC, typename TS>
+__global__ __launch_bounds__(kStBlock) void st_eta(FrameArgs a, const StreamKS* __restrict__ ks, float* __restrict__ eta,
+                                                   double* __restrict__ part) {
+  if (ks->bad) return;
+  __shared__ float ys[KC], yl[KC];
+  __shared__ double red[kStWaves][kStL];
+  const int tid = thread_index();
+  if (tid < KC) {
+    ys[tid] = ks->yf[tid];
+    yl[tid] = ks->yl[tid];
+  }
+  __syncthreads();
+  const int p = blockIdx.x * kStBlock + tid;
+  const bool valid = p < a.P;
+  const float wt = valid ? st_weight(a, p) : 0.f;
+  const TS* __restrict__ U = (const TS*)a.U;
+  const TS* __restrict__ X = (const TS*)a.x;
+  float acc[KC + 2];
+#pragma unroll
+  for (int j = 0; j < KC + 2; ++j) acc[j] = 0.f;
+  if (valid)
+    for (int c = 0; c < a.C; ++c) {
+      const long long e = (long long)c * a.P + p;
+      float u[KC];
+      float r = ld_elem(X, e), rl = 0.f;
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        u[j] = (j < a.k) ? ld_elem(U, (long long)j * a.ldU + e) : 0.f;
+        r = fmaf(-u[j], ys[j], r);
+        rl = fmaf(-u[j], yl[j], rl);
+      }
+      r += rl;
+      float phi, cc;
+      cost_eval(r, a.cp, phi, cc);
+      const float et = -wt * cc * r;
+      eta[e] = et;
+      acc[KC] = fmaf(et, et, acc[KC]);
+      acc[KC + 1] = fmaf(wt, phi, acc[KC + 1]);
+#pragma unroll
+      for (int j = 0; j < KC; ++j) acc[j] = fmaf(et, u[j], acc[j]);
+    }
+  st_block_partials<KC + 2>(acc, red, part);
+}
+
+// Geodesic scalars (Sec. 3.3 Step 2, Sec. 3.4 step size) from the reduced
+// a = U^T eta, ||eta||^2 and the final cost, as geodesic_setup does.
+template <int KC>
+__global__ __launch_bounds__(kStRed) void st_geodesic(FrameArgs a, StreamKS* ks, const double* __restrict__ part,
+                                                      int nblk) {
+  if (ks->bad) return;
+  __shared__ double grp[kStRed / 32][32];
+  __shared__ double tot[32];
+  st_sum_partials<KC + 2>(part, nblk, grp, tot);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const double av = (lane < a.k) ? tot[lane] : 0.0;
+    const double yv = (lane < a.k) ? ks->y[lane] : 0.0;
+    const double aa = row16_sum(av * av);
+    const double yy = row16_sum(yv * yv);
+    const double ee = tot[KC];
+    const double zeta = sqrt(fmax(ee - aa, 0.0));
+    const double nu = sqrt(yy);
+    const double sigma = zeta * nu;
+    const int upd = (zeta > 0.0 && nu > 0.0) ? 1 : 0;
+    if (lane < kMaxK) {
+      ks->af[lane] = (float)av;
+      ks->vf[lane] = upd ? (float)(yv / nu) : 0.f;
+    }
+    if (lane == 0) {
+      const long long n = *a.nframe;
+      const GeoScalars g = geodesic_scalars(a.tau * (double)n, a.t_init, a.t_min, sigma, zeta);
+      ks->cm1 = upd ? (float)g.cm1 : 0.f;
+      ks->sz = upd ? (float)g.sz : 0.f;
+      ks->nu = (float)nu;
+      ks->upd = upd;
+      const int steps = ks->steps;
+      a.stats->f[steps] = tot[KC + 1];
+      a.stats->cg_steps = steps;
+      a.stats->restarts = ks->restarts;
+      a.stats->t = g.t;
+      a.stats->sigma = sigma;
+      a.stats->theta = g.theta;
+      a.stats->zeta = zeta;
+      a.stats->nu = nu;
+      a.stats->updated = upd;
+    }
+  }
+}
+
+// Rank-one geodesic update of every row and the pixel labels (Step 3), one
+// pass: u <- u + coef v with coef = (cos theta - 1)(u.v) - (sin theta / zeta)
+// (eta - u.a); r' = r - coef nu (r' = x - U' y); label = any channel with
+// |r'| >= delta.
+template <int KC, typename TS>
+__global__ __launch_bounds__(kStBlock) void st_update(FrameArgs a, const StreamKS* __restrict__ ks,
+                                                      const float* __restrict__ eta) {
+  if (ks->bad) return;
+  __shared__ float ys[KC], yl[KC], vs[KC], as[KC];
+  const int tid = thread_index();
+  if (tid < KC) {
+    ys[tid] = ks->yf[tid];
+    yl[tid] = ks->yl[tid];
+    vs[tid] = ks->vf[tid];
+    as[tid] = ks->af[tid];
+  }
+  __syncthreads();
+  const int p = blockIdx.x * kStBlock + tid;
+  if (p >= a.P) return;
+  const float cm1 = ks->cm1, sz = ks->sz, nu = ks->nu;
+  const bool upd = ks->upd != 0;
+  TS* __restrict__ U = (TS*)a.U;
+  const TS* __restrict__ X = (const TS*)a.x;
+  uint8_t label = 0;
+  for (int c = 0; c < a.C; ++c) {
+    const long long e = (long long)c * a.P + p;
+    float u[KC];
+    float r = ld_elem(X, e), rl = 0.f;
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      u[j] = (j < a.k) ? ld_elem(U, (long long)j * a.ldU + e) : 0.f;
+      r = fmaf(-u[j], ys[j], r);
+      rl = fmaf(-u[j], yl[j], rl);
+    }
+    r += rl;
+    if (upd) {
+      float uv = 0.f, ua = 0.f;
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        uv = fmaf(u[j], vs[j], uv);
+        ua = fmaf(u[j], as[j], ua);
+      }
+      const float coef = fmaf(cm1, uv, -sz * (eta[e] - ua));
+#pragma unroll
+      for (int j = 0; j < KC; ++j)
+        if (j < a.k) st_elem(U, (long long)j * a.ldU + e, fmaf(coef, vs[j], u[j]));
+      if (a.labels_after_update) r = fmaf(-coef, nu, r);
+    }
+    if (fabsf(r) >= a.delta) label = 1;
+  }
+  a.lab[p] = label;
+}
+
+// Frame end: y and the frame counter (an accepted frame only).
+__global__ void st_end(FrameArgs a, const StreamKS* __restrict__ ks) {
+  const int t = threadIdx.x;
+  if (ks->bad) {
+    if (t == 0) a.stats->bad_frame = 1;
+    return;
+  }
+  if (t < a.k) a.y[t] = ks->y[t];
+  if (t == 0) {
+    a.stats->bad_frame = 0;
+    *a.nframe = *a.nframe + 1;
+  }
+}
+
+template <int KC, typename TS>
+static void st_frame_launch(const FrameArgs& a, StreamKS* ks, float* wc, float* eta, double* part, int nblk,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(st_begin, dim3(1), dim3(64), 0, s, a, ks);
+  for (int it = 0; it < a.J; ++it) {
+    hipLaunchKernelGGL((st_grad<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, wc, part);
+    hipLaunchKernelGGL((st_direction<KC>), dim3(1), dim3(kStRed), 0, s, a, ks, (const double*)part, nblk, it);
+    hipLaunchKernelGGL((st_curv<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks,
+                       (const float*)wc, part);
+    hipLaunchKernelGGL(st_advance, dim3(1), dim3(kStRed), 0, s, a, ks, (const double*)part, nblk, it);
+  }
+  hipLaunchKernelGGL((st_eta<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, eta, part);
+  hipLaunchKernelGGL((st_geodesic<KC>), dim3(1), dim3(kStRed), 0, s, a, ks, (const double*)part, nblk);
+  hipLaunchKernelGGL((st_update<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks,
+                     (const float*)eta);
+  hipLaunchKernelGGL(st_end, dim3(1), dim3(64), 0, s, a, (const StreamKS*)ks);
+}
+
+template <typename TS>
+static void st_frame_class(int kc, const FrameArgs& a, StreamKS* ks, float* wc, float* eta, double* part, int nblk,
+                           hipStream_t s) {
+  switch (kc) {
+    case 2: st_frame_launch<2, TS>(a, ks, wc, eta, part, nblk, s); break;
+    case 4: st_frame_launch<4, TS>(a, ks, wc, eta, part, nblk, s); break;
+    case 5: st_frame_launch<5, TS>(a, ks, wc, eta, part, nblk, s); break;
+    case 8: st_frame_launch<8, TS>(a, ks, wc, eta, part, nblk, s); break;
+    case 10: st_frame_launch<10, TS>(a, ks, wc, eta, part, nblk, s); break;
+    case 12: st_frame_launch<12, TS>(a, ks, wc, eta, part, nblk, s); break;
+    case 15: st_frame_launch<15, TS>(a, ks, wc, eta, part, nblk, s); break;
+    default: st_frame_launch<16, TS>(a, ks, wc, eta, part, nblk, s); break;
+  }
+}
+
+static int st_class(int k) {
+  return k <= 2 ? 2 : k <= 4 ? 4 : k <= 5 ? 5 : k <= 8 ? 8 : k <= 10 ? 10 : k <= 12 ? 12 : k <= 15 ? 15 : 16;
+}
+
+}  // namespace prost
+
+// Device buffers of the streamed path: k-space state, per-entry w c and eta,
+// per-workgroup partials.
+pros_status prost_stream_alloc(pros_handle* h) {
+  using namespace prost;
+  const int nblk = (h->P + kStBlock - 1) / kStBlock;
+  const size_t bytes = sizeof(StreamKS) + 2 * sizeof(float) * (size_t)h->m + sizeof(double) * (size_t)nblk * kStL + 1024;
+  hipError_t e = hipMalloc(&h->stream_ws, bytes);
+  if (e != hipSuccess) return prost_host::set_error(PROS_ENOMEM, "streamed-frame buffers: %s", hipGetErrorString(e));
+  e = hipMemsetAsync(h->stream_ws, 0, bytes, h->stream);
+  if (e != hipSuccess) return prost_host::set_error(PROS_EHIP, "streamed-frame buffers: %s", hipGetErrorString(e));
+  h->stream_blocks = nblk;
+  return PROS_OK;
+}
+
+pros_status prost_stream_frame(pros_handle* h, const prost::FrameArgs& a) {
+  using namespace prost;
+  char* base = (char*)h->stream_ws;
+  StreamKS* ks = (StreamKS*)base;
+  float* wc = (float*)(base + ((sizeof(StreamKS) + 255) / 256) * 256);
+  float* eta = wc + h->m;
+  double* part = (double*)(((uintptr_t)(eta + h->m) + 255) / 256 * 256);
+  const int kc = st_class(h->k);
+  if (h->prm.storage == PROS_BF16)
+    st_frame_class<uint16_t>(kc, a, ks, wc, eta, part, h->stream_blocks, h->stream);
+  else
+    st_frame_class<float>(kc, a, ks, wc, eta, part, h->stream_blocks, h->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    h->broken = true;
+    h->broken_status = PROS_EHIP;
+    return prost_host::set_error(PROS_EHIP, "streamed frame launch failed: %s", hipGetErrorString(e));
+  }
+  return PROS_OK;
+}

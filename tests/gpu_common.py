@@ -122,7 +122,7 @@ def compare_step(trk, prm, st, x64, storage="f32", guard=GUARD):
     return rep
 
 
-def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U, f_ref0=False):
+def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U, f_ref0=False, tol_step=TOL_STEP):
     """f_ref0: compare the costs relative to the frame's first cost f_0
     instead of each f_j.  For frames the subspace fits exactly (k = m) the
     log cost's f_j tends to 0, and the float32 residuals (absolute error
@@ -149,8 +149,8 @@ def assert_parity(rep, tol_y=TOL_Y, tol_u=TOL_U, f_ref0=False):
     assert (rep["f_rel0"] if f_ref0 else rep["f_rel"]) <= TOL_F
     assert rep["U_elem"] <= TOL_U_ELEM
     if not f_ref0:   # (an exactly fitted frame drives theta and the last alpha to rounding level)
-        assert rep["theta_rel"] <= TOL_STEP
-        assert rep["alpha_rel"] <= TOL_STEP
+        assert rep["theta_rel"] <= tol_step
+        assert rep["alpha_rel"] <= tol_step
     if "pre" in rep:   # float32 running statistics against float64
         say(f"  pre-processing: count {rep['pre']['count']} mean {rep['pre']['mean_err']:.1e} "
             f"m2 {rep['pre']['m2_rel']:.1e}")
