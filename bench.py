@@ -40,6 +40,19 @@ def pass_bytes(m, k, P, bu, bx, J=5):
     return (J + 3) * m * k * bu + (J + 2) * m * bx + (J + 4) * P
 
 
+def streamed_bytes(m, k, P, bu, bx, J=5):
+    """HBM bytes of one frame in the streamed form (frames too large for
+    resident register tiles): per CG step the gradient pass reads U, x and
+    the labels and writes w c per entry, the curvature pass reads U and w c;
+    the eta pass reads U, x and the labels and writes eta; the update pass
+    reads U, x and eta, writes U and the labels (4-byte w c and eta)."""
+    grad = m * k * bu + m * bx + P + 4 * m
+    curv = m * k * bu + 4 * m
+    eta = m * k * bu + m * bx + P + 4 * m
+    upd = 2 * m * k * bu + m * bx + 4 * m + P
+    return J * (grad + curv) + eta + upd
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1302_2073_amd", "csrc")
@@ -119,6 +132,45 @@ def run_plain(storage, steps, warmup, pool, curvature=0, cooperative=1):
     trk.close()
     return dict(ms_total=ms, ms_per_frame=ms / steps, fps=steps / (ms / 1e3), launch=info,
                 cg_steps=stats["cg_steps"], spread_ms=[round(lo, 3), round(hi, 3)])
+
+
+def run_streamed(storage, steps, warmup, pool=4, width=1280, height=720):
+    """One stream of frames beyond the resident register tiles (1280x720x3,
+    k = 15): the streamed form, one launch per dependent pass."""
+    import torch
+    from paper_1302_2073_amd import Tracker
+    from synth import video as V
+    spec = V.VideoSpec(width, height, CH, rank=10, seed=7, noise=0.01, fg_kind="rects", fg_count=3,
+                       fg_density=0.05, speed=(1.0, 2.0))
+    sv = V.SyntheticVideo(spec)
+    X = np.stack([sv.frame(n) for n in range(pool)]).astype(np.float32)
+    frames = torch.from_numpy(X).cuda()
+    if storage == "bf16":
+        frames = frames.to(torch.bfloat16)
+    frames = frames.contiguous()
+    trk = Tracker(width, height, CH, K, mu=1e-3, storage=storage, seed=11)
+    info = trk.launch_info()
+    if info["sync_mode"] != -1:
+        raise RuntimeError(f"{width}x{height}x{CH} is not streamed: {info}")
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        trk.track(frames[i % pool])
+    torch.cuda.synchronize()
+    ms, lo, hi = timed_median(lambda i: trk.track(frames[i % pool]), steps, stream)
+    st = trk.sync()
+    if st != 0:
+        raise RuntimeError(f"tracker error {st}")
+    trk.close()
+    del frames
+    m, P = width * height * CH, width * height
+    bu = bx = 4 if storage == "f32" else 2
+    per = ms / steps
+    return {"fps": round(steps / (ms / 1e3), 1), "ms_per_frame": round(per, 5),
+            "alg_GBps": round(alg_bytes(m, K, P, bu, bx) / (per * 1e-3) / 1e9, 1),
+            "streamed_bytes_per_frame": streamed_bytes(m, K, P, bu, bx),
+            "streamed_GBps": round(streamed_bytes(m, K, P, bu, bx) / (per * 1e-3) / 1e9, 1),
+            "launch": info, "spread_ms": [round(lo, 3), round(hi, 3)],
+            "workload": f"{width}x{height}x{CH}, k = {K}, {storage}, one stream"}
 
 
 def run_plain_seq(storage, steps, warmup, pool, chunk=64):
@@ -509,7 +561,7 @@ def main():
     # also available: plain_f32_curv1, plain_f32_ordinary, batched_bf16_ordinary
     ap.add_argument("--forms", default="plain_f32,plain_f32_seq,plain_bf16,plain_bf16_seq,plain_f32_host,"
                     "batched_bf16,batched_bf16_seq,batched_mixed_bf16,batched_mixed_bf16_seq,lpcost,"
-                    "quality,ingest,stream_copy",
+                    "quality,ingest,streamed_f32_1280x720,streamed_bf16_1280x720,stream_copy",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -548,6 +600,15 @@ def main():
     if "plain_f32" in want:
         plain = run_plain("f32", args.steps * 4, args.warmup, args.pool)
         achieved = record("plain_f32", plain, 4, 4)
+    for storage in ("f32", "bf16"):
+        name = f"streamed_{storage}_1280x720"
+        if name in want:
+            try:
+                forms[name] = run_streamed(storage, max(args.steps // 4, 10), min(args.warmup, 5))
+                forms[name]["note"] = ("frames beyond the resident register tiles: one launch per dependent "
+                                       "pass, U and x read from HBM in every pass")
+            except Exception as exc:
+                forms[name] = {"error": repr(exc)[:300]}
     if "plain_f32_curv1" in want:
         try:
             curv = run_plain("f32", args.steps * 4, args.warmup, args.pool, curvature=1)

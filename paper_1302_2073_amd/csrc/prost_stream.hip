@@ -58,20 +58,42 @@ __device__ __forceinline__ void st_block_partials(float (&acc)[L], double (*red)
 }
 
 // Sum over the nblk workgroups' partials of the first L values, into out[]
-// (shared): thread t adds value t % 32 of workgroups t / 32, t / 32 + 32, ...
-// in order, then the 32 group sums of each value are added in order.
+// (shared).  Each value is summed by NG = kStRed / Lp threads (Lp: L rounded
+// up to a power of two): thread (q, g) takes workgroups g, g + NG, g + 2 NG,
+// ... in order (kStUnroll loads in flight), then the NG group sums are
+// folded in a fixed tree (the upper half onto the lower, down to 32) and
+// those are added in order.  Every step is fixed, so the result is
+// deterministic.
+constexpr int kStUnroll = 16;
 template <int L>
-__device__ __forceinline__ void st_sum_partials(const double* __restrict__ part, int nblk, double (*grp)[32],
+__device__ __forceinline__ void st_sum_partials(const double* __restrict__ part, int nblk, double* grp,
                                                 double* out) {
-  const int t = threadIdx.x, q = t & 31, g = t >> 5;
+  constexpr int Lp = pow2_at_least(L);
+  constexpr int NG = kStRed / Lp;
+  static_assert(NG >= 32, "at least 32 threads per value");
+  const int t = threadIdx.x, q = t % Lp, g = t / Lp;
   double s = 0.0;
-  if (q < L)
-    for (int b = g; b < nblk; b += kStRed / 32) s += part[(size_t)b * kStL + q];
-  grp[g][q] = s;
+  if (q < L) {
+    int b = g;
+    for (; b + (kStUnroll - 1) * NG < nblk; b += kStUnroll * NG) {
+      double v[kStUnroll];
+#pragma unroll
+      for (int i = 0; i < kStUnroll; ++i) v[i] = part[(size_t)(b + i * NG) * kStL + q];
+#pragma unroll
+      for (int i = 0; i < kStUnroll; ++i) s += v[i];
+    }
+    for (; b < nblk; b += NG) s += part[(size_t)b * kStL + q];
+  }
+  grp[g * Lp + q] = s;
   __syncthreads();
+#pragma unroll
+  for (int h = NG / 2; h >= 32; h >>= 1) {
+    if (g < h) grp[g * Lp + q] += grp[(g + h) * Lp + q];
+    __syncthreads();
+  }
   if (t < L) {
     double v = 0.0;
-    for (int r = 0; r < kStRed / 32; ++r) v += grp[r][t];
+    for (int r = 0; r < 32; ++r) v += grp[r * Lp + t];
     out[t] = v;
   }
   __syncthreads();
@@ -153,7 +175,7 @@ template <int KC>
 __global__ __launch_bounds__(kStRed) void st_direction(FrameArgs a, StreamKS* ks, const double* __restrict__ part,
                                                        int nblk, int it) {
   if (ks->stop || ks->bad) return;
-  __shared__ double grp[kStRed / 32][32];
+  __shared__ double grp[kStRed];
   __shared__ double tot[32];
   st_sum_partials<KC + 1>(part, nblk, grp, tot);
   if (threadIdx.x < 64) {
@@ -225,7 +247,7 @@ __global__ __launch_bounds__(kStBlock) void st_curv(FrameArgs a, const StreamKS*
 __global__ __launch_bounds__(kStRed) void st_advance(FrameArgs a, StreamKS* ks, const double* __restrict__ part,
                                                      int nblk, int it) {
   if (ks->stop || ks->bad) return;
-  __shared__ double grp[kStRed / 32][32];
+  __shared__ double grp[kStRed];
   __shared__ double tot[32];
   st_sum_partials<1>(part, nblk, grp, tot);
   const double dHd = tot[0];
@@ -297,7 +319,7 @@ template <int KC>
 __global__ __launch_bounds__(kStRed) void st_geodesic(FrameArgs a, StreamKS* ks, const double* __restrict__ part,
                                                       int nblk) {
   if (ks->bad) return;
-  __shared__ double grp[kStRed / 32][32];
+  __shared__ double grp[kStRed];
   __shared__ double tot[32];
   st_sum_partials<KC + 2>(part, nblk, grp, tot);
   if (threadIdx.x < 64) {
