@@ -9,7 +9,8 @@
 // Layouts (row-major): U (m, k), Y (B, k), X (B, m), w (m) or NULL.
 // The per-entry derivative code is the cost functor the frame kernel uses.
 // Reductions are deterministic: per-workgroup partials in float64, summed in
-// a fixed order by a finishing kernel.
+// a fixed order by a finishing kernel.  The backward's contraction of the
+// per-entry factors with U (dY) runs on the matrix cores in float32.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -26,6 +27,8 @@ constexpr int kLpWaves = kLpBlock / 64;
 constexpr int kLpChunkF = 32;        // frames per pass, forward
 constexpr int kLpChunkB = 16;        // frames per pass, backward (LDS for s)
 constexpr int kLpPad = kLpBlock + 4; // LDS row stride (16-byte aligned, spreads banks)
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ CostParams make_cp(int form, float p, float mu) {
   CostParams cp;
@@ -154,6 +157,8 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
   __shared__ float ys[CH][K];
   __shared__ float gs[CH];
   __shared__ double redm[kLpWaves];
+  __shared__ double dyw[kLpWaves][16][17];   // per-wavefront dY tiles [frame][j]
+  static_assert(CH == 16 && K <= 16 && kLpBlock == 64 * kLpWaves, "one 16 x 16 tile per wavefront");
   const CostParams cp = make_cp(form, p, *mu_p);
   const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
   const int nblk = gridDim.x;
@@ -199,25 +204,36 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
 #pragma unroll
           for (int j = 0; j < K; ++j) du[j] = fmaf(-sd, ys[bl][j], du[j]);
         }
-        if (bl < nb) sdl[bl][tid] = sd;
+        sdl[bl][tid] = sd;   // 0 past the last frame or row
       }
     }
     __syncthreads();
-    // dY share of this workgroup: -sum_rows s[b][row] u[row][j], rows in order
-    // (four interleaved float32 partial sums, combined in float64)
+    // dY share of this workgroup: -sum_rows s[b][row] u[row][j], a 16 x 256
+    // by 256 x K product on the matrix cores: wavefront w multiplies its 64
+    // rows in 16 steps of v_mfma_f32_16x16x4f32 (A = s[frame][4 rows], B =
+    // u[4 rows][j], float32 accumulation), and the four wavefronts' 16 x 16
+    // tiles are added in order in float64.  Frames past nb and columns past
+    // K only reach outputs that are not written.
+    {
+      const int i16 = lane & 15, k4 = lane >> 4;
+      f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const int row = wv * 64 + st * 4 + k4;
+        const float av = sdl[i16][row];
+        const float bv = (i16 < K) ? uT[i16 < K ? i16 : 0][row] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dyw[wv][k4 * 4 + v][i16] = (double)acc[v];   // D[frame][j]
+    }
+    __syncthreads();
     for (int q = tid; q < nb * K; q += kLpBlock) {
       const int bl = q / K, j = q - bl * K;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll 4
-      for (int row = 0; row < kLpBlock; row += 4) {
-        const float4 sv = *(const float4*)&sdl[bl][row];
-        const float4 uv = *(const float4*)&uT[j][row];
-        a0 = fmaf(sv.x, uv.x, a0);
-        a1 = fmaf(sv.y, uv.y, a1);
-        a2 = fmaf(sv.z, uv.z, a2);
-        a3 = fmaf(sv.w, uv.w, a3);
-      }
-      part[(size_t)((size_t)b0 * K + q) * nblk + blockIdx.x] = -(((double)a0 + (double)a1) + ((double)a2 + (double)a3));
+      double sum = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < kLpWaves; ++w2) sum += dyw[w2][bl][j];
+      part[(size_t)((size_t)b0 * K + q) * nblk + blockIdx.x] = -sum;
     }
   }
   if (dU) {   // coalesced store of the workgroup's dU rows through LDS
