@@ -303,8 +303,11 @@ PROS_API pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out)
  * tiles form a gang for the frame's reductions, and a host-built schedule
  * packs the gangs onto the resident workgroups in rounds.  Frames are read
  * from a caller-registered ring of device frames: stream s reads
- * frames[s * ring + (n_s % ring)] where n_s is its frame counter.  All
- * streams start with U = 0; set each with pros_batch_set_state.
+ * frames[s * ring + (n_s % ring)] where n_s is its frame counter.  Every
+ * stream starts from its own seeded U0 (pros_batch_init); pros_batch_set_state
+ * replaces it.  A stream whose gang does not fit the resident workgroups (a
+ * frame beyond the single-stream resident bound, see pros_init) is refused
+ * with PROS_EUNSUPPORTED: the batched form has no streamed form.
  * Errors as for single streams; a failed launch makes the batch unusable.
  * ------------------------------------------------------------------------- */
 typedef struct pros_batch pros_batch;

@@ -254,9 +254,9 @@ def test_benchmark_launch_configuration():
     """The benchmark's headline launch: 16 bfloat16 640x480x3 k=15 streams,
     register budget 128, one workgroup per CU, gangs in stream order (two
     per round, eight rounds), two-hop exchange, replayed from a hipGraph,
-    8 steps per launch over a ring of 8 frames.  One step is checked
+    32 steps per launch over a ring of 8 frames.  One step is checked
     against the oracle on a sample of streams from six of the eight rounds;
-    then two 8-step launches must equal 16 single steps (no graph) bit for
+    then one 32-step launch must equal 32 single steps (no graph) bit for
     bit, for every stream's state and mask."""
     import hashlib
     from paper_1302_2073_amd.tracker import BatchTracker
@@ -292,14 +292,13 @@ def test_benchmark_launch_configuration():
             if multi:
                 for s in sample:
                     _check_vga_bf16_step(bt, s, starts[s], _rne(svs[s].frame(0)), wls[s].mu)
-                bt.steps(8)
-                bt.steps(8)
+                bt.steps(32)
             else:
-                for _ in range(16):
+                for _ in range(32):
                     bt.step()
             assert bt.sync() == 0
             res.append(digest(bt))
-    assert [r[3] for r in res[0]] == [17] * ns
+    assert [r[3] for r in res[0]] == [33] * ns
     for s in range(ns):
         assert res[0][s] == res[1][s], f"stream {s}"
 
