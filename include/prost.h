@@ -354,6 +354,18 @@ PROS_API pros_status pros_batch_get_preprocess(pros_batch* b, int32_t s, double*
 PROS_API pros_status pros_batch_set_frames(pros_batch* b, const void* const* frames, int32_t ring);
 /* One batch step: every stream processes its next frame.  Asynchronous. */
 PROS_API pros_status pros_batch_track(pros_batch* b);
+/* One batch step on the frames given for this call (Sec. 3.3: each stream's
+ * new frame arrives online): frames[s] is stream s's device frame (m_s
+ * entries of the storage type) for this step, n pointers in a host array
+ * that may be reused as soon as the call returns.  The frames themselves
+ * must stay valid until the step has run (pros_batch_sync).  The table of
+ * frame pointers is updated in stream order (from pinned staging), so
+ * consecutive calls queue without waiting, also with hipGraph replay; the
+ * first call, a change from a ring registered with pros_batch_set_frames,
+ * or a change in a frame's 4-byte alignment registers the frames
+ * synchronously (ring of 1).  Errors as pros_batch_track; PROS_EINVAL for a
+ * NULL pointer.  Asynchronous otherwise. */
+PROS_API pros_status pros_batch_track_frames(pros_batch* b, const void* const* frames);
 /* `steps` batch steps (1..4096) with the same results as `steps` calls of
  * pros_batch_track, in one launch: every (stream, tile) item of the
  * schedule advances its stream by `steps` frames of the ring with its tile

@@ -122,6 +122,7 @@ _SIGS = {
                                             C.c_void_p]),
     "pros_batch_set_frames": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32]),
     "pros_batch_track": (C.c_int, [C.c_void_p]),
+    "pros_batch_track_frames": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "pros_batch_track_steps": (C.c_int, [C.c_void_p, C.c_int32]),
     "pros_batch_use_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "pros_batch_sync": (C.c_int, [C.c_void_p]),

@@ -115,6 +115,11 @@ struct pros_batch {
   FrameArgs* d_descs_seq = nullptr;
   int seq_steps = 0;
   long long descs_version = 0, seq_version = -1;
+  // per-call frames (pros_batch_track_frames): two pinned copies of the
+  // frame table, each reusable once the copy queued from it has run
+  const void** h_xstage[2] = {nullptr, nullptr};
+  hipEvent_t xstage_done[2] = {nullptr, nullptr};
+  int xstage_next = 0;
 };
 
 static void drop_graph(pros_batch* b) {
@@ -142,6 +147,10 @@ static void free_batch(pros_batch* b) {
   if (b->d_descs_seq) (void)hipFree(b->d_descs_seq);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_xtab) (void)hipFree((void*)b->d_xtab);
+  for (int i = 0; i < 2; ++i) {
+    if (b->xstage_done[i]) (void)hipEventDestroy(b->xstage_done[i]);
+    if (b->h_xstage[i]) (void)hipHostFree((void*)b->h_xstage[i]);
+  }
   delete b;
 }
 
@@ -476,6 +485,44 @@ pros_status pros_batch_track(pros_batch* b) {
     h->mask_stale = true;
   }
   return PROS_OK;
+}
+
+pros_status pros_batch_track_frames(pros_batch* b, const void* const* frames) {
+  pros_status st = check_batch(b);
+  if (st != PROS_OK) return st;
+  if (!frames) return fail(PROS_EINVAL, "frames is NULL");
+  for (int s = 0; s < b->n; ++s)
+    if (!frames[s]) return fail(PROS_EINVAL, "frame pointer %d is NULL", s);
+  // The kernels' descriptors depend on the ring length and on whether each
+  // stream's frame is 4-byte aligned; a change goes through the synchronous
+  // registration.
+  bool same = b->frames_set && b->ring == 1;
+  for (int s = 0; same && s < b->n; ++s) same = (((uintptr_t)frames[s] & 3u) == 0) == (b->frames_aligned[s] != 0);
+  if (!same) {
+    st = pros_batch_set_frames(b, frames, 1);
+    if (st != PROS_OK) return st;
+    return pros_batch_track(b);
+  }
+  const int i = b->xstage_next;
+  hipError_t e = hipSuccess;
+  if (!b->h_xstage[i]) {
+    e = hipHostMalloc((void**)&b->h_xstage[i], sizeof(void*) * (size_t)b->n, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(PROS_ENOMEM, "pinned frame table: %s", hipGetErrorString(e));
+    e = hipEventCreateWithFlags(&b->xstage_done[i], hipEventDisableTiming);
+    if (e != hipSuccess) return fail(PROS_EHIP, "event: %s", hipGetErrorString(e));
+  } else {
+    e = hipEventSynchronize(b->xstage_done[i]);   // the copy queued from this table two calls ago has run
+    if (e != hipSuccess) return fail(PROS_EHIP, "event wait: %s", hipGetErrorString(e));
+  }
+  std::memcpy((void*)b->h_xstage[i], frames, sizeof(void*) * (size_t)b->n);
+  // stream-ordered: the previous step's kernel has finished reading the
+  // table when the copy runs, and this step's launch reads the new one
+  e = hipMemcpyAsync((void*)b->d_xtab, (const void*)b->h_xstage[i], sizeof(void*) * (size_t)b->n,
+                     hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->xstage_done[i], b->stream);
+  if (e != hipSuccess) return fail(PROS_EHIP, "frame table upload: %s", hipGetErrorString(e));
+  b->xstage_next = 1 - i;
+  return pros_batch_track(b);
 }
 
 pros_status pros_batch_track_steps(pros_batch* b, int32_t steps) {

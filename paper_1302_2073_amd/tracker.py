@@ -330,6 +330,18 @@ class BatchTracker:
     def step(self):
         L.check(L.lib().pros_batch_track(self._b))
 
+    def track(self, frames):
+        """One batch step on this call's frames: frames[s] is a device tensor
+        of stream s (pros_batch_track_frames).  References to the last four
+        calls' tensors are kept; synchronise before reusing older ones."""
+        assert len(frames) == self.n
+        ptrs = (C.c_void_p * self.n)()
+        for s, t in enumerate(frames):
+            assert t.is_cuda and t.is_contiguous() and t.numel() == self._dims(s)[1]
+            ptrs[s] = t.data_ptr()
+        L.check(L.lib().pros_batch_track_frames(self._b, ptrs))
+        self._recent = (getattr(self, "_recent", []) + [list(frames)])[-4:]
+
     def steps(self, n):
         """n batch steps in one launch (pros_batch_track_steps)."""
         L.check(L.lib().pros_batch_track_steps(self._b, int(n)))

@@ -440,3 +440,76 @@ def test_256_thread_workgroups(storage):
                 np.testing.assert_array_equal(a, b)
         else:
             np.testing.assert_array_equal(sa, sb)
+
+
+def _per_call_state(storage, streams, rows, graph, ring_mode):
+    """Six batch steps over frames rows[n][s] (n = step, s = stream), either
+    registered as a ring of six (ring_mode) or handed over per call
+    (pros_batch_track_frames); the final states and masks."""
+    from paper_1302_2073_amd.tracker import BatchTracker
+    with BatchTracker(_specs(streams), storage=storage) as bt:
+        _load(bt, streams)
+        bt.use_graph(graph)
+        if ring_mode:   # stream s reads ring slot (frame counter) mod ring
+            R = len(rows)
+            n0 = [bt.get_state(s)[3] for s in range(len(streams))]
+            bt.set_frames([[rows[(i - n0[s]) % R][s] for i in range(R)] for s in range(len(streams))])
+            for _ in range(len(rows)):
+                bt.step()
+        else:
+            for n in range(len(rows)):
+                bt.track(rows[n])
+        assert bt.sync() == 0
+        return [bt.get_state(s) + (bt.mask(s),) for s in range(len(streams))]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_per_call_frames_equal_the_ring(graph):
+    """pros_batch_track_frames (each call names that step's frames, the
+    table updated in stream order from pinned staging) gives bit for bit the
+    states and masks of stepping a registered ring over the same frames,
+    with and without graph replay."""
+    streams = _streams(SHAPES[:3], warm=2)
+    fr = _frames_tensor(streams, 2, 6)
+    rows = [[fr[s][n] for s in range(len(streams))] for n in range(6)]
+    a = _per_call_state("f32", streams, rows, graph, ring_mode=True)
+    b = _per_call_state("f32", streams, rows, graph, ring_mode=False)
+    for s in range(len(streams)):
+        for x, y in zip(a[s], b[s]):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), f"stream {s}"
+
+
+def test_per_call_frames_with_changing_alignment():
+    """bfloat16 frames handed over per call at alternating 4-byte and 2-byte
+    aligned addresses (the calls whose alignment changes register the frames
+    synchronously): the states follow the oracle step by step."""
+    import torch
+    streams = _streams([(64, 48, 3, 10), (80, 60, 1, 5)], warm=2)
+    fr = _frames_tensor(streams, 2, 4, "bf16")
+    from paper_1302_2073_amd.tracker import BatchTracker, bf16_to_f64
+    with BatchTracker(_specs(streams), storage="bf16") as bt:
+        starts = _load(bt, streams)
+        keep = []
+        for n in range(4):
+            row = []
+            for s in range(len(streams)):
+                t = fr[s][n]
+                if n % 2 == 1:   # an odd bfloat16 offset: not 4-byte aligned
+                    buf = torch.empty(t.numel() + 1, dtype=torch.bfloat16, device="cuda")
+                    buf[1:].copy_(t)
+                    t = buf[1:]
+                row.append(t)
+            keep.append(row)
+            bt.track(row)
+            assert bt.sync() == 0
+            nxt = []
+            for s, (sv, prm, _) in enumerate(streams):
+                x64 = bf16_to_f64(fr[s][n].cpu().view(torch.int16).numpy().view(np.uint16))
+                exp, _ = O.track_frame(starts[s], x64, prm)
+                U1, y1, l1, n1 = bt.get_state(s)
+                assert n1 == exp.n
+                assert np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y) <= TOL_Y
+                band = O.band_pixels(exp.U, x64, exp.y, prm.thr, prm.channels, GUARD)
+                assert int(np.sum((l1 != exp.labels) & ~band)) == 0
+                nxt.append(O.State(U1, y1, l1, O.median3x3(l1, prm.height, prm.width), n1))
+            starts = nxt
