@@ -226,6 +226,48 @@ def run_plain_host(steps, warmup, pool):
     return dict(ms_total=el * 1e3, ms_per_frame=el * 1e3 / steps, fps=steps / el)
 
 
+def time_batch_steps(bt, steps, warmup, per_launch, stream):
+    """HIP-event time of exactly `steps` batch steps of `bt` (graph replay
+    already chosen).  per_launch > 1: launches of that many steps plus one
+    shorter launch for the remainder; per_launch = 0: the steps per launch
+    are chosen from {4, 8, 16, 32} by timing each on the real frames.
+    Returns (median ms, fastest, slowest, steps per launch, the candidates'
+    ms per step or None)."""
+    import torch
+    spl_times = None
+    if per_launch == 0:
+        spl_times = {}
+        for cand in (4, 8, 16, 32):
+            for _ in range(2):
+                bt.steps(cand)
+            torch.cuda.synchronize()
+            n_calls = max(64 // cand, 2)
+            t, _, _ = timed_median(lambda i: bt.steps(cand), n_calls, stream)
+            spl_times[cand] = round(t / (n_calls * cand), 5)
+        per_launch = min(spl_times, key=spl_times.get)
+    if per_launch > 1:   # several steps per launch, tiles kept in registers
+        for _ in range(max(warmup // per_launch, 2)):
+            bt.steps(per_launch)
+        if steps % per_launch:
+            bt.steps(steps % per_launch)   # the remainder launch's graph, captured before timing
+        torch.cuda.synchronize()
+        calls = steps // per_launch
+        rem = steps % per_launch
+
+        def run(i):
+            if i < calls:
+                bt.steps(per_launch)
+            else:
+                bt.steps(rem)
+        ms, lo, hi = timed_median(run, calls + (1 if rem else 0), stream)
+    else:
+        for _ in range(warmup):
+            bt.step()
+        torch.cuda.synchronize()
+        ms, lo, hi = timed_median(lambda i: bt.step(), steps, stream)
+    return ms, lo, hi, per_launch, spl_times
+
+
 def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1, per_launch=1):
     """nstreams independent 640x480x3 k=15 streams, each with its own seeded
     video, one persistent launch per batch step (hipGraph replay).
@@ -259,37 +301,7 @@ def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1
     tuned = bt.tune(steps=3) if tune else None
     bt.use_graph(True)
     stream = torch.cuda.current_stream()
-    spl_times = None
-    if per_launch == 0:   # steps per launch tuned on the real frames
-        spl_times = {}
-        for cand in (4, 8, 16, 32):
-            for _ in range(2):
-                bt.steps(cand)
-            torch.cuda.synchronize()
-            n_calls = max(64 // cand, 2)
-            t, _, _ = timed_median(lambda i: bt.steps(cand), n_calls, stream)
-            spl_times[cand] = round(t / (n_calls * cand), 5)
-        per_launch = min(spl_times, key=spl_times.get)
-    if per_launch > 1:   # several steps per launch, tiles kept in registers
-        for _ in range(max(warmup // per_launch, 2)):
-            bt.steps(per_launch)
-        if steps % per_launch:
-            bt.steps(steps % per_launch)   # the remainder launch's graph, captured before timing
-        torch.cuda.synchronize()
-        calls = steps // per_launch
-        rem = steps % per_launch
-
-        def run(i):
-            if i < calls:
-                bt.steps(per_launch)
-            else:
-                bt.steps(rem)
-        ms, lo, hi = timed_median(run, calls + (1 if rem else 0), stream)
-    else:
-        for _ in range(warmup):
-            bt.step()
-        torch.cuda.synchronize()
-        ms, lo, hi = timed_median(lambda i: bt.step(), steps, stream)
+    ms, lo, hi, per_launch, spl_times = time_batch_steps(bt, steps, warmup, per_launch, stream)
     st = bt.sync()
     if st != 0:
         raise RuntimeError(f"batch error {st}")
@@ -325,18 +337,7 @@ def run_batched_mixed(nstreams, steps, warmup, pool, per_launch=1):
     tuned = bt.tune(steps=3)
     bt.use_graph(True)
     stream = torch.cuda.current_stream()
-    if per_launch > 1:   # several steps per launch (register budget 128), tiles kept in registers
-        for _ in range(max(warmup // per_launch, 2)):
-            bt.steps(per_launch)
-        torch.cuda.synchronize()
-        calls = max(steps // per_launch, 1)
-        ms, lo, hi = timed_median(lambda i: bt.steps(per_launch), calls, stream)
-        steps = calls * per_launch
-    else:
-        for _ in range(warmup):
-            bt.step()
-        torch.cuda.synchronize()
-        ms, lo, hi = timed_median(lambda i: bt.step(), steps, stream)
+    ms, lo, hi, per_launch, spl_times = time_batch_steps(bt, steps, warmup, per_launch, stream)
     st = bt.sync()
     cfg = bt.config()
     bt.close()
@@ -345,7 +346,8 @@ def run_batched_mixed(nstreams, steps, warmup, pool, per_launch=1):
     per = ms / steps
     return dict(ms_total=ms, ms_per_step=per, fps=nstreams / (per * 1e-3),
                 vga_k15_equiv_fps=(mk / (WIDTH * HEIGHT * CH * K)) / (per * 1e-3),
-                alg_bytes_per_step=alg, config=cfg, tuned=tuned, spread_ms=[round(lo, 3), round(hi, 3)])
+                alg_bytes_per_step=alg, config=cfg, tuned=tuned, spread_ms=[round(lo, 3), round(hi, 3)],
+                steps_per_launch=per_launch, steps_per_launch_ms_per_step=spl_times)
 
 
 def run_lpcost(steps, warmup):
@@ -687,13 +689,16 @@ def main():
             forms["batched_mixed_bf16"] = {"error": repr(exc)[:300]}
     if "batched_mixed_bf16_seq" in want:
         try:
-            mixed = run_batched_mixed(64, max(args.steps // 4, 16), args.warmup, args.pool, per_launch=8)
+            mixed = run_batched_mixed(64, max(args.steps // 4, 16), args.warmup, args.pool, per_launch=0)
             per = mixed["ms_per_step"]
             forms["batched_mixed_bf16_seq"] = {
                 "stream_fps": round(mixed["fps"], 1), "vga_k15_equiv_fps": round(mixed["vga_k15_equiv_fps"], 1),
                 "ms_per_step": round(per, 5), "alg_GBps": round(mixed["alg_bytes_per_step"] / (per * 1e-3) / 1e9, 1),
                 "streams": 64, "config": mixed["config"], "spread_ms": mixed["spread_ms"],
-                "note": "8 batch steps per launch when the tuned register budget is 128 (else one launch per step)"}
+                "steps_per_launch": mixed["steps_per_launch"],
+                "steps_per_launch_ms_per_step": mixed["steps_per_launch_ms_per_step"],
+                "note": ("batch steps per launch tuned over {4, 8, 16, 32} (multi-step launches need register "
+                         "budget 128; otherwise one launch per step)")}
         except Exception as exc:   # a side form must not cost the headline line
             forms["batched_mixed_bf16_seq"] = {"error": repr(exc)[:300]}
     if "lpcost" in want:

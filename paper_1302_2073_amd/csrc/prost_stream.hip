@@ -104,6 +104,53 @@ __device__ __forceinline__ float st_weight(const FrameArgs& a, int p) {
   return src[p] ? a.omega : 1.0f;
 }
 
+// Pixels per thread of a pass: one, or (PAIR, bfloat16 with even P and
+// 4-byte aligned planes) two adjacent pixels whose entries are one aligned
+// 32-bit word in every plane of U and of the frame: half the load and store
+// instructions for the same bytes.
+template <typename TS, bool PAIR>
+struct StPix {
+  static_assert(!PAIR || sizeof(TS) == 2, "pairs of bfloat16 entries");
+  static constexpr int N = PAIR ? 2 : 1;
+};
+
+// The entries of channel c of this thread's pixels p0 (.. p0 + 1): U rows
+// (columns >= k are 0) and frame values.
+template <int KC, typename TS, bool PAIR>
+__device__ __forceinline__ void st_load(const FrameArgs& a, int c, int p0, float (&u)[StPix<TS, PAIR>::N][KC],
+                                        float (&x)[StPix<TS, PAIR>::N]) {
+  const long long e = (long long)c * a.P + p0;
+  if constexpr (PAIR) {
+    const uint32_t* __restrict__ U = (const uint32_t*)a.U;
+    const uint32_t xw = ((const uint32_t*)a.x)[e >> 1];
+    x[0] = bf_lo(xw);
+    x[1] = bf_hi(xw);
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+      const uint32_t w = (j < a.k) ? U[((long long)j * a.ldU + e) >> 1] : 0u;
+      u[0][j] = bf_lo(w);
+      u[1][j] = bf_hi(w);
+    }
+  } else {
+    const TS* __restrict__ U = (const TS*)a.U;
+    x[0] = ld_elem((const TS*)a.x, e);
+#pragma unroll
+    for (int j = 0; j < KC; ++j) u[0][j] = (j < a.k) ? ld_elem(U, (long long)j * a.ldU + e) : 0.f;
+  }
+}
+
+// r = x - U y with y as the float32 pair (value, remainder).
+template <int KC>
+__device__ __forceinline__ float st_residual(float x, const float (&u)[KC], const float* ys, const float* yl) {
+  float r = x, rl = 0.f;
+#pragma unroll
+  for (int j = 0; j < KC; ++j) {
+    r = fmaf(-u[j], ys[j], r);
+    rl = fmaf(-u[j], yl[j], rl);
+  }
+  return r + rl;
+}
+
 // y (float64) as the float32 pair the passes use: every pass recomputes
 // r = x - U y from the frame, and the remainder keeps that residual as
 // accurate as the float64 y (near a fit the gradient is small and a
@@ -126,9 +173,10 @@ __global__ void st_begin(FrameArgs a, StreamKS* ks) {
 }
 
 // Step 1 gradient pass at the current y (float32 per thread, as the frame kernel).
-template <int KC, typename TS>
+template <int KC, typename TS, bool PAIR>
 __global__ __launch_bounds__(kStBlock) void st_grad(FrameArgs a, const StreamKS* __restrict__ ks, float* __restrict__ wc,
                                                     double* __restrict__ part) {
+  constexpr int N = StPix<TS, PAIR>::N;
   if (ks->stop || ks->bad) return;
   __shared__ float ys[KC], yl[KC];
   __shared__ double red[kStWaves][kStL];
@@ -138,34 +186,31 @@ __global__ __launch_bounds__(kStBlock) void st_grad(FrameArgs a, const StreamKS*
     yl[tid] = ks->yl[tid];
   }
   __syncthreads();
-  const int p = blockIdx.x * kStBlock + tid;
-  const bool valid = p < a.P;
-  const float wt = valid ? st_weight(a, p) : 0.f;
-  const TS* __restrict__ U = (const TS*)a.U;
-  const TS* __restrict__ X = (const TS*)a.x;
+  const int p0 = (blockIdx.x * kStBlock + tid) * N;
+  const bool valid = p0 < a.P;   // with pairs P is even, so both pixels are
+  float wt[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) wt[i] = valid ? st_weight(a, p0 + i) : 0.f;
   float acc[KC + 1];
 #pragma unroll
   for (int j = 0; j <= KC; ++j) acc[j] = 0.f;
   if (valid)
     for (int c = 0; c < a.C; ++c) {
-      const long long e = (long long)c * a.P + p;
-      float u[KC];
-      float r = ld_elem(X, e), rl = 0.f;
+      float u[N][KC], x[N];
+      st_load<KC, TS, PAIR>(a, c, p0, u, x);
+      const long long e = (long long)c * a.P + p0;
 #pragma unroll
-      for (int j = 0; j < KC; ++j) {
-        u[j] = (j < a.k) ? ld_elem(U, (long long)j * a.ldU + e) : 0.f;
-        r = fmaf(-u[j], ys[j], r);
-        rl = fmaf(-u[j], yl[j], rl);
+      for (int i = 0; i < N; ++i) {
+        const float r = st_residual<KC>(x[i], u[i], ys, yl);
+        float phi, cc;
+        cost_eval(r, a.cp, phi, cc);
+        const float w_c = wt[i] * cc;
+        wc[e + i] = w_c;
+        const float wd = w_c * r;                 // w phi'(r)
+        acc[KC] = fmaf(wt[i], phi, acc[KC]);
+#pragma unroll
+        for (int j = 0; j < KC; ++j) acc[j] = fmaf(wd, u[i][j], acc[j]);
       }
-      r += rl;
-      float phi, cc;
-      cost_eval(r, a.cp, phi, cc);
-      const float w_c = wt * cc;
-      wc[e] = w_c;
-      const float wd = w_c * r;                 // w phi'(r)
-      acc[KC] = fmaf(wt, phi, acc[KC]);
-#pragma unroll
-      for (int j = 0; j < KC; ++j) acc[j] = fmaf(wd, u[j], acc[j]);
     }
   st_block_partials<KC + 1>(acc, red, part);
 }
@@ -219,26 +264,30 @@ __global__ __launch_bounds__(kStRed) void st_direction(FrameArgs a, StreamKS* ks
 }
 
 // Curvature of the majoriser along d: sum w c (u . d)^2.
-template <int KC, typename TS>
+template <int KC, typename TS, bool PAIR>
 __global__ __launch_bounds__(kStBlock) void st_curv(FrameArgs a, const StreamKS* __restrict__ ks,
                                                     const float* __restrict__ wc, double* __restrict__ part) {
+  constexpr int N = StPix<TS, PAIR>::N;
   if (ks->stop || ks->bad) return;
   __shared__ float ds[KC];
   __shared__ double red[kStWaves][kStL];
   const int tid = thread_index();
   if (tid < KC) ds[tid] = ks->df[tid];
   __syncthreads();
-  const int p = blockIdx.x * kStBlock + tid;
-  const TS* __restrict__ U = (const TS*)a.U;
+  const int p0 = (blockIdx.x * kStBlock + tid) * N;
   float acc[1] = {0.f};
-  if (p < a.P)
+  if (p0 < a.P)
     for (int c = 0; c < a.C; ++c) {
-      const long long e = (long long)c * a.P + p;
-      float t = 0.f;
+      float u[N][KC], x[N];
+      st_load<KC, TS, PAIR>(a, c, p0, u, x);   // x unused: the compiler drops its load
+      const long long e = (long long)c * a.P + p0;
 #pragma unroll
-      for (int j = 0; j < KC; ++j)
-        if (j < a.k) t = fmaf(ld_elem(U, (long long)j * a.ldU + e), ds[j], t);
-      acc[0] = fmaf(wc[e] * t, t, acc[0]);
+      for (int i = 0; i < N; ++i) {
+        float t = 0.f;
+#pragma unroll
+        for (int j = 0; j < KC; ++j) t = fmaf(u[i][j], ds[j], t);
+        acc[0] = fmaf(wc[e + i] * t, t, acc[0]);
+      }
     }
   st_block_partials<1>(acc, red, part);
 }
@@ -269,9 +318,10 @@ __global__ __launch_bounds__(kStRed) void st_advance(FrameArgs a, StreamKS* ks, 
 
 // Step 2 eta pass at the final y: eta = -w phi'(r) stored per entry;
 // partials of U^T eta, ||eta||^2 and the final cost.
-template <int KC, typename TS>
+template <int KC, typename TS, bool PAIR>
 __global__ __launch_bounds__(kStBlock) void st_eta(FrameArgs a, const StreamKS* __restrict__ ks, float* __restrict__ eta,
                                                    double* __restrict__ part) {
+  constexpr int N = StPix<TS, PAIR>::N;
   if (ks->bad) return;
   __shared__ float ys[KC], yl[KC];
   __shared__ double red[kStWaves][kStL];
@@ -281,34 +331,31 @@ __global__ __launch_bounds__(kStBlock) void st_eta(FrameArgs a, const StreamKS* 
     yl[tid] = ks->yl[tid];
   }
   __syncthreads();
-  const int p = blockIdx.x * kStBlock + tid;
-  const bool valid = p < a.P;
-  const float wt = valid ? st_weight(a, p) : 0.f;
-  const TS* __restrict__ U = (const TS*)a.U;
-  const TS* __restrict__ X = (const TS*)a.x;
+  const int p0 = (blockIdx.x * kStBlock + tid) * N;
+  const bool valid = p0 < a.P;
+  float wt[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) wt[i] = valid ? st_weight(a, p0 + i) : 0.f;
   float acc[KC + 2];
 #pragma unroll
   for (int j = 0; j < KC + 2; ++j) acc[j] = 0.f;
   if (valid)
     for (int c = 0; c < a.C; ++c) {
-      const long long e = (long long)c * a.P + p;
-      float u[KC];
-      float r = ld_elem(X, e), rl = 0.f;
+      float u[N][KC], x[N];
+      st_load<KC, TS, PAIR>(a, c, p0, u, x);
+      const long long e = (long long)c * a.P + p0;
 #pragma unroll
-      for (int j = 0; j < KC; ++j) {
-        u[j] = (j < a.k) ? ld_elem(U, (long long)j * a.ldU + e) : 0.f;
-        r = fmaf(-u[j], ys[j], r);
-        rl = fmaf(-u[j], yl[j], rl);
+      for (int i = 0; i < N; ++i) {
+        const float r = st_residual<KC>(x[i], u[i], ys, yl);
+        float phi, cc;
+        cost_eval(r, a.cp, phi, cc);
+        const float et = -wt[i] * cc * r;
+        eta[e + i] = et;
+        acc[KC] = fmaf(et, et, acc[KC]);
+        acc[KC + 1] = fmaf(wt[i], phi, acc[KC + 1]);
+#pragma unroll
+        for (int j = 0; j < KC; ++j) acc[j] = fmaf(et, u[i][j], acc[j]);
       }
-      r += rl;
-      float phi, cc;
-      cost_eval(r, a.cp, phi, cc);
-      const float et = -wt * cc * r;
-      eta[e] = et;
-      acc[KC] = fmaf(et, et, acc[KC]);
-      acc[KC + 1] = fmaf(wt, phi, acc[KC + 1]);
-#pragma unroll
-      for (int j = 0; j < KC; ++j) acc[j] = fmaf(et, u[j], acc[j]);
     }
   st_block_partials<KC + 2>(acc, red, part);
 }
@@ -362,9 +409,10 @@ __global__ __launch_bounds__(kStRed) void st_geodesic(FrameArgs a, StreamKS* ks,
 // pass: u <- u + coef v with coef = (cos theta - 1)(u.v) - (sin theta / zeta)
 // (eta - u.a); r' = r - coef nu (r' = x - U' y); label = any channel with
 // |r'| >= delta.
-template <int KC, typename TS>
+template <int KC, typename TS, bool PAIR>
 __global__ __launch_bounds__(kStBlock) void st_update(FrameArgs a, const StreamKS* __restrict__ ks,
                                                       const float* __restrict__ eta) {
+  constexpr int N = StPix<TS, PAIR>::N;
   if (ks->bad) return;
   __shared__ float ys[KC], yl[KC], vs[KC], as[KC];
   const int tid = thread_index();
@@ -375,40 +423,51 @@ __global__ __launch_bounds__(kStBlock) void st_update(FrameArgs a, const StreamK
     as[tid] = ks->af[tid];
   }
   __syncthreads();
-  const int p = blockIdx.x * kStBlock + tid;
-  if (p >= a.P) return;
+  const int p0 = (blockIdx.x * kStBlock + tid) * N;
+  if (p0 >= a.P) return;
   const float cm1 = ks->cm1, sz = ks->sz, nu = ks->nu;
   const bool upd = ks->upd != 0;
-  TS* __restrict__ U = (TS*)a.U;
-  const TS* __restrict__ X = (const TS*)a.x;
-  uint8_t label = 0;
+  uint8_t label[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) label[i] = 0;
   for (int c = 0; c < a.C; ++c) {
-    const long long e = (long long)c * a.P + p;
-    float u[KC];
-    float r = ld_elem(X, e), rl = 0.f;
+    float u[N][KC], x[N];
+    st_load<KC, TS, PAIR>(a, c, p0, u, x);
+    const long long e = (long long)c * a.P + p0;
+    float un[N][KC];
 #pragma unroll
-    for (int j = 0; j < KC; ++j) {
-      u[j] = (j < a.k) ? ld_elem(U, (long long)j * a.ldU + e) : 0.f;
-      r = fmaf(-u[j], ys[j], r);
-      rl = fmaf(-u[j], yl[j], rl);
-    }
-    r += rl;
-    if (upd) {
-      float uv = 0.f, ua = 0.f;
+    for (int i = 0; i < N; ++i) {
+      float r = st_residual<KC>(x[i], u[i], ys, yl);
+      if (upd) {
+        float uv = 0.f, ua = 0.f;
 #pragma unroll
-      for (int j = 0; j < KC; ++j) {
-        uv = fmaf(u[j], vs[j], uv);
-        ua = fmaf(u[j], as[j], ua);
+        for (int j = 0; j < KC; ++j) {
+          uv = fmaf(u[i][j], vs[j], uv);
+          ua = fmaf(u[i][j], as[j], ua);
+        }
+        const float coef = fmaf(cm1, uv, -sz * (eta[e + i] - ua));
+#pragma unroll
+        for (int j = 0; j < KC; ++j) un[i][j] = fmaf(coef, vs[j], u[i][j]);
+        if (a.labels_after_update) r = fmaf(-coef, nu, r);
       }
-      const float coef = fmaf(cm1, uv, -sz * (eta[e] - ua));
-#pragma unroll
-      for (int j = 0; j < KC; ++j)
-        if (j < a.k) st_elem(U, (long long)j * a.ldU + e, fmaf(coef, vs[j], u[j]));
-      if (a.labels_after_update) r = fmaf(-coef, nu, r);
+      if (fabsf(r) >= a.delta) label[i] = 1;
     }
-    if (fabsf(r) >= a.delta) label = 1;
+    if (upd) {
+      if constexpr (PAIR) {
+        uint32_t* __restrict__ U = (uint32_t*)a.U;
+#pragma unroll
+        for (int j = 0; j < KC; ++j)
+          if (j < a.k) U[((long long)j * a.ldU + e) >> 1] = pack_bf16_rne(un[0][j], un[1][j]);
+      } else {
+        TS* __restrict__ U = (TS*)a.U;
+#pragma unroll
+        for (int j = 0; j < KC; ++j)
+          if (j < a.k) st_elem(U, (long long)j * a.ldU + e, un[0][j]);
+      }
+    }
   }
-  a.lab[p] = label;
+#pragma unroll
+  for (int i = 0; i < N; ++i) a.lab[p0 + i] = label[i];
 }
 
 // Frame end: y and the frame counter (an accepted frame only).
@@ -425,36 +484,38 @@ __global__ void st_end(FrameArgs a, const StreamKS* __restrict__ ks) {
   }
 }
 
-template <int KC, typename TS>
+// One frame: nblk workgroups of kStBlock threads, each thread one pixel (or
+// one pixel pair with PAIR).
+template <int KC, typename TS, bool PAIR>
 static void st_frame_launch(const FrameArgs& a, StreamKS* ks, float* wc, float* eta, double* part, int nblk,
                             hipStream_t s) {
   hipLaunchKernelGGL(st_begin, dim3(1), dim3(64), 0, s, a, ks);
   for (int it = 0; it < a.J; ++it) {
-    hipLaunchKernelGGL((st_grad<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, wc, part);
+    hipLaunchKernelGGL((st_grad<KC, TS, PAIR>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, wc, part);
     hipLaunchKernelGGL((st_direction<KC>), dim3(1), dim3(kStRed), 0, s, a, ks, (const double*)part, nblk, it);
-    hipLaunchKernelGGL((st_curv<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks,
+    hipLaunchKernelGGL((st_curv<KC, TS, PAIR>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks,
                        (const float*)wc, part);
     hipLaunchKernelGGL(st_advance, dim3(1), dim3(kStRed), 0, s, a, ks, (const double*)part, nblk, it);
   }
-  hipLaunchKernelGGL((st_eta<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, eta, part);
+  hipLaunchKernelGGL((st_eta<KC, TS, PAIR>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, eta, part);
   hipLaunchKernelGGL((st_geodesic<KC>), dim3(1), dim3(kStRed), 0, s, a, ks, (const double*)part, nblk);
-  hipLaunchKernelGGL((st_update<KC, TS>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks,
+  hipLaunchKernelGGL((st_update<KC, TS, PAIR>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks,
                      (const float*)eta);
   hipLaunchKernelGGL(st_end, dim3(1), dim3(64), 0, s, a, (const StreamKS*)ks);
 }
 
-template <typename TS>
+template <typename TS, bool PAIR>
 static void st_frame_class(int kc, const FrameArgs& a, StreamKS* ks, float* wc, float* eta, double* part, int nblk,
                            hipStream_t s) {
   switch (kc) {
-    case 2: st_frame_launch<2, TS>(a, ks, wc, eta, part, nblk, s); break;
-    case 4: st_frame_launch<4, TS>(a, ks, wc, eta, part, nblk, s); break;
-    case 5: st_frame_launch<5, TS>(a, ks, wc, eta, part, nblk, s); break;
-    case 8: st_frame_launch<8, TS>(a, ks, wc, eta, part, nblk, s); break;
-    case 10: st_frame_launch<10, TS>(a, ks, wc, eta, part, nblk, s); break;
-    case 12: st_frame_launch<12, TS>(a, ks, wc, eta, part, nblk, s); break;
-    case 15: st_frame_launch<15, TS>(a, ks, wc, eta, part, nblk, s); break;
-    default: st_frame_launch<16, TS>(a, ks, wc, eta, part, nblk, s); break;
+    case 2: st_frame_launch<2, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
+    case 4: st_frame_launch<4, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
+    case 5: st_frame_launch<5, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
+    case 8: st_frame_launch<8, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
+    case 10: st_frame_launch<10, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
+    case 12: st_frame_launch<12, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
+    case 15: st_frame_launch<15, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
+    default: st_frame_launch<16, TS, PAIR>(a, ks, wc, eta, part, nblk, s); break;
   }
 }
 
@@ -486,10 +547,17 @@ pros_status prost_stream_frame(pros_handle* h, const prost::FrameArgs& a) {
   float* eta = wc + h->m;
   double* part = (double*)(((uintptr_t)(eta + h->m) + 255) / 256 * 256);
   const int kc = st_class(h->k);
-  if (h->prm.storage == PROS_BF16)
-    st_frame_class<uint16_t>(kc, a, ks, wc, eta, part, h->stream_blocks, h->stream);
-  else
-    st_frame_class<float>(kc, a, ks, wc, eta, part, h->stream_blocks, h->stream);
+  if (h->prm.storage == PROS_BF16) {
+    // pixel pairs: even P and every plane start 4-byte aligned (U's planes
+    // are ldU apart with ldU a multiple of 64; the frame is the caller's)
+    const bool pair = h->P % 2 == 0 && h->ldU % 2 == 0 && ((uintptr_t)a.x & 3u) == 0 && ((uintptr_t)a.U & 3u) == 0;
+    if (pair)
+      st_frame_class<uint16_t, true>(kc, a, ks, wc, eta, part, (h->P / 2 + kStBlock - 1) / kStBlock, h->stream);
+    else
+      st_frame_class<uint16_t, false>(kc, a, ks, wc, eta, part, h->stream_blocks, h->stream);
+  } else {
+    st_frame_class<float, false>(kc, a, ks, wc, eta, part, h->stream_blocks, h->stream);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     h->broken = true;

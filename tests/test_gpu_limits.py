@@ -213,3 +213,64 @@ def test_streamed_free_running_matches_tiles():
         assert n1 == n0 and np.array_equal(U1, U0) and np.array_equal(y1, y0) and np.array_equal(l1, l0)
     say(f"  worst label disagreement over 60 streamed frames: {worst:.4%}")
     assert worst <= 0.005
+
+
+@pytest.mark.parametrize("shape", [(40, 30, 3, 15), (33, 17, 1, 4), (64, 47, 2, 16)])
+def test_streamed_bfloat16_small_frames(shape):
+    """The streamed form in bfloat16 storage, forced on small frames: even P
+    (two adjacent pixels per thread, 32-bit accesses) and odd P (one pixel
+    per thread), against the oracle on bfloat16 inputs."""
+    from test_gpu_precision import _bf16_check, rne_bf16
+    from paper_1302_2073_amd import Tracker
+    W, H, Cc, k = shape
+    spec = V.VideoSpec(W, H, Cc, rank=min(k, 3), seed=70 + W, noise=0.01, fg_kind="rects", fg_count=2,
+                       fg_density=0.1)
+    sv = V.SyntheticVideo(spec)
+    prm = O.Params(W, H, Cc, k=k, mu=1e-3, t_init=5e-3, t_min=1e-4, i_init=20)
+    st = O.initial_state(rne_bf16(V.initial_subspace(prm.m, k, 5)), prm.P)
+    for n in range(4):
+        st, _ = O.track_frame(st, rne_bf16(sv.frame(n)), prm)
+    with Tracker(W, H, Cc, k, **tracker_kwargs(prm, "bf16")) as trk:
+        trk.set_launch(-1)
+        assert trk.launch_info()["sync_mode"] == -1
+        _bf16_check(trk, prm, st, rne_bf16(sv.frame(4)), f"{W}x{H}x{Cc} k={k} streamed")
+
+
+def test_streamed_bfloat16_device_frames_at_both_alignments():
+    """A bfloat16 device frame of the streamed form at a 4-byte aligned
+    address (pixel pairs) and at an odd element offset (one pixel per
+    thread): both steps follow the oracle (y within 1e-4, labels exact
+    outside the guard band) from the same injected state."""
+    import torch
+    from test_gpu_precision import rne_bf16
+    from paper_1302_2073_amd import Tracker
+    from paper_1302_2073_amd.tracker import bf16_bits
+    from gpu_common import GUARD
+    W, H, Cc, k = 64, 48, 3, 10
+    spec = V.VideoSpec(W, H, Cc, rank=3, seed=71, noise=0.01, fg_kind="rects", fg_count=2, fg_density=0.1)
+    sv = V.SyntheticVideo(spec)
+    prm = O.Params(W, H, Cc, k=k, mu=1e-3, i_init=20)
+    st = O.initial_state(rne_bf16(V.initial_subspace(prm.m, k, 6)), prm.P)
+    for n in range(3):
+        st, _ = O.track_frame(st, rne_bf16(sv.frame(n)), prm)
+    x64 = rne_bf16(sv.frame(3))
+    x = torch.from_numpy(bf16_bits(x64).view(np.int16)).cuda().view(torch.bfloat16)
+    for offset in (0, 1):
+        with Tracker(W, H, Cc, k, **tracker_kwargs(prm, "bf16")) as trk:
+            trk.set_launch(-1)
+            trk.set_state(st.U, st.y, st.labels, st.n)
+            U0, y0, l0, n0 = trk.get_state()
+            start = O.State(U0, y0, l0, O.median3x3(l0, prm.height, prm.width), n0)
+            exp, _ = O.track_frame(start, x64, prm)
+            buf = torch.empty(prm.m + 1, dtype=torch.bfloat16, device="cuda")
+            view = buf[offset:offset + prm.m]
+            view.copy_(x)
+            torch.cuda.synchronize()
+            trk.track(view)
+            assert trk.sync() == 0
+            U1, y1, l1, n1 = trk.get_state()
+        band = O.band_pixels(exp.U, x64, exp.y, prm.thr, prm.channels, GUARD)
+        y_rel = np.linalg.norm(y1 - exp.y) / np.linalg.norm(exp.y)
+        say(f"  offset {offset}: y_rel {y_rel:.2e}, labels outside band {int(np.sum((l1 != exp.labels) & ~band))}")
+        assert n1 == exp.n and y_rel <= TOL_Y
+        assert int(np.sum((l1 != exp.labels) & ~band)) == 0
