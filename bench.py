@@ -40,17 +40,20 @@ def pass_bytes(m, k, P, bu, bx, J=5):
     return (J + 3) * m * k * bu + (J + 2) * m * bx + (J + 4) * P
 
 
-def streamed_bytes(m, k, P, bu, bx, J=5):
+def streamed_bytes(m, k, P, bu, bx, J=5, curvature=0):
     """HBM bytes of one frame in the streamed form (frames too large for
     resident register tiles): per CG step the gradient pass reads U, x and
-    the labels and writes w c per entry, the curvature pass reads U and w c;
-    the eta pass reads U, x and the labels and writes eta; the update pass
-    reads U, x and eta, writes U and the labels (4-byte w c and eta)."""
+    the labels and writes w c per entry, the curvature pass reads U and w c
+    (curvature schedule 1: one pass reading U, x and the labels, H reduced
+    with the gradient); the eta pass reads U, x and the labels and writes
+    eta; the update pass reads U, x and eta, writes U and the labels (4-byte
+    w c and eta)."""
     grad = m * k * bu + m * bx + P + 4 * m
     curv = m * k * bu + 4 * m
     eta = m * k * bu + m * bx + P + 4 * m
     upd = 2 * m * k * bu + m * bx + 4 * m + P
-    return J * (grad + curv) + eta + upd
+    step = (m * k * bu + m * bx + P) if curvature == 1 else grad + curv
+    return J * step + eta + upd
 
 
 def kernel_source_hash():
@@ -134,9 +137,10 @@ def run_plain(storage, steps, warmup, pool, curvature=0, cooperative=1):
                 cg_steps=stats["cg_steps"], spread_ms=[round(lo, 3), round(hi, 3)])
 
 
-def run_streamed(storage, steps, warmup, pool=4, width=1280, height=720):
+def run_streamed(storage, steps, warmup, pool=4, width=1280, height=720, curvature=None):
     """One stream of frames beyond the resident register tiles (1280x720x3,
-    k = 15): the streamed form, one launch per dependent pass."""
+    k = 15): the streamed form, one launch per dependent pass (curvature:
+    the CG curvature schedule, None = the handle's default)."""
     import torch
     from paper_1302_2073_amd import Tracker
     from synth import video as V
@@ -149,6 +153,8 @@ def run_streamed(storage, steps, warmup, pool=4, width=1280, height=720):
         frames = frames.to(torch.bfloat16)
     frames = frames.contiguous()
     trk = Tracker(width, height, CH, K, mu=1e-3, storage=storage, seed=11)
+    if curvature is not None:
+        trk.set_curvature(curvature)
     info = trk.launch_info()
     if info["sync_mode"] != -1:
         raise RuntimeError(f"{width}x{height}x{CH} is not streamed: {info}")
@@ -165,10 +171,11 @@ def run_streamed(storage, steps, warmup, pool=4, width=1280, height=720):
     m, P = width * height * CH, width * height
     bu = bx = 4 if storage == "f32" else 2
     per = ms / steps
+    sb = streamed_bytes(m, K, P, bu, bx, curvature=info["curvature"])
     return {"fps": round(steps / (ms / 1e3), 1), "ms_per_frame": round(per, 5),
             "alg_GBps": round(alg_bytes(m, K, P, bu, bx) / (per * 1e-3) / 1e9, 1),
-            "streamed_bytes_per_frame": streamed_bytes(m, K, P, bu, bx),
-            "streamed_GBps": round(streamed_bytes(m, K, P, bu, bx) / (per * 1e-3) / 1e9, 1),
+            "streamed_bytes_per_frame": sb,
+            "streamed_GBps": round(sb / (per * 1e-3) / 1e9, 1),
             "launch": info, "spread_ms": [round(lo, 3), round(hi, 3)],
             "workload": f"{width}x{height}x{CH}, k = {K}, {storage}, one stream"}
 
@@ -603,14 +610,16 @@ def main():
         plain = run_plain("f32", args.steps * 4, args.warmup, args.pool)
         achieved = record("plain_f32", plain, 4, 4)
     for storage in ("f32", "bf16"):
-        name = f"streamed_{storage}_1280x720"
-        if name in want:
-            try:
-                forms[name] = run_streamed(storage, max(args.steps // 4, 10), min(args.warmup, 5))
-                forms[name]["note"] = ("frames beyond the resident register tiles: one launch per dependent "
-                                       "pass, U and x read from HBM in every pass")
-            except Exception as exc:
-                forms[name] = {"error": repr(exc)[:300]}
+        for curv, suffix in ((None, ""), (0, "_curv0"), (1, "_curv1")):
+            name = f"streamed_{storage}_1280x720{suffix}"
+            if name in want:
+                try:
+                    forms[name] = run_streamed(storage, max(args.steps // 4, 10), min(args.warmup, 5),
+                                               curvature=curv)
+                    forms[name]["note"] = ("frames beyond the resident register tiles: one launch per dependent "
+                                           "pass, U and x read from HBM in every pass")
+                except Exception as exc:
+                    forms[name] = {"error": repr(exc)[:300]}
     if "plain_f32_curv1" in want:
         try:
             curv = run_plain("f32", args.steps * 4, args.warmup, args.pool, curvature=1)

@@ -182,8 +182,7 @@ PROS_API pros_status pros_validate(const pros_params* prm);
  * pass (pros_get_launch_info reports sync_mode -1); it has the default
  * features only, so pre-processing (preprocess = 1) or the IRLS step
  * (ysolve = 2) with such a frame gives PROS_EUNSUPPORTED, before any
- * allocation, as do pros_set_launch, pros_set_curvature and
- * pros_set_score_output on a streamed handle. */
+ * allocation, as does pros_set_score_output on a streamed handle. */
 PROS_API pros_status pros_init(const pros_params* prm, void* hip_stream, pros_handle** out);
 
 /* Release all device memory of the handle (waits for its stream).  NULL is
@@ -496,7 +495,9 @@ PROS_API pros_status pros_batch_set_dispatch(pros_batch* b, int32_t cooperative)
  * method: the two agree to float32 rounding of the sums.  Schedule 1 needs
  * float32 storage (PROS_EUNSUPPORTED otherwise) and a tagged exchange
  * (sync_mode 1..3).  The IRLS solver (ysolve = 2) always reduces H.
- * Synchronises; the tile (rows per thread) is kept. */
+ * Synchronises; the tile (rows per thread) is kept.  On a streamed handle
+ * (frames beyond the resident tiles) both schedules are available in either
+ * storage type: schedule 1 reads U once per CG step instead of twice. */
 PROS_API pros_status pros_set_curvature(pros_handle* h, int32_t schedule);
 
 /* ---------------------------------------------------------------------------

@@ -265,10 +265,11 @@ static pros_status choose_launch(pros_handle* h, int force_nr) {
   if (!best) {
     // no resident gang holds the frame's register tiles: stream every pass
     // (default features only; the optional features need the tile kernels)
-    if (force_nr > 0 || ext)
+    const bool stream_ok = h->prm.preprocess == 0 && h->score == nullptr && h->prm.ysolve != 2;
+    if (force_nr > 0 || !stream_ok)
       return fail(PROS_EUNSUPPORTED,
                   "frame of %d pixels x %d channels at k=%d does not fit the device's resident workgroups%s", h->P,
-                  h->C, h->k, ext ? " (its streamed form has no pre-processing, scores, IRLS or curvature schedule 1)" : "");
+                  h->C, h->k, stream_ok ? "" : " (its streamed form has no pre-processing, scores or IRLS step)");
     h->streamed = true;
     h->kfn = nullptr;
     h->NR = 0;
@@ -766,8 +767,8 @@ pros_status pros_set_launch(pros_handle* h, int32_t rows_per_thread, int32_t syn
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
   if (rows_per_thread == -1) {   // the streamed form, whatever the frame's size
-    if (h->prm.preprocess || h->score || wide_exchange(h))
-      return fail(PROS_EUNSUPPORTED, "the streamed form has no pre-processing, scores, IRLS or curvature schedule 1");
+    if (h->prm.preprocess || h->score || h->prm.ysolve == 2)
+      return fail(PROS_EUNSUPPORTED, "the streamed form has no pre-processing, scores or IRLS step");
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (!h->stream_ws) {
       st = prost_stream_alloc(h);
@@ -811,8 +812,12 @@ pros_status pros_set_dispatch(pros_handle* h, int32_t cooperative) {
 pros_status pros_set_curvature(pros_handle* h, int32_t schedule) {
   pros_status st = check_usable(h);
   if (st != PROS_OK) return st;
-  if (h->streamed) return fail(PROS_EUNSUPPORTED, "the frame is streamed (it does not fit resident register tiles)");
   if (schedule != 0 && schedule != 1) return fail(PROS_EINVAL, "curvature schedule must be 0 or 1");
+  if (h->streamed) {   // one launch per pass: both schedules, any storage, no exchange slots
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->curv = schedule;
+    return PROS_OK;
+  }
   if (schedule == 1 && h->prm.storage != PROS_F32)
     return fail(PROS_EUNSUPPORTED, "curvature schedule 1 needs float32 storage");
   if (schedule == 1 && h->sync_mode == 0)

@@ -28,6 +28,10 @@ constexpr int kStBlock = 256;           // pixels per workgroup of a pass: one t
 constexpr int kStWaves = kStBlock / 64;
 constexpr int kStRed = 1024;            // threads of the reducing (k-space) kernels
 constexpr int kStL = kMaxK + 2;         // partials per workgroup: up to K values and two scalars
+constexpr int kStWide = 160;            // schedule 1: g (K), f and H's upper triangle (<= 153 values)
+template <int KC>
+constexpr int st_nh() { return KC + 1 + KC * (KC + 1) / 2; }
+static_assert(st_nh<kMaxK>() <= kStWide, "wide partial vector");
 
 // k-space state of the frame being streamed (device memory, one per handle).
 struct StreamKS {
@@ -37,6 +41,7 @@ struct StreamKS {
   float df[kMaxK], vf[kMaxK], af[kMaxK];
   float cm1, sz, nu;
   int stop, bad, upd, steps, restarts;
+  double htot[kStWide];   // curvature schedule 1: reduced g, f and upper triangle of H
 };
 
 // Workgroup sum of L float partials per thread into part[blk * kStL + q]
@@ -215,7 +220,68 @@ __global__ __launch_bounds__(kStBlock) void st_grad(FrameArgs a, const StreamKS*
   st_block_partials<KC + 1>(acc, red, part);
 }
 
-// Reduced gradient and cost -> PR+ direction (the frame kernel's k-space step).
+// PR+ direction from the reduced gradient and cost tot[0..KC] (the frame
+// kernel's k-space step), by the first wavefront; d, its float32 copy, the
+// previous gradient, g.d and the stop / bad flags land in ks.
+template <int KC>
+__device__ __forceinline__ void st_dir_core(const FrameArgs& a, StreamKS* ks, const double* tot, int it) {
+  const int lane = threadIdx.x;
+  const double g = (lane < a.k) ? -tot[lane] : 0.0;
+  const double f = tot[KC];
+  const double gg = row16_sum(g * g);
+  int stop = 0, bad = 0;
+  if (it == 0 && !(isfinite(f) && isfinite(gg))) stop = bad = 1;
+  if (gg == 0.0) stop = 1;
+  double beta = 0.0, dj = -g;
+  if (!stop && it > 0 && a.ysolve == 0) {
+    const double gpv = (lane < a.k) ? ks->gp[lane] : 0.0;
+    const double num = row16_sum(g * (g - gpv));
+    const double den = row16_sum(gpv * gpv);
+    beta = fmax(0.0, num / den);
+    const double dpv = (lane < a.k) ? ks->dp[lane] : 0.0;
+    dj = -g + beta * dpv;
+    if (row16_sum(g * dj) >= 0.0) {
+      dj = -g;
+      if (lane == 0) ++ks->restarts;
+    }
+  }
+  const double gd = row16_sum(g * dj);
+  if (lane < kMaxK) {
+    ks->d[lane] = (lane < a.k) ? dj : 0.0;
+    ks->df[lane] = (lane < a.k) ? (float)dj : 0.f;
+    ks->gp[lane] = (lane < a.k) ? g : 0.0;
+  }
+  if (lane == 0) {
+    a.stats->f[it] = f;
+    a.stats->beta[it] = beta;
+    ks->gd = gd;
+    ks->stop = stop;
+    if (bad) {
+      ks->bad = 1;
+      __hip_atomic_fetch_or(&a.sync[2], kErrBadFrame, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Majoriser step alpha = -g.d / d^T H d, y += alpha d (stop if d^T H d <= 0).
+__device__ __forceinline__ void st_adv_core(const FrameArgs& a, StreamKS* ks, double dHd, int it) {
+  const int t = threadIdx.x;
+  if (!(dHd > 0.0)) {
+    if (t == 0) ks->stop = 1;
+    return;
+  }
+  const double alpha = -ks->gd / dHd;
+  if (t < kMaxK) {
+    st_set_y(ks, t, ks->y[t] + alpha * ks->d[t]);
+    ks->dp[t] = ks->d[t];
+  }
+  if (t == 0) {
+    a.stats->alpha[it] = alpha;
+    ks->steps = it + 1;
+  }
+}
+
+// Reduced gradient and cost -> PR+ direction (curvature schedule 0).
 template <int KC>
 __global__ __launch_bounds__(kStRed) void st_direction(FrameArgs a, StreamKS* ks, const double* __restrict__ part,
                                                        int nblk, int it) {
@@ -223,44 +289,7 @@ __global__ __launch_bounds__(kStRed) void st_direction(FrameArgs a, StreamKS* ks
   __shared__ double grp[kStRed];
   __shared__ double tot[32];
   st_sum_partials<KC + 1>(part, nblk, grp, tot);
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    const double g = (lane < a.k) ? -tot[lane] : 0.0;
-    const double f = tot[KC];
-    const double gg = row16_sum(g * g);
-    int stop = 0, bad = 0;
-    if (it == 0 && !(isfinite(f) && isfinite(gg))) stop = bad = 1;
-    if (gg == 0.0) stop = 1;
-    double beta = 0.0, dj = -g;
-    if (!stop && it > 0 && a.ysolve == 0) {
-      const double gpv = (lane < a.k) ? ks->gp[lane] : 0.0;
-      const double num = row16_sum(g * (g - gpv));
-      const double den = row16_sum(gpv * gpv);
-      beta = fmax(0.0, num / den);
-      const double dpv = (lane < a.k) ? ks->dp[lane] : 0.0;
-      dj = -g + beta * dpv;
-      if (row16_sum(g * dj) >= 0.0) {
-        dj = -g;
-        if (lane == 0) ++ks->restarts;
-      }
-    }
-    const double gd = row16_sum(g * dj);
-    if (lane < kMaxK) {
-      ks->d[lane] = (lane < a.k) ? dj : 0.0;
-      ks->df[lane] = (lane < a.k) ? (float)dj : 0.f;
-      ks->gp[lane] = (lane < a.k) ? g : 0.0;
-    }
-    if (lane == 0) {
-      a.stats->f[it] = f;
-      a.stats->beta[it] = beta;
-      ks->gd = gd;
-      ks->stop = stop;
-      if (bad) {
-        ks->bad = 1;
-        __hip_atomic_fetch_or(&a.sync[2], kErrBadFrame, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-  }
+  if (threadIdx.x < 64) st_dir_core<KC>(a, ks, tot, it);
 }
 
 // Curvature of the majoriser along d: sum w c (u . d)^2.
@@ -299,21 +328,121 @@ __global__ __launch_bounds__(kStRed) void st_advance(FrameArgs a, StreamKS* ks, 
   __shared__ double grp[kStRed];
   __shared__ double tot[32];
   st_sum_partials<1>(part, nblk, grp, tot);
-  const double dHd = tot[0];
-  if (!(dHd > 0.0)) {
-    if (threadIdx.x == 0) ks->stop = 1;
-    return;
+  st_adv_core(a, ks, tot[0], it);
+}
+
+// Curvature schedule 1 (d^T H d from the reduced matrix H): one pass per CG
+// step reduces g, f and the upper triangle of H = U^T diag(w c) U together
+// (k (k + 1) / 2 more products per entry), so the curvature pass and its
+// launches drop out.  Partials value-major: part[v * nblk + workgroup].
+template <int KC, typename TS, bool PAIR>
+__global__ __launch_bounds__(kStBlock) void st_gradh(FrameArgs a, const StreamKS* __restrict__ ks,
+                                                     double* __restrict__ part, int nblk) {
+  constexpr int N = StPix<TS, PAIR>::N;
+  constexpr int NV = st_nh<KC>();
+  if (ks->stop || ks->bad) return;
+  __shared__ float ys[KC], yl[KC];
+  __shared__ double red[kStWaves][NV];
+  const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
+  if (tid < KC) {
+    ys[tid] = ks->yf[tid];
+    yl[tid] = ks->yl[tid];
   }
-  const double alpha = -ks->gd / dHd;
-  const int t = threadIdx.x;
-  if (t < kMaxK) {
-    st_set_y(ks, t, ks->y[t] + alpha * ks->d[t]);
-    ks->dp[t] = ks->d[t];
+  __syncthreads();
+  const int p0 = (blockIdx.x * kStBlock + tid) * N;
+  const bool valid = p0 < a.P;
+  float wt[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) wt[i] = valid ? st_weight(a, p0 + i) : 0.f;
+  float acc[NV];   // g (KC), f, H upper triangle row by row
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.f;
+  if (valid)
+    for (int c = 0; c < a.C; ++c) {
+      float u[N][KC], x[N];
+      st_load<KC, TS, PAIR>(a, c, p0, u, x);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const float r = st_residual<KC>(x[i], u[i], ys, yl);
+        float phi, cc;
+        cost_eval(r, a.cp, phi, cc);
+        const float w_c = wt[i] * cc;
+        const float wd = w_c * r;                 // w phi'(r)
+        acc[KC] = fmaf(wt[i], phi, acc[KC]);
+#pragma unroll
+        for (int j = 0; j < KC; ++j) acc[j] = fmaf(wd, u[i][j], acc[j]);
+        int q = KC + 1;
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+          const float tj = w_c * u[i][j];
+#pragma unroll
+          for (int l = j; l < KC; ++l) {
+            acc[q] = fmaf(tj, u[i][l], acc[q]);
+            ++q;
+          }
+        }
+      }
+    }
+  // workgroup sums in chunks of 32 values (fixed order, float64 across wavefronts)
+#pragma unroll
+  for (int c0 = 0; c0 < NV; c0 += 32) {
+    float ch[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) ch[q] = (c0 + q < NV) ? acc[(c0 + q < NV) ? c0 + q : 0] : 0.f;
+    int comp;
+    const float v = wave_reduce_scatter<32>(ch, comp);
+    if ((lane & 1) == 0 && c0 + comp < NV) red[wv][c0 + comp] = (double)v;
   }
-  if (t == 0) {
-    a.stats->alpha[it] = alpha;
-    ks->steps = it + 1;
+  __syncthreads();
+  for (int q = tid; q < NV; q += kStBlock) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kStWaves; ++w) sum += red[w][q];
+    part[(size_t)q * nblk + blockIdx.x] = sum;
   }
+}
+
+// Sum of value v's partials over the nblk workgroups (one workgroup per
+// value, fixed order) into ks->htot[v].
+__global__ __launch_bounds__(256) void st_hsum(StreamKS* ks, const double* __restrict__ part, int nblk) {
+  if (ks->stop || ks->bad) return;
+  __shared__ double red[4];
+  const int v = blockIdx.x, t = threadIdx.x;
+  const double* row = part + (size_t)v * nblk;
+  double s = 0.0;
+  for (int b = t; b < nblk; b += 256) s += row[b];
+  s = wave_sum(s);
+  if ((t & 63) == 0) red[t >> 6] = s;
+  __syncthreads();
+  if (t == 0) ks->htot[v] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Direction and majoriser step of schedule 1: d^T H d from the reduced H.
+template <int KC>
+__global__ __launch_bounds__(64) void st_step(FrameArgs a, StreamKS* ks, int it) {
+  if (ks->stop || ks->bad) return;
+  __shared__ double tot[st_nh<KC>()];
+  __shared__ double dsh[KC];
+  for (int q = threadIdx.x; q < st_nh<KC>(); q += 64) tot[q] = ks->htot[q];
+  __syncthreads();
+  st_dir_core<KC>(a, ks, tot, it);
+  __syncthreads();
+  if (ks->stop || ks->bad) return;
+  if (threadIdx.x < KC) dsh[threadIdx.x] = ks->d[threadIdx.x];
+  __syncthreads();
+  // row i of the triangle by lane i, rows added in order
+  __shared__ double rowsum[KC];
+  const int i = threadIdx.x;
+  if (i < KC) {
+    int q = KC + 1 + i * KC - i * (i - 1) / 2;   // H[i][i]
+    double sacc = tot[q] * dsh[i] * dsh[i];
+    for (int l = i + 1; l < KC; ++l) sacc += 2.0 * tot[++q] * dsh[i] * dsh[l];
+    rowsum[i] = sacc;
+  }
+  __syncthreads();
+  double dHd = 0.0;
+  for (int r = 0; r < KC; ++r) dHd += rowsum[r];
+  st_adv_core(a, ks, dHd, it);
 }
 
 // Step 2 eta pass at the final y: eta = -w phi'(r) stored per entry;
@@ -485,12 +614,20 @@ __global__ void st_end(FrameArgs a, const StreamKS* __restrict__ ks) {
 }
 
 // One frame: nblk workgroups of kStBlock threads, each thread one pixel (or
-// one pixel pair with PAIR).
+// one pixel pair with PAIR).  a.curv selects the CG curvature schedule: 0,
+// d^T H d from a second pass over U per step; 1, H reduced with the gradient.
 template <int KC, typename TS, bool PAIR>
 static void st_frame_launch(const FrameArgs& a, StreamKS* ks, float* wc, float* eta, double* part, int nblk,
                             hipStream_t s) {
   hipLaunchKernelGGL(st_begin, dim3(1), dim3(64), 0, s, a, ks);
   for (int it = 0; it < a.J; ++it) {
+    if (a.curv == 1) {
+      hipLaunchKernelGGL((st_gradh<KC, TS, PAIR>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, part,
+                         nblk);
+      hipLaunchKernelGGL(st_hsum, dim3(st_nh<KC>()), dim3(256), 0, s, ks, (const double*)part, nblk);
+      hipLaunchKernelGGL((st_step<KC>), dim3(1), dim3(64), 0, s, a, ks, it);
+      continue;
+    }
     hipLaunchKernelGGL((st_grad<KC, TS, PAIR>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks, wc, part);
     hipLaunchKernelGGL((st_direction<KC>), dim3(1), dim3(kStRed), 0, s, a, ks, (const double*)part, nblk, it);
     hipLaunchKernelGGL((st_curv<KC, TS, PAIR>), dim3(nblk), dim3(kStBlock), 0, s, a, (const StreamKS*)ks,
@@ -530,7 +667,8 @@ static int st_class(int k) {
 pros_status prost_stream_alloc(pros_handle* h) {
   using namespace prost;
   const int nblk = (h->P + kStBlock - 1) / kStBlock;
-  const size_t bytes = sizeof(StreamKS) + 2 * sizeof(float) * (size_t)h->m + sizeof(double) * (size_t)nblk * kStL + 1024;
+  const size_t bytes = sizeof(StreamKS) + 2 * sizeof(float) * (size_t)h->m + sizeof(double) * (size_t)nblk * kStWide +
+                       1024;
   hipError_t e = hipMalloc(&h->stream_ws, bytes);
   if (e != hipSuccess) return prost_host::set_error(PROS_ENOMEM, "streamed-frame buffers: %s", hipGetErrorString(e));
   e = hipMemsetAsync(h->stream_ws, 0, bytes, h->stream);

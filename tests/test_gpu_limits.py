@@ -87,11 +87,12 @@ def test_largest_bfloat16_frame_matches_the_oracle():
         _bf16_check(trk, prm, st, rne_bf16(sv.frame(1)), f"640x{H}x3")
 
 
-def _streamed_step(prm, st, x64, storage="f32", force=False):
+def _streamed_step(prm, st, x64, storage="f32", force=False, curvature=0):
     from paper_1302_2073_amd import Tracker
     with Tracker(prm.width, prm.height, prm.channels, prm.k, **tracker_kwargs(prm, storage)) as trk:
         if force:
             trk.set_launch(-1)
+        trk.set_curvature(curvature)
         info = trk.launch_info()
         assert info["sync_mode"] == -1, info
         say(f"  streamed {prm.width}x{prm.height}x{prm.channels} k={prm.k}: {info}")
@@ -106,17 +107,18 @@ def test_one_row_beyond_the_resident_size_is_streamed():
     assert_parity(rep)
 
 
-@pytest.mark.parametrize("n", [0, 150])
-def test_streamed_1280x720_float32(n):
+@pytest.mark.parametrize("n,curvature", [(0, 0), (150, 0), (150, 1)])
+def test_streamed_1280x720_float32(n, curvature):
     """1280x720x3 at k = 15 (four times the 640x480 frame, beyond the
     resident register tiles) against the oracle, before and after the
-    initialization phase of the step-size rule."""
+    initialization phase of the step-size rule, with either curvature
+    schedule of the CG step."""
     spec = V.VideoSpec(1280, 720, 3, rank=10, seed=7, noise=0.01, fg_kind="rects", fg_count=3, fg_density=0.05,
                        speed=(1.0, 2.0))
     prm = O.Params(1280, 720, 3, k=15, mu=1e-3)
     sv, st = _start_state(prm, spec, 1)
     st.n = n
-    rep = _streamed_step(prm, st, f32(sv.frame(1)))
+    rep = _streamed_step(prm, st, f32(sv.frame(1)), curvature=curvature)
     assert_parity(rep)
 
 
@@ -139,10 +141,11 @@ def test_streamed_1280x720_bfloat16():
 
 @pytest.mark.parametrize("cost", ["lp", "log"])
 @pytest.mark.parametrize("shape", [(7, 5, 3, 4), (33, 17, 1, 1), (123, 77, 3, 9), (41, 29, 2, 16), (1, 9, 3, 2)])
-def test_streamed_form_on_small_frames(shape, cost):
+@pytest.mark.parametrize("curvature", [0, 1])
+def test_streamed_form_on_small_frames(shape, cost, curvature):
     """The streamed form forced on small ragged frames (partial last
-    workgroup, k = 1 and k = 16, 1-3 channels, both cost forms) against the
-    oracle."""
+    workgroup, k = 1 and k = 16, 1-3 channels, both cost forms, both
+    curvature schedules) against the oracle."""
     W, H, Cc, k = shape
     spec = V.VideoSpec(W, H, Cc, rank=min(k, 3), seed=90 + W, noise=0.01, fg_kind="rects", fg_count=2,
                        fg_density=0.1)
@@ -151,7 +154,7 @@ def test_streamed_form_on_small_frames(shape, cost):
     st = O.initial_state(V.initial_subspace(prm.m, k, 3), prm.P)
     for n in range(6):
         st, _ = O.track_frame(st, f32(sv.frame(n)), prm)
-    rep = _streamed_step(prm, st, f32(sv.frame(6)), force=True)
+    rep = _streamed_step(prm, st, f32(sv.frame(6)), force=True, curvature=curvature)
     from paper_1302_2073_amd import Tracker
     with Tracker(W, H, Cc, k, **tracker_kwargs(prm)) as trk:   # the register-tile kernel on the same frame
         tiles = compare_step(trk, prm, st, f32(sv.frame(6)))
@@ -216,10 +219,12 @@ def test_streamed_free_running_matches_tiles():
 
 
 @pytest.mark.parametrize("shape", [(40, 30, 3, 15), (33, 17, 1, 4), (64, 47, 2, 16)])
-def test_streamed_bfloat16_small_frames(shape):
+@pytest.mark.parametrize("curvature", [0, 1])
+def test_streamed_bfloat16_small_frames(shape, curvature):
     """The streamed form in bfloat16 storage, forced on small frames: even P
     (two adjacent pixels per thread, 32-bit accesses) and odd P (one pixel
-    per thread), against the oracle on bfloat16 inputs."""
+    per thread), both curvature schedules, against the oracle on bfloat16
+    inputs."""
     from test_gpu_precision import _bf16_check, rne_bf16
     from paper_1302_2073_amd import Tracker
     W, H, Cc, k = shape
@@ -232,8 +237,9 @@ def test_streamed_bfloat16_small_frames(shape):
         st, _ = O.track_frame(st, rne_bf16(sv.frame(n)), prm)
     with Tracker(W, H, Cc, k, **tracker_kwargs(prm, "bf16")) as trk:
         trk.set_launch(-1)
+        trk.set_curvature(curvature)
         assert trk.launch_info()["sync_mode"] == -1
-        _bf16_check(trk, prm, st, rne_bf16(sv.frame(4)), f"{W}x{H}x{Cc} k={k} streamed")
+        _bf16_check(trk, prm, st, rne_bf16(sv.frame(4)), f"{W}x{H}x{Cc} k={k} streamed, schedule {curvature}")
 
 
 def test_streamed_bfloat16_device_frames_at_both_alignments():
