@@ -8,9 +8,13 @@
 //   direction:   fixed-order sum of the partials, PR+ direction d
 //   curvature:   partials of sum w c (u . d)^2 (the majoriser's d^T H d)
 //   advance:     alpha = -g.d / d^T H d, y += alpha d
-// then (Step 2) the eta pass (eta = -w phi'(r) stored per entry, partials of
-// U^T eta, ||eta||^2 and the final cost), the geodesic scalars, and one pass
-// that updates U and labels every pixel (Step 3).  Reductions: float32 per
+// (curvature schedule 1 instead: one pass reduces g, f and the upper
+// triangle of H = U^T diag(w c) U, and one kernel forms d, d^T H d and the
+// step), then (Step 2) the eta pass (eta = -w phi'(r) stored per entry,
+// partials of U^T eta, ||eta||^2 and the final cost), the geodesic scalars,
+// and one pass that updates U and labels every pixel (Step 3).  A thread
+// takes one pixel (all channels), or two adjacent ones in bfloat16 storage
+// with even P and aligned planes (32-bit accesses).  Reductions: float32 per
 // thread, float64 per workgroup and across workgroups in a fixed order, so
 // results are deterministic.
 #include <hip/hip_runtime.h>
@@ -24,7 +28,7 @@
 
 namespace prost {
 
-constexpr int kStBlock = 256;           // pixels per workgroup of a pass: one thread per pixel, all channels
+constexpr int kStBlock = 256;           // threads per workgroup of a pass (one pixel or pixel pair each)
 constexpr int kStWaves = kStBlock / 64;
 constexpr int kStRed = 1024;            // threads of the reducing (k-space) kernels
 constexpr int kStL = kMaxK + 2;         // partials per workgroup: up to K values and two scalars
@@ -35,7 +39,7 @@ static_assert(st_nh<kMaxK>() <= kStWide, "wide partial vector");
 
 // k-space state of the frame being streamed (device memory, one per handle).
 struct StreamKS {
-  double y[kMaxK], g[kMaxK], gp[kMaxK], d[kMaxK], dp[kMaxK], a[kMaxK];
+  double y[kMaxK], gp[kMaxK], d[kMaxK], dp[kMaxK];   // y, previous gradient, direction, previous direction
   double gd;
   float yf[kMaxK], yl[kMaxK];   // y as float32 plus its float32 remainder: r = x - U yf - U yl
   float df[kMaxK], vf[kMaxK], af[kMaxK];
