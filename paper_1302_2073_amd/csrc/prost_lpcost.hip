@@ -89,6 +89,9 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_fwd_kernel(const float* __res
   __shared__ __align__(16) float uT[K][kLpPad];
   __shared__ float ys[CH][K];
   __shared__ double red[kLpWaves][CH];
+  // A run-time form here: with the form a compile-time constant the compiler
+  // hoists every frame's LDS reads of y ahead of the arithmetic and needs
+  // 256 VGPRs (one wavefront per SIMD, 2x slower); the backward gains from it.
   const CostParams cp = make_cp(form, p, *mu_p);
   const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
   const int nblk = gridDim.x;
@@ -144,10 +147,10 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_fwd_kernel(const float* __res
 // formed from LDS, one output per thread, rows in order.  Frame entries are
 // prefetched eight frames ahead as in the forward kernel.  Partials
 // (output q = b K + j of dY, then dmu at q = B K): part[q * nblk + workgroup].
-template <int K>
+template <int K, int FORM>
 __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __restrict__ U, const float* __restrict__ Y,
                                                               const float* __restrict__ X, const float* __restrict__ w,
-                                                              int m, int B, int form, float p, const float* __restrict__ mu_p,
+                                                              int m, int B, float p, const float* __restrict__ mu_p,
                                                               const float* __restrict__ gout, float* __restrict__ dX,
                                                               float* __restrict__ dU, double* __restrict__ part) {
   constexpr int CH = kLpChunkB;
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_bwd_kernel(const float* __res
   __shared__ double redm[kLpWaves];
   __shared__ double dyw[kLpWaves][16][17];   // per-wavefront dY tiles [frame][j]
   static_assert(CH == 16 && K <= 16 && kLpBlock == 64 * kLpWaves, "one 16 x 16 tile per wavefront");
-  const CostParams cp = make_cp(form, p, *mu_p);
+  const CostParams cp = make_cp(FORM, p, *mu_p);   // the form is a compile-time constant: no per-entry branch
   const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
   const int nblk = gridDim.x;
   const long long e0 = (long long)blockIdx.x * kLpBlock;
@@ -367,8 +370,12 @@ static pros_status lp_bwd_launch(const float* U, const float* Y, const float* X,
                                  float* dX, float* dU, float* dY, float* dmu, double* part, hipStream_t s) {
   const int nblk = lp_blocks(m);
   const int form = (cost == PROS_COST_LOG) ? 1 : 0;
-  PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_bwd_kernel<KK>), dim3(nblk), dim3(kLpBlock), 0, s, U, Y, X, w, m, B,
-                                       form, p, mu, gout, dX, dU, part));
+  if (form)
+    PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_bwd_kernel<KK, 1>), dim3(nblk), dim3(kLpBlock), 0, s, U, Y, X, w, m,
+                                         B, p, mu, gout, dX, dU, part))
+  else
+    PROST_K_SWITCH(k, hipLaunchKernelGGL((lpcost_bwd_kernel<KK, 0>), dim3(nblk), dim3(kLpBlock), 0, s, U, Y, X, w, m,
+                                         B, p, mu, gout, dX, dU, part))
   if (dY || dmu) {
     const int n = B * k + 1;
     hipLaunchKernelGGL(lpcost_finish, dim3(n), dim3(256), 0, s, (const double*)part, nblk, n, B * k, dY, dmu);
