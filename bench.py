@@ -180,6 +180,41 @@ def run_streamed(storage, steps, warmup, pool=4, width=1280, height=720, curvatu
             "workload": f"{width}x{height}x{CH}, k = {K}, {storage}, one stream"}
 
 
+def run_plain_workload(name, steps, warmup, pool=8):
+    """One float32 stream of a smaller workload (80x60x1 k=5 or 320x240x3
+    k=10) in the automatic launch: frames per second of single launches and
+    of 64-frame sequences."""
+    import torch
+    from paper_1302_2073_amd import Tracker
+    from synth import video as V
+    wl = {"80x60": V.small_gray, "320x240": V.qvga_rgb}[name]()
+    v = wl.video
+    sv = V.SyntheticVideo(v)
+    frames = torch.from_numpy(np.stack([sv.frame(n) for n in range(pool)]).astype(np.float32)).cuda()
+    kw = dict(mu=wl.mu) if wl.delta is None else dict(mu=wl.mu, delta=wl.delta)
+    trk = Tracker(v.width, v.height, v.channels, wl.k, **kw)
+    trk.set_state(V.initial_subspace(trk.m, wl.k, v.seed))
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        trk.track(frames[i % pool])
+    torch.cuda.synchronize()
+    ms, lo, hi = timed_median(lambda i: trk.track(frames[i % pool]), steps, stream)
+    seq = [frames[i % pool] for i in range(64)]
+    trk.track_many(seq)
+    torch.cuda.synchronize()
+    n_calls = max(steps // 64, 2)
+    ms_seq, _, _ = timed_median(lambda i: trk.track_many(seq), n_calls, stream)
+    st = trk.sync()
+    info = trk.launch_info()
+    trk.close()
+    if st != 0:
+        raise RuntimeError(f"tracker error {st}")
+    return {"fps": round(steps / (ms / 1e3), 1), "us_per_frame": round(1e3 * ms / steps, 2),
+            "seq64_fps": round(64 * n_calls / (ms_seq / 1e3), 1),
+            "seq64_us_per_frame": round(1e3 * ms_seq / (64 * n_calls), 2), "launch": info,
+            "spread_ms": [round(lo, 3), round(hi, 3)], "workload": f"{wl.name}, float32, one stream"}
+
+
 def run_plain_seq(storage, steps, warmup, pool, chunk=64):
     """One stream fed buffered sequences (pros_track_frames): `chunk` frames
     per call, up to 256 per kernel launch, the U tile kept in registers
@@ -570,7 +605,8 @@ def main():
     # also available: plain_f32_curv1, plain_f32_ordinary, batched_bf16_ordinary
     ap.add_argument("--forms", default="plain_f32,plain_f32_seq,plain_bf16,plain_bf16_seq,plain_f32_host,"
                     "batched_bf16,batched_bf16_seq,batched_mixed_bf16,batched_mixed_bf16_seq,lpcost,"
-                    "quality,ingest,streamed_f32_1280x720,streamed_bf16_1280x720,stream_copy",
+                    "quality,ingest,streamed_f32_1280x720,streamed_bf16_1280x720,plain_f32_80x60,"
+                    "plain_f32_320x240,stream_copy",
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
@@ -609,6 +645,12 @@ def main():
     if "plain_f32" in want:
         plain = run_plain("f32", args.steps * 4, args.warmup, args.pool)
         achieved = record("plain_f32", plain, 4, 4)
+    for name in ("80x60", "320x240"):
+        if f"plain_f32_{name}" in want:
+            try:
+                forms[f"plain_f32_{name}"] = run_plain_workload(name, args.steps * 2, args.warmup)
+            except Exception as exc:
+                forms[f"plain_f32_{name}"] = {"error": repr(exc)[:300]}
     for storage in ("f32", "bf16"):
         for curv, suffix in ((None, ""), (0, "_curv0"), (1, "_curv1")):
             name = f"streamed_{storage}_1280x720{suffix}"
