@@ -282,7 +282,10 @@ PROS_API pros_status pros_sync(pros_handle* h);
  * every reorth_every frames. */
 PROS_API pros_status pros_reorthonormalize(pros_handle* h);
 
-/* Launch configuration chosen for the handle (for diagnostics). */
+/* Launch configuration chosen for the handle (for diagnostics).  A
+ * streamed handle reports sync_mode -1, rows_per_thread 0 and the workgroups
+ * of one pass (256 threads, one pixel each, or a pixel pair each in bfloat16
+ * storage with even P and a 4-byte aligned frame). */
 typedef struct pros_launch_info {
   int32_t workgroups;        /* persistent workgroups of the frame kernel */
   int32_t threads;           /* threads per workgroup */

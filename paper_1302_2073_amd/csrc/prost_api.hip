@@ -735,13 +735,15 @@ pros_status pros_get_stats(pros_handle* h, pros_stats* out) {
 pros_status pros_get_launch_info(pros_handle* h, pros_launch_info* out) {
   if (!h || !out) return fail(PROS_EINVAL, "NULL argument");
   if (h->streamed) {   // one launch per pass: no register tile, no gang exchange
-    out->workgroups = h->stream_blocks;
+    // bfloat16 with even P takes pixel pairs (for 4-byte aligned frames)
+    const bool pairs = h->prm.storage == PROS_BF16 && h->P % 2 == 0 && h->ldU % 2 == 0;
     out->threads = 256;
+    out->pixels_per_wg = pairs ? 512 : 256;
+    out->workgroups = (h->P + out->pixels_per_wg - 1) / out->pixels_per_wg;
     out->rows_per_thread = 0;
-    out->pixels_per_wg = 256;
     out->barriers_per_frame = 0;
     out->sync_mode = -1;
-    out->curvature = 0;
+    out->curvature = h->curv;
     return PROS_OK;
   }
   out->workgroups = h->G;
