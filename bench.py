@@ -57,11 +57,19 @@ def streamed_bytes(m, k, P, bu, bx, J=5, curvature=0):
 
 
 def kernel_source_hash():
+    """Hash of the HIP sources with comments and blank lines removed, so that
+    a profile stays attached to the code it measured when only comments
+    change."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1302_2073_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+            text = open(os.path.join(csrc, f), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+            h.update(f.encode() + b"\0" + code.encode())
     return h.hexdigest()[:16]
 
 

@@ -1,11 +1,13 @@
 // Persistent per-frame kernel of pROST (Sec. 3.3, Steps 1-3, plus the 3x3
 // median of Sec. 3.4) for one video stream.
 //
-// One launch processes one frame.  The m x k subspace U is split into
-// workgroup tiles of `tpw` pixels (all colour entries of a pixel stay in one
-// tile); each thread keeps NR rows of U in registers for the whole frame (K
-// floats per row, or K bfloat16 pairs per two rows with bfloat16 storage), so
-// U is read from HBM once and written once per frame.
+// One launch processes one frame (or, in the sequence form, several frames
+// with the tile kept in registers between them and U stored after the last
+// one).  The m x k subspace U is split into workgroup tiles of `tpw` pixels
+// (all colour entries of a pixel stay in one tile); each thread keeps NR rows
+// of U in registers for the whole frame (K floats per row, or K bfloat16
+// pairs per two rows with bfloat16 storage), so U is read from HBM once and
+// written once per frame (per launch in the sequence form).
 // The frame's sequence of dependent reductions runs as gang-wide reductions
 // between all workgroups of the launch (cooperative launch, so all of them
 // are resident):
@@ -16,7 +18,9 @@
 // (or in median_kernel when the mask is asked for first), which saves the
 // exchange that would otherwise separate the label writes from the median.
 // Every workgroup reduces the published partials in the same fixed order, so
-// all of them hold bit-identical k-vectors without a broadcast step.
+// all of them hold bit-identical k-vectors without a broadcast step.  Waiting
+// workgroups spin on epoch-tagged float64 slots (each thread on its own
+// values, no barrier inside the wait, bounded by a wall-clock time-out).
 #pragma once
 
 #include <utility>
