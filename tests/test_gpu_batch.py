@@ -513,3 +513,19 @@ def test_per_call_frames_with_changing_alignment():
                 assert int(np.sum((l1 != exp.labels) & ~band)) == 0
                 nxt.append(O.State(U1, y1, l1, O.median3x3(l1, prm.height, prm.width), n1))
             starts = nxt
+
+
+def test_batch_refuses_streams_beyond_the_resident_tiles():
+    """A stream whose gang of register tiles cannot be resident (1280x720x3
+    at k = 15, which a single tracker runs in its streamed form) is refused
+    by pros_batch_init with PROS_EUNSUPPORTED, and per-call frames with a NULL
+    pointer are refused with PROS_EINVAL, before any launch."""
+    from paper_1302_2073_amd import _lib as L
+    from paper_1302_2073_amd.tracker import BatchTracker
+    with pytest.raises(L.ProstError) as ei:
+        BatchTracker([dict(width=1280, height=720, channels=3, k=15, mu=1e-3)], storage="f32")
+    assert ei.value.status == L.PROS_EUNSUPPORTED
+    import ctypes as C
+    with BatchTracker([dict(width=80, height=60, channels=1, k=5, mu=1e-3)], storage="f32") as bt:
+        ptrs = (C.c_void_p * 1)()
+        assert L.lib().pros_batch_track_frames(bt._b, ptrs) == L.PROS_EINVAL
