@@ -400,6 +400,59 @@ def run_batched_mixed(nstreams, steps, warmup, pool, per_launch=1):
                 steps_per_launch=per_launch, steps_per_launch_ms_per_step=spl_times)
 
 
+def run_batched_mixed_grouped(nstreams, steps, warmup, pool, groups=((5,), (10,), (15,)), per_launch=32):
+    """The mixed workload as one batch per group of subspace dimensions (one
+    launch each per step, back to back on one stream): a batch's kernel is
+    compiled for the largest k of its streams, so a k = 5 stream in a
+    k = 15 batch holds as many workgroups as a k = 15 stream of its size,
+    while in a batch of its own its tile holds twice the rows."""
+    import torch
+    from paper_1302_2073_amd.tracker import BatchTracker, bf16_bits
+    from synth import video as V
+    wls = V.mixed_streams(nstreams)
+    mk = sum(w.video.m * w.k for w in wls)
+    alg = sum(alg_bytes(w.video.m, w.k, w.video.width * w.video.height, 2, 2) for w in wls)
+    bts, cfgs = [], []
+    for ks in groups:
+        idx = [s for s, w in enumerate(wls) if w.k in ks]
+        if not idx:
+            continue
+        specs = [dict(width=wls[s].video.width, height=wls[s].video.height, channels=3, k=wls[s].k, mu=wls[s].mu)
+                 for s in idx]
+        bt = BatchTracker(specs, storage="bf16")
+        frames = []
+        for i, s in enumerate(idx):
+            bt.set_state(i, V.initial_subspace(wls[s].video.m, wls[s].k, 4, s))
+            sv = V.SyntheticVideo(wls[s].video)
+            frames.append([torch.from_numpy(bf16_bits(sv.frame(n)).view(np.int16)).cuda().view(torch.bfloat16)
+                           for n in range(pool)])
+        bt.set_frames(frames)
+        bt.tune(steps=3)
+        bt.use_graph(True)
+        bts.append(bt)
+        cfgs.append(dict(k=list(ks), streams=len(idx), **bt.config()))
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        for bt in bts:
+            bt.steps(per_launch)
+    torch.cuda.synchronize()
+    calls = max(steps // per_launch, 2)
+
+    def run(i):
+        for bt in bts:
+            bt.steps(per_launch)
+    ms, lo, hi = timed_median(run, calls, stream)
+    bad = [bt.sync() for bt in bts]
+    for bt in bts:
+        bt.close()
+    if any(bad):
+        raise RuntimeError(f"batch error {bad}")
+    per = ms / (calls * per_launch)
+    return dict(ms_per_step=per, fps=nstreams / (per * 1e-3),
+                vga_k15_equiv_fps=(mk / (WIDTH * HEIGHT * CH * K)) / (per * 1e-3), alg_bytes_per_step=alg,
+                groups=cfgs, steps_per_launch=per_launch, spread_ms=[round(lo, 3), round(hi, 3)])
+
+
 def run_lpcost(steps, warmup):
     """Differentiation form: forward + backward of the weighted smoothed cost
     over B = 32 frames of m = 230400 entries, k = 10 (float32)."""
@@ -612,7 +665,7 @@ def main():
                     help="only time the float64 oracle on every workload (1 and all host threads)")
     # also available: plain_f32_curv1, plain_f32_ordinary, batched_bf16_ordinary
     ap.add_argument("--forms", default="plain_f32,plain_f32_seq,plain_bf16,plain_bf16_seq,plain_f32_host,"
-                    "batched_bf16,batched_bf16_seq,batched_mixed_bf16,batched_mixed_bf16_seq,lpcost,"
+                    "batched_bf16,batched_bf16_seq,batched_mixed_bf16,batched_mixed_bf16_seq,batched_mixed_bf16_by_k,lpcost,"
                     "quality,ingest,streamed_f32_1280x720,streamed_bf16_1280x720,plain_f32_80x60,"
                     "plain_f32_320x240,stream_copy",
                     help="comma list of forms to time (the headline is batched_bf16)")
@@ -746,6 +799,20 @@ def main():
                 "streams": 64, "config": mixed["config"], "spread_ms": mixed["spread_ms"]}
         except Exception as exc:   # a side form must not cost the headline line
             forms["batched_mixed_bf16"] = {"error": repr(exc)[:300]}
+    for name, groups in (("batched_mixed_bf16_by_k", ((5,), (10,), (15,))),
+                         ("batched_mixed_bf16_k5_rest", ((5,), (10, 15)))):
+        if name in want:
+            try:
+                mg = run_batched_mixed_grouped(64, max(args.steps // 4, 64), args.warmup, args.pool, groups)
+                per = mg["ms_per_step"]
+                forms[name] = {
+                    "stream_fps": round(mg["fps"], 1), "vga_k15_equiv_fps": round(mg["vga_k15_equiv_fps"], 1),
+                    "ms_per_step": round(per, 5), "alg_GBps": round(mg["alg_bytes_per_step"] / (per * 1e-3) / 1e9, 1),
+                    "streams": 64, "groups": mg["groups"], "steps_per_launch": mg["steps_per_launch"],
+                    "spread_ms": mg["spread_ms"],
+                    "note": "one batch per group of subspace dimensions, launched back to back each step"}
+            except Exception as exc:
+                forms[name] = {"error": repr(exc)[:300]}
     if "batched_mixed_bf16_seq" in want:
         try:
             mixed = run_batched_mixed(64, max(args.steps // 4, 16), args.warmup, args.pool, per_launch=0)
