@@ -980,6 +980,16 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
   float r[NR], wt[NR], cw[NR];
   int eix[NR];
   bool u_pending = false;   // sequence: the registers hold an update not yet stored
+  auto store_tile = [&]() {  // sequence: the register tile to the U planes
+    float* __restrict__ Uw = (float*)a.U;
+#pragma unroll
+    for (int s = 0; s < NR; ++s)
+      if (eix[s] >= 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+          if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = u[s][j];
+      }
+  };
   const bool pre = EXT && a.pre_mean != nullptr;   // compiled out without EXT
   const bool pupd = EXT && ks.pre_upd != 0;
   const float pinv_n = ks.pre_inv_n, pinv_s = ks.pre_inv_s;
@@ -1115,7 +1125,9 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     float* __restrict__ Uw = (float*)a.U;
     const float cm1 = ks.scal[0], sz = ks.scal[1], nu_f = ks.scal[2];
     const bool upd = ks.flag[2] != 0;
-    // a sequence keeps U in the registers: it is stored after its last frame only
+    // a sequence keeps U in the registers (the next frame starts from them)
+    // and stores it after its last frame only, in a loop of its own, so the
+    // update of the other frames carries no per-entry store decisions
     const bool store_u = !SEQ || fi + 1 >= a.nseq;
     if (SEQ && upd) u_pending = !store_u;
 #pragma unroll
@@ -1134,8 +1146,8 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             const float nv = fmaf(coef, ks.vf[j], u[s][j]);   // columns >= k stay 0 (v_j = 0)
-            if (j < a.k && store_u) Uw[(long long)j * a.ldU + eix[s]] = nv;
-            if constexpr (SEQ) u[s][j] = nv;   // the next frame of a sequence starts from it
+            if constexpr (SEQ) u[s][j] = nv;
+            else if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = nv;
           }
           if (a.labels_after_update) rl = fmaf(-coef, nu_f, rl);
         }
@@ -1144,6 +1156,7 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
         s_flag[q] = (fabsf(rl) >= a.delta) ? 1 : 0;
       }
     }
+    if (SEQ && upd && store_u) store_tile();
     trace_point(a, tile, 61);
     write_labels<SEQ>(a, s_flag, ctx.p0, ctx.npx);
     trace_point(a, tile, 62);
@@ -1167,18 +1180,8 @@ __device__ __forceinline__ bool frame_tile(const FrameArgs& a, const int tile, F
     r[s] = acc;
   }
   }
-  if constexpr (SEQ) {   // the last frame stored nothing (rejected, or no step): store the updated tile
-    if (u_pending) {
-      float* __restrict__ Uw = (float*)a.U;
-#pragma unroll
-      for (int s = 0; s < NR; ++s)
-        if (eix[s] >= 0) {
-#pragma unroll
-          for (int j = 0; j < K; ++j)
-            if (j < a.k) Uw[(long long)j * a.ldU + eix[s]] = u[s][j];
-        }
-    }
-  }
+  // the last frame stored nothing (rejected, or no step): store the updated tile
+  if (SEQ && u_pending) store_tile();
   return true;
 }
 
@@ -1352,6 +1355,29 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
   };
   static_assert(!(SEQ && NL > 0), "sequences keep register tiles only");
   bool u_pending = false;   // sequence: the registers hold an update not yet stored
+  auto store_tile = [&]() {  // sequence: the register tile to the U planes
+    uint16_t* __restrict__ Uw = (uint16_t*)a.U;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int q0 = 2 * (tid + s * kBlock);
+      if (q0 >= ctx.nq) continue;
+      const bool has1 = (vbits >> (2 * s + 1)) & 1u;
+      const int c = q0 / ctx.npx;
+      const int e = c * a.P + ctx.p0 + (q0 - c * ctx.npx);
+      const int e1 = ((sbits >> s) & 1u) ? e + 1 + (a.P - ctx.npx) : e + 1;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (j < a.k) {
+          uint16_t* col = Uw + (long long)j * a.ldU;
+          if (al) {
+            st_u32(col, 2u * (unsigned)e, u[s][j]);
+          } else {
+            st_u16(col, 2u * (unsigned)e, (uint16_t)(u[s][j] & 0xFFFFu));
+            if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(u[s][j] >> 16));
+          }
+        }
+    }
+  };
 
   for (int fi = 0;;) {   // frames of this launch; U stays in the registers between them
   if constexpr (SEQ) tid = thread_index();   // re-enters opaquely each frame (see the float32 tile)
@@ -1514,7 +1540,9 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
     uint16_t* __restrict__ Uw = (uint16_t*)a.U;
     const float cm1 = ks.scal[0], sz = ks.scal[1], nu_f = ks.scal[2];
     const bool upd = ks.flag[2] != 0;
-    // a sequence keeps U in the registers: it is stored after its last frame only
+    // a sequence keeps U in the registers (the next frame starts from them)
+    // and stores it after its last frame only, in a loop of its own, so the
+    // update of the other frames carries no per-entry store decisions
     const bool store_u = !SEQ || fi + 1 >= a.nseq;
     if (SEQ && upd) u_pending = !store_u;
     pin_tile(u);
@@ -1540,21 +1568,21 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
         const float coef0 = fmaf(cm1, uv0, -sz * (cw[2 * s] - ua0));
         const float coef1 = fmaf(cm1, uv1, -sz * (cw[2 * s + 1] - ua1));
 #pragma unroll
-        for (int j = 0; j < K; ++j)
-          if (SEQ || j < a.k) {   // columns >= k stay 0 (v_j = 0)
+        for (int j = 0; j < K; ++j) {
+          if constexpr (SEQ) {   // columns >= k stay 0 (v_j = 0)
+            u[s][j] = pack_bf16_rne(fmaf(coef0, ks.vf[j], bf_lo(u[s][j])), fmaf(coef1, ks.vf[j], bf_hi(u[s][j])));
+          } else if (j < a.k) {
             const uint32_t nw = pack_bf16_rne(fmaf(coef0, ks.vf[j], bf_lo(u[s][j])),
                                               fmaf(coef1, ks.vf[j], bf_hi(u[s][j])));
-            if (j < a.k && store_u) {
-              uint16_t* col = Uw + (long long)j * a.ldU;
-              if (al) {
-                st_u32(col, 2u * (unsigned)e, nw);
-              } else {
-                st_u16(col, 2u * (unsigned)e, (uint16_t)(nw & 0xFFFFu));
-                if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(nw >> 16));
-              }
+            uint16_t* col = Uw + (long long)j * a.ldU;
+            if (al) {
+              st_u32(col, 2u * (unsigned)e, nw);
+            } else {
+              st_u16(col, 2u * (unsigned)e, (uint16_t)(nw & 0xFFFFu));
+              if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(nw >> 16));
             }
-            if constexpr (SEQ) u[s][j] = nw;   // the next frame of a sequence starts from it
           }
+        }
         if (a.labels_after_update) {
           rl0 = fmaf(-coef0, nu_f, rl0);
           rl1 = fmaf(-coef1, nu_f, rl1);
@@ -1571,6 +1599,7 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
       s_flag[q0] = (fabsf(rl0) >= a.delta) ? 1 : 0;
       if (has1) s_flag[q0 + 1] = (fabsf(rl1) >= a.delta) ? 1 : 0;
     }
+    if (SEQ && upd && store_u) store_tile();
 #pragma unroll 1
     for (int s = NP; s < NT; ++s) {   // LDS pairs (no optional features)
       const int q0 = 2 * (tid + s * kBlock);
@@ -1663,31 +1692,8 @@ __device__ __forceinline__ bool frame_tile_packed(const FrameArgs& a, const int 
     r[2 * s + 1] = has1 ? acc1 : 0.f;
   }
   }
-  if constexpr (SEQ) {   // the last frame stored nothing (rejected, or no step): store the updated tile
-    if (u_pending) {
-      uint16_t* __restrict__ Uw = (uint16_t*)a.U;
-#pragma unroll
-      for (int s = 0; s < NP; ++s) {
-        const int q0 = 2 * (tid + s * kBlock);
-        if (q0 >= ctx.nq) continue;
-        const bool has1 = (vbits >> (2 * s + 1)) & 1u;
-        const int c = q0 / ctx.npx;
-        const int e = c * a.P + ctx.p0 + (q0 - c * ctx.npx);
-        const int e1 = ((sbits >> s) & 1u) ? e + 1 + (a.P - ctx.npx) : e + 1;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-          if (j < a.k) {
-            uint16_t* col = Uw + (long long)j * a.ldU;
-            if (al) {
-              st_u32(col, 2u * (unsigned)e, u[s][j]);
-            } else {
-              st_u16(col, 2u * (unsigned)e, (uint16_t)(u[s][j] & 0xFFFFu));
-              if (has1) st_u16(col, 2u * (unsigned)e1, (uint16_t)(u[s][j] >> 16));
-            }
-          }
-      }
-    }
-  }
+  // the last frame stored nothing (rejected, or no step): store the updated tile
+  if (SEQ && u_pending) store_tile();
   return true;
 }
 
