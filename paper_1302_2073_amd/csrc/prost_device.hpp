@@ -121,35 +121,84 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 // Reduce-scatter of L values across the 64 lanes of a wavefront: at each of
 // log2(P) stages (P = L rounded up to a power of two) a lane keeps one half of
-// its values and adds the partner's copy of that half, so the work halves
-// every stage (P - 1 exchanges instead of 6 L).  On return lane l holds the
-// wavefront total of component `comp`; lanes whose low 6 - log2(P) bits are
-// zero hold each component exactly once.  Fixed order, deterministic.
-template <int L, typename T>
-__device__ __forceinline__ T wave_reduce_scatter(T (&a)[L], int& comp) {
+// its values and adds its partner's copy of that half, so the work halves
+// every stage (P - 1 exchanges instead of 6 L); the lane bits left over are
+// then summed over (all-reduce).  The exchanges stay in the vector unit:
+// partners across lane bit 5 or 4 trade both halves in one
+// v_permlane32_swap / v_permlane16_swap, partners across bits 3, 0 and 1 are
+// reached with DPP (row_ror:8, quad_perm), and the last all-reduce bit, 2,
+// with row_ror:12 (lane l reads lane l - 12 mod 16 of its row), which gives
+// the partner l + 4 to the lanes with bit 2 clear: those lanes own the
+// results.  Stage order: bits 5, 4, 3, 0, 1, then
+// 2.  On return every owner lane (wave_rs_owner) holds the wavefront total of
+// component `comp`, each component in exactly one owner.  Fixed order,
+// deterministic.
+constexpr int kRsOrder[6] = {5, 4, 3, 0, 1, 2};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), CTRL, 0xf, 0xf, false));
+}
+
+// One reduce-scatter stage across lane bit b for the value pair (lo, hi):
+// lanes with the bit clear end with lo + partner's lo, the others with
+// hi + partner's hi.
+__device__ __forceinline__ float rs_stage(int b, float lo, float hi, int lane) {
+  if (b == 5 || b == 4) {
+    const auto r = (b == 5) ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                            : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool up = (lane >> b) & 1;
+  const float send = up ? lo : hi, keep = up ? hi : lo;
+  return keep + (b == 3 ? dpp_mov<0x128>(send) : b == 0 ? dpp_mov<0xB1>(send) : dpp_mov<0x4E>(send));
+}
+
+// One all-reduce stage across lane bit b (bit 2: right in the lanes with bit
+// 2 clear only).
+__device__ __forceinline__ float ar_stage(int b, float v) {
+  if (b == 5 || b == 4) {
+    const auto r = (b == 5) ? __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false)
+                            : __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  return v + (b == 3 ? dpp_mov<0x128>(v) : b == 0 ? dpp_mov<0xB1>(v) : b == 1 ? dpp_mov<0x4E>(v) : dpp_mov<0x12C>(v));
+}
+
+template <int L>
+__device__ __forceinline__ float wave_reduce_scatter(float (&a)[L], int& comp) {
   constexpr int P = pow2_at_least(L);
   constexpr int S = ilog2(P);
+  static_assert(S <= 5, "at most 32 components");
   const int lane = thread_index() & 63;
   int base = 0;
 #pragma unroll
   for (int st = 0; st < S; ++st) {
     const int half = P >> (st + 1);
-    const int o = 32 >> st;
-    const bool up = (lane & o) != 0;
+    const int b = kRsOrder[st];
 #pragma unroll
     for (int i = 0; i < half; ++i) {      // in place; entries >= L are zero
-      const T lo = a[i];
-      const T hi = (i + half < L) ? a[(i + half < L) ? i + half : 0] : T(0);
-      const T send = up ? lo : hi;
-      const T keep = up ? hi : lo;
-      a[i] = keep + __shfl_xor(send, o, 64);
+      const float lo = a[i];
+      const float hi = (i + half < L) ? a[(i + half < L) ? i + half : 0] : 0.f;
+      a[i] = rs_stage(b, lo, hi, lane);
     }
-    if (up) base += half;
+    if ((lane >> b) & 1) base += half;
   }
 #pragma unroll
-  for (int o = 32 >> S; o > 0; o >>= 1) a[0] += __shfl_xor(a[0], o, 64);
+  for (int st = S; st < 6; ++st) a[0] = ar_stage(kRsOrder[st], a[0]);
   comp = base;
   return a[0];
+}
+
+// The lanes that hold each component of wave_reduce_scatter<L> once: those
+// whose all-reduced bits are clear.
+template <int L>
+__device__ __forceinline__ bool wave_rs_owner(int lane) {
+  constexpr int S = ilog2(pow2_at_least(L));
+  int mask = 0;
+#pragma unroll
+  for (int st = S; st < 6; ++st) mask |= 1 << kRsOrder[st];
+  return (lane & mask) == 0;
 }
 
 __device__ __forceinline__ long long now_ticks() { return wall_clock64(); }

@@ -372,8 +372,7 @@ __device__ __forceinline__ void wg_reduce(float (&acc)[L], double (*s_red)[kSlot
   const int wv = thread_index() >> 6;
   int comp;
   const float v = wave_reduce_scatter<L>(acc, comp);
-  constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
-  if ((lane & kLowMask) == 0 && comp < L) s_red[wv][comp] = (double)v;
+  if (wave_rs_owner<L>(lane) && comp < L) s_red[wv][comp] = (double)v;
   __syncthreads();
   if (thread_index() < L) {
     double v = 0.0;
@@ -390,12 +389,11 @@ __device__ __forceinline__ bool gang_reduce_counter(float (&acc)[L], const Frame
                                                     double* s_out, int* s_ctl) {
   const int lane = thread_index() & 63;
   const int wv = thread_index() >> 6;
-  constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
   // 1. per wave
   {
     int comp;
     const float v = wave_reduce_scatter<L>(acc, comp);
-    if ((lane & kLowMask) == 0 && comp < L) s_red[wv][comp] = (double)v;
+    if (wave_rs_owner<L>(lane) && comp < L) s_red[wv][comp] = (double)v;
   }
   __syncthreads();
   double* slot = a.part + ((size_t)(nbar & 1) * a.G + tile) * kSlot;

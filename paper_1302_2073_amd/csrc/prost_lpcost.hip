@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kLpBlock) void lpcost_fwd_kernel(const float* __res
     }
     int comp;
     const float v = wave_reduce_scatter<CH>(acc, comp);
-    if ((lane & 1) == 0) red[wv][comp] = (double)v;   // each component once per wavefront
+    if (wave_rs_owner<CH>(lane)) red[wv][comp] = (double)v;   // each component once per wavefront
     __syncthreads();
     if (tid < nb) {
       double sum = 0.0;

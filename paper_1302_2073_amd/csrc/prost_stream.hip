@@ -55,8 +55,7 @@ __device__ __forceinline__ void st_block_partials(float (&acc)[L], double (*red)
   const int tid = thread_index(), lane = tid & 63, wv = tid >> 6;
   int comp;
   const float v = wave_reduce_scatter<L>(acc, comp);
-  constexpr int kLowMask = (64 / pow2_at_least(L)) - 1;
-  if ((lane & kLowMask) == 0 && comp < L) red[wv][comp] = (double)v;
+  if (wave_rs_owner<L>(lane) && comp < L) red[wv][comp] = (double)v;
   __syncthreads();
   if (tid < L) {
     double s = 0.0;
@@ -395,7 +394,7 @@ __global__ __launch_bounds__(kStBlock) void st_gradh(FrameArgs a, const StreamKS
     for (int q = 0; q < 32; ++q) ch[q] = (c0 + q < NV) ? acc[(c0 + q < NV) ? c0 + q : 0] : 0.f;
     int comp;
     const float v = wave_reduce_scatter<32>(ch, comp);
-    if ((lane & 1) == 0 && c0 + comp < NV) red[wv][c0 + comp] = (double)v;
+    if (wave_rs_owner<32>(lane) && c0 + comp < NV) red[wv][c0 + comp] = (double)v;
   }
   __syncthreads();
   for (int q = tid; q < NV; q += kStBlock) {
