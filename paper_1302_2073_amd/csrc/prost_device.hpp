@@ -97,23 +97,62 @@ __device__ __forceinline__ void cost_eval(float r, const CostParams& cp, float& 
 // ---------------------------------------------------------------------------
 // reductions (fixed order: identical results in every workgroup and run)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Cross-lane moves in the vector unit (gfx950): DPP row rotations (lane l of
+// a 16-lane row reads lane l - r mod 16 for row_ror:r) and quad permutations,
+// and the permlane swaps that trade the upper 32 (16 of each 32) lanes of one
+// register with the lower ones of another.  Every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), CTRL, 0xf, 0xf, false));
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)b, CTRL, 0xf, 0xf, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128, kRowRor12 = 0x12C;
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E;   // quad_perm [1,0,3,2], [2,3,0,1]
+
+// v of lane l plus v of lane l ^ 32 (W = 32) or l ^ 16 (W = 16), the same
+// sum in both lanes of a pair.
+template <int W>
+__device__ __forceinline__ float swap_sum(float v) {
+  const auto r = (W == 32) ? __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false)
+                           : __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int W>
+__device__ __forceinline__ double swap_sum(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const auto lo = (W == 32) ? __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false)
+                            : __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = (W == 32) ? __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false)
+                            : __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+  return x + y;
 }
 
-// Sum over the first 16 lanes (k-space vectors live in lanes 0..15); every
-// lane of each 16-lane row ends with its row's total.
-__device__ __forceinline__ double row16_sum(double v) {
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Sum over each 16-lane row, in every lane of the row: partners l ^ 8, then
+// l - 4 mod 16 (with the first step, the sum over l, l ^ 4, l ^ 8, l ^ 12),
+// then l ^ 2 and l ^ 1.  Each step adds the same two values in both lanes of
+// a pair, so every lane of the row holds the same total.
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+  v += dpp_mov<kRowRor8>(v);
+  v += dpp_mov<kRowRor4>(v);
+  v += dpp_mov<kQuadXor2>(v);
+  v += dpp_mov<kQuadXor1>(v);
   return v;
+}
+// Sum over the 64 lanes, in every lane.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v = swap_sum<32>(v);
+  v = swap_sum<16>(v);
+  return row16_sum(v);
 }
 
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : 32; }
@@ -135,11 +174,6 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 // deterministic.
 constexpr int kRsOrder[6] = {5, 4, 3, 0, 1, 2};
 
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(v), CTRL, 0xf, 0xf, false));
-}
-
 // One reduce-scatter stage across lane bit b for the value pair (lo, hi):
 // lanes with the bit clear end with lo + partner's lo, the others with
 // hi + partner's hi.
@@ -151,7 +185,7 @@ __device__ __forceinline__ float rs_stage(int b, float lo, float hi, int lane) {
   }
   const bool up = (lane >> b) & 1;
   const float send = up ? lo : hi, keep = up ? hi : lo;
-  return keep + (b == 3 ? dpp_mov<0x128>(send) : b == 0 ? dpp_mov<0xB1>(send) : dpp_mov<0x4E>(send));
+  return keep + (b == 3 ? dpp_mov<kRowRor8>(send) : b == 0 ? dpp_mov<kQuadXor1>(send) : dpp_mov<kQuadXor2>(send));
 }
 
 // One all-reduce stage across lane bit b (bit 2: right in the lanes with bit
@@ -162,7 +196,8 @@ __device__ __forceinline__ float ar_stage(int b, float v) {
                             : __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  return v + (b == 3 ? dpp_mov<0x128>(v) : b == 0 ? dpp_mov<0xB1>(v) : b == 1 ? dpp_mov<0x4E>(v) : dpp_mov<0x12C>(v));
+  return v + (b == 3 ? dpp_mov<kRowRor8>(v) : b == 0 ? dpp_mov<kQuadXor1>(v) : b == 1 ? dpp_mov<kQuadXor2>(v)
+                                                                     : dpp_mov<kRowRor12>(v));
 }
 
 template <int L>
