@@ -820,7 +820,8 @@ __device__ __forceinline__ float cg_advance(const FrameArgs& a, KSpace<kMaxK>& k
 
 // Step size and angle of the geodesic step and the trigonometric scalars of
 // the row pass: t = max(exp(-tau n) t_init, t_min) (Sec. 3.4),
-// theta = sigma t, cos(theta) - 1 = -2 sin^2(theta / 2), sin(theta) / zeta.
+// theta = sigma t, cos(theta) - 1 = -2 sin^2(theta / 2),
+// sin(theta) / zeta = 2 sin(theta / 2) cos(theta / 2) / zeta.
 // Out of line on purpose: inlined into the persistent kernels, the float64
 // polynomial constants of exp and sin were hoisted out of the tile loop and
 // held in registers (and spilled) for the whole launch.
@@ -832,9 +833,10 @@ __device__ __attribute__((noinline)) GeoScalars geodesic_scalars(double tau_n, d
   GeoScalars g;
   g.t = fmax(exp(-tau_n) * t_init, t_min);
   g.theta = sigma * g.t;
-  const double sh = sin(0.5 * g.theta);
+  double sh, ch;   // sin and cos of theta / 2 from one range reduction; sin(theta) = 2 sh ch
+  sincos(0.5 * g.theta, &sh, &ch);
   g.cm1 = -2.0 * sh * sh;
-  g.sz = zeta > 0.0 ? sin(g.theta) / zeta : 0.0;
+  g.sz = zeta > 0.0 ? 2.0 * sh * ch / zeta : 0.0;
   return g;
 }
 
