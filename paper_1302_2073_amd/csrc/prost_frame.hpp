@@ -475,20 +475,42 @@ __device__ __forceinline__ bool gang_reduce(float (&acc)[L], const FrameArgs& a,
 template <bool COH = false>
 __device__ __forceinline__ void median3x3_range(const uint8_t* __restrict__ lab, uint8_t* __restrict__ mask, int W,
                                                 int H, int p0, int npx) {
-  for (int pl = thread_index(); pl < npx; pl += blockDim.x) {
-    const int pix = p0 + pl;
-    const int row = pix / W, col = pix - row * W;
-    const int rows[3] = {max(row - 1, 0), row, min(row + 1, H - 1)};
-    const int cols[3] = {max(col - 1, 0), col, min(col + 1, W - 1)};
-    int cnt = 0;
+  // kMedBatch pixels per thread at a time: their 9 kMedBatch loads are all
+  // issued before the first is used (an entry past the tile loads the
+  // tile's last pixel again and is not stored), so a tile costs one memory
+  // latency per batch instead of one per pixel
+  constexpr int kMedBatch = 3;
+  for (int pl0 = thread_index(); pl0 < npx; pl0 += kMedBatch * blockDim.x) {
+    int rb[kMedBatch][3], cb[kMedBatch][3];   // clamped neighbour rows (times W) and columns
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int b = 0; b < kMedBatch; ++b) {
+      const int pix = p0 + min(pl0 + b * (int)blockDim.x, npx - 1);
+      const int row = pix / W, col = pix - row * W;
+      rb[b][0] = max(row - 1, 0) * W;
+      rb[b][1] = row * W;
+      rb[b][2] = min(row + 1, H - 1) * W;
+      cb[b][0] = max(col - 1, 0);
+      cb[b][1] = col;
+      cb[b][2] = min(col + 1, W - 1);
+    }
+    uint8_t v[kMedBatch][9];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const uint8_t* p = lab + rows[i] * W + cols[j];
-        cnt += COH ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
-      }
-    mask[pix] = (cnt >= 5) ? 1 : 0;
+    for (int b = 0; b < kMedBatch; ++b)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const uint8_t* p = lab + rb[b][i] + cb[b][j];
+          v[b][3 * i + j] = COH ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+        }
+#pragma unroll
+    for (int b = 0; b < kMedBatch; ++b) {
+      int cnt = 0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) cnt += v[b][t];
+      const int pl = pl0 + b * (int)blockDim.x;
+      if (pl < npx) mask[p0 + pl] = (cnt >= 5) ? 1 : 0;
+    }
   }
 }
 
