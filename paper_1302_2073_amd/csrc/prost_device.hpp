@@ -168,10 +168,9 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 // reached with DPP (row_ror:8, quad_perm), and the last all-reduce bit, 2,
 // with row_ror:12 (lane l reads lane l - 12 mod 16 of its row), which gives
 // the partner l + 4 to the lanes with bit 2 clear: those lanes own the
-// results.  Stage order: bits 5, 4, 3, 0, 1, then
-// 2.  On return every owner lane (wave_rs_owner) holds the wavefront total of
-// component `comp`, each component in exactly one owner.  Fixed order,
-// deterministic.
+// results.  Stage order: bits 5, 4, 3, 0, 1, then 2.  On return every owner
+// lane (wave_rs_owner) holds the wavefront total of component `comp`, each
+// component in exactly one owner.  Fixed order, deterministic.
 constexpr int kRsOrder[6] = {5, 4, 3, 0, 1, 2};
 
 // One reduce-scatter stage across lane bit b for the value pair (lo, hi):
