@@ -318,7 +318,7 @@ def time_batch_steps(bt, steps, warmup, per_launch, stream):
     return ms, lo, hi, per_launch, spl_times
 
 
-def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1, per_launch=1):
+def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1, per_launch=1, tile_scale=1.0):
     """nstreams independent 640x480x3 k=15 streams, each with its own seeded
     video, one persistent launch per batch step (hipGraph replay).
     per_launch > 1: launches of that many steps each (also replayed from a
@@ -349,6 +349,9 @@ def run_batched(storage, nstreams, steps, warmup, pool, tune=True, cooperative=1
     if not cooperative:
         bt.set_dispatch(0)
     tuned = bt.tune(steps=3) if tune else None
+    if not tune and tile_scale != 1.0:   # profiling runs: the tuned tile scale without the tuner's launches
+        cfg = {k: v for k, v in bt.config().items() if k not in ("workgroups", "rounds")}
+        bt.configure(**{**cfg, "tile_scale": tile_scale})
     bt.use_graph(True)
     stream = torch.cuda.current_stream()
     ms, lo, hi, per_launch, spl_times = time_batch_steps(bt, steps, warmup, per_launch, stream)
@@ -671,6 +674,8 @@ def main():
                     help="comma list of forms to time (the headline is batched_bf16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched form: keep the default launch configuration (profiling runs)")
+    ap.add_argument("--tile-scale", type=float, default=1.0,
+                    help="batched forms with --no-tune: tile scale of the launch configuration")
     ap.add_argument("--steps-per-launch", type=int, default=8,
                     help="headline form with --no-tune: batch steps per launch (tuned otherwise)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -765,14 +770,15 @@ def main():
         except Exception as exc:   # a side form must not cost the headline line
             forms["plain_f32_host"] = {"error": repr(exc)[:300]}
     if "batched_bf16" in want:
-        batched = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune)
+        batched = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune,
+                              tile_scale=args.tile_scale)
         achieved = record("batched_bf16", batched, 2, 2, args.streams)
         if plain:
             forms["batched_bf16"]["vs_plain_f32"] = round(batched["fps"] / plain["fps"], 3)
     bsq = None
     if "batched_bf16_seq" in want:
         bsq = run_batched("bf16", args.streams, args.steps, args.warmup, args.pool, tune=not args.no_tune,
-                          per_launch=0 if not args.no_tune else args.steps_per_launch)
+                          per_launch=0 if not args.no_tune else args.steps_per_launch, tile_scale=args.tile_scale)
         achieved = record("batched_bf16_seq", bsq, 2, 2, args.streams)
         if batched:
             forms["batched_bf16_seq"]["vs_one_step_per_launch"] = round(bsq["fps"] / batched["fps"], 3)
